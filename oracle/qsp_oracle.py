@@ -1,0 +1,499 @@
+"""Plain FP64 CPU oracle of the quasi-static PIC per-slice loop.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link this module: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` use it.  It shares no code with the HIP
+path; the only common dependency is the input description in ``workloads``.
+
+What it computes (HiPACE++, arXiv:2109.10277), in normalised units
+(c = eps0 = mu0 = 1, lengths in k_p^-1, densities in n0, fields in E0):
+
+* field equations, Sec. II eqs. (psi), (exmby), (ez), (bxby), (bz):
+    lap psi = -(rho - Jz);  Ex-By = -d_x psi;  Ey+Bx = -d_y psi
+    lap Ez  = d_x Jx + d_y Jy
+    lap Bx  = -d_y Jz + d_zeta Jy;  lap By = d_x Jz - d_zeta Jx
+    lap Bz  = d_y Jx - d_x Jy
+* the 2D slice routine, Sec. II (enumerated steps 1-7), head to tail;
+* the plasma pusher, Sec. III.B eqs. for d_zeta x_perp, d_zeta u_perp,
+  d_zeta Psi and the Lorentz factor gamma(u_perp, Psi), for electrons
+  (q = -1, M = m_e) with a fifth-order Adams-Bashforth step in zeta;
+* zeroth-order longitudinal, first-order (CIC) transverse deposition,
+  Sec. III.B ("current deposition");
+* Dirichlet fast Poisson solves by a type-I discrete sine transform plus
+  finite-difference operators, Sec. III.B ("solving a transverse Poisson
+  equation");
+* the Bx/By predictor-corrector, Sec. III.B ("predictor-corrector field
+  solver"), with the initial guess built from Bx/By of the two previous
+  slices (Sec. V.B, the list of per-cell quantities S_cell).
+
+Where the paper is silent, this file takes the readings listed beside each
+function (node-centred grid, centred differences, linear-extrapolation
+initial guess, relative-L2 P-C criterion, 1+Psi floor, absorbing box edge).
+
+Every step is a plain array expression or a library primitive
+(``numpy.bincount`` for scatter-add, ``scipy.fft.dstn`` for the sine
+transform).  Array layout: node fields are float64 arrays of shape
+(ny+1, nx+1) indexed [j, i] (row = y).  Boundary rows/columns are zero.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Optional, Sequence
+
+import numpy as np
+import scipy.fft
+
+# fifth-order Adams-Bashforth weights for f_k, f_{k-1}, ..., f_{k-4}
+# (standard textbook values, denominator 720)
+AB5 = np.array([1901.0, -2774.0, 2616.0, -1274.0, 251.0]) / 720.0
+
+FIELDS = ("psi", "exmby", "eypbx", "ez", "bx", "by", "bz")
+DEPOSITS = ("rho_mjz", "jx", "jy", "jz", "rho")
+
+
+# --------------------------------------------------------------------------
+# Grid helpers
+# --------------------------------------------------------------------------
+
+def node_coords(cfg):
+    x = cfg.x_lo + cfg.hx * np.arange(cfg.nx + 1)
+    y = cfg.y_lo + cfg.hy * np.arange(cfg.ny + 1)
+    return x, y
+
+
+def zero_boundary(f: np.ndarray) -> np.ndarray:
+    """Homogeneous Dirichlet nodes (index 0 and n on each axis) are zero."""
+    f[0, :] = 0.0
+    f[-1, :] = 0.0
+    f[:, 0] = 0.0
+    f[:, -1] = 0.0
+    return f
+
+
+# --------------------------------------------------------------------------
+# Plasma particles
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Plasma:
+    """One slice of plasma electrons plus the Adams-Bashforth history.
+
+    ``w`` is the macro-particle weight n0*hx*hy/(ppc_x*ppc_y) (charge per
+    unit zeta is q*w); w = 0 marks an absorbed particle.  ``hist[m]`` holds
+    the right-hand side f_{k-1-m} (m = 0..3) of the five integrated
+    quantities (x, y, ux, uy, Psi).
+    """
+    x: np.ndarray
+    y: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    psi: np.ndarray
+    w: np.ndarray
+    hist: np.ndarray          # [4, 5, N]
+
+    def copy(self) -> "Plasma":
+        return Plasma(*(np.array(getattr(self, f.name), copy=True)
+                        for f in dataclasses.fields(Plasma)))
+
+
+def init_plasma(cfg) -> Plasma:
+    """Unperturbed plasma ahead of the box (Sec. II: "a slice of unperturbed
+    plasma is initialized ahead of the beams"): electrons at rest on a
+    uniform lattice, Psi = 0 and zero history (exact for a plasma that has
+    not yet met any field)."""
+    nX, nY = cfg.nx * cfg.ppc_x, cfg.ny * cfg.ppc_y
+    I, J = np.meshgrid(np.arange(nX), np.arange(nY))
+    x = cfg.x_lo + (I.ravel() + 0.5) * cfg.hx / cfg.ppc_x
+    y = cfg.y_lo + (J.ravel() + 0.5) * cfg.hy / cfg.ppc_y
+    n = x.size
+    w = np.full(n, cfg.n0 * cfg.hx * cfg.hy / (cfg.ppc_x * cfg.ppc_y))
+    z = np.zeros(n)
+    return Plasma(x=x, y=y, ux=z.copy(), uy=z.copy(), psi=z.copy(), w=w,
+                  hist=np.zeros((4, 5, n)))
+
+
+def cic_weights(cfg, x, y):
+    """Linear (CIC) shape: the particle in cell (i, j) with fractional
+    offsets (fx, fy) gives weights (1-fx)(1-fy), fx(1-fy), (1-fx)fy, fx*fy
+    to nodes (i,j), (i+1,j), (i,j+1), (i+1,j+1)."""
+    sx = (x - cfg.x_lo) / cfg.hx
+    sy = (y - cfg.y_lo) / cfg.hy
+    i = np.clip(np.floor(sx).astype(np.int64), 0, cfg.nx - 1)
+    j = np.clip(np.floor(sy).astype(np.int64), 0, cfg.ny - 1)
+    fx = sx - i
+    fy = sy - j
+    nodes = [(i, j), (i + 1, j), (i, j + 1), (i + 1, j + 1)]
+    wts = [(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy]
+    return nodes, wts
+
+
+def deposit_values(cfg, x, y, values: np.ndarray) -> np.ndarray:
+    """Scatter-add per-particle density ``values`` to the nodes with the CIC
+    shape (zeroth order in zeta); deposits on boundary nodes are dropped."""
+    out = np.zeros((cfg.ny + 1) * (cfg.nx + 1))
+    nodes, wts = cic_weights(cfg, x, y)
+    for (i, j), s in zip(nodes, wts):
+        out += np.bincount(j * (cfg.nx + 1) + i, weights=values * s,
+                           minlength=out.size)
+    return zero_boundary(out.reshape(cfg.ny + 1, cfg.nx + 1))
+
+
+def gather(cfg, field: np.ndarray, x, y) -> np.ndarray:
+    """Interpolate a node field to the particles with the same CIC shape
+    (the transpose of ``deposit_values`` up to the 1/(hx hy) density
+    normalisation)."""
+    nodes, wts = cic_weights(cfg, x, y)
+    return sum(field[j, i] * s for (i, j), s in zip(nodes, wts))
+
+
+def clamp_d(cfg, psi):
+    """D = 1 + Psi, floored at cfg.psi_floor (the paper's equations are
+    singular at 1 + Psi = 0 and it does not say how that is handled)."""
+    return np.maximum(1.0 + psi, cfg.psi_floor)
+
+
+def gamma_of(ux, uy, d):
+    """Lorentz factor from the transverse momentum and 1 + Psi, Sec. III.B
+    eq. for gamma_p."""
+    return (1.0 + ux * ux + uy * uy + d * d) / (2.0 * d)
+
+
+def plasma_deposit(cfg, p: Plasma, channels: Sequence[str] = DEPOSITS):
+    """Charge and current densities of the plasma electrons (q = -1).
+
+    A macro-particle crossing the slice contributes q*w*S/(hx hy) times
+    1/(1 - v_z) = gamma/(1 + Psi) to rho, and rho*v to J.  Hence
+    rho - Jz = q*w*S/(hx hy) exactly (the quasi-static invariant
+    gamma - u_z = 1 + Psi), which is deposited on its own channel so the
+    psi source never forms the difference of two large numbers.
+    """
+    d = clamp_d(cfg, p.psi)
+    g = gamma_of(p.ux, p.uy, d)
+    uz = g - d
+    qn = -p.w / (cfg.hx * cfg.hy)          # q * w / cell area
+    per = {"rho_mjz": qn,
+           "jx": qn * p.ux / d,
+           "jy": qn * p.uy / d,
+           "jz": qn * uz / d,
+           "rho": qn * g / d}
+    return {c: deposit_values(cfg, p.x, p.y, per[c]) for c in channels}
+
+
+def add_ion_background(cfg, dep: dict) -> dict:
+    """Immobile ions of density n0: +n0 to rho (and rho - Jz) everywhere
+    inside the box (Sec. II: the ions remain practically immobile)."""
+    ion = zero_boundary(np.full((cfg.ny + 1, cfg.nx + 1), cfg.n0))
+    for c in ("rho_mjz", "rho"):
+        if c in dep:
+            dep[c] = dep[c] + ion
+    return dep
+
+
+def particle_rhs(cfg, p: Plasma, flds: dict):
+    """d/dzeta of (x, y, ux, uy, Psi) for electrons (q = -1, M = m_e, so
+    -q/M = +1 and -q m_e/(M e) = +1), Sec. III.B pusher equations:
+
+      dx/dzeta   = -ux / D
+      dux/dzeta  = gamma/D (Ex-By) + By + Bz uy / D
+      duy/dzeta  = gamma/D (Ey+Bx) - Bx - Bz ux / D
+      dPsi/dzeta = (ux (Ex-By) + uy (Ey+Bx)) / D - Ez
+
+    with D = 1 + Psi (floored) and the six fields gathered at the particle.
+    Returns (f [5, N], number of particles whose D was floored).
+    """
+    g = {k: gather(cfg, flds[k], p.x, p.y)
+         for k in ("exmby", "eypbx", "ez", "bx", "by", "bz")}
+    raw = 1.0 + p.psi
+    d = np.maximum(raw, cfg.psi_floor)
+    gam = gamma_of(p.ux, p.uy, d)
+    f = np.empty((5, p.x.size))
+    f[0] = -p.ux / d
+    f[1] = -p.uy / d
+    f[2] = gam / d * g["exmby"] + g["by"] + g["bz"] * p.uy / d
+    f[3] = gam / d * g["eypbx"] - g["bx"] - g["bz"] * p.ux / d
+    f[4] = (p.ux * g["exmby"] + p.uy * g["eypbx"]) / d - g["ez"]
+    alive = p.w > 0
+    f[:, ~alive] = 0.0
+    nclamp = int(np.count_nonzero(alive & (raw < cfg.psi_floor)))
+    return f, nclamp
+
+
+def ab5_push(cfg, p: Plasma, flds: dict, commit: bool):
+    """Advance the slice from zeta_k to zeta_{k+1} = zeta_k - dzeta with the
+    fifth-order Adams-Bashforth formula (Sec. III.B; history zero before
+    the first slice):
+
+      y_{k+1} = y_k - dzeta * sum_m AB5[m] f_{k-m}
+
+    A particle that ends outside the box is absorbed: its weight becomes 0
+    and its state keeps the last in-box values.  With ``commit`` the new
+    f_k is pushed onto the history (the real push); without it (the
+    predictor-corrector trial push) the history is left alone.
+    Returns (new plasma, clamp count, newly absorbed count).
+    """
+    f, nclamp = particle_rhs(cfg, p, flds)
+    incr = AB5[0] * f
+    for m in range(4):
+        incr = incr + AB5[m + 1] * p.hist[m]
+    q = p.copy()
+    new = np.stack([p.x, p.y, p.ux, p.uy, p.psi]) - cfg.dzeta * incr
+    alive = p.w > 0
+    inside = ((new[0] >= cfg.x_lo) & (new[0] <= cfg.x_hi) &
+              (new[1] >= cfg.y_lo) & (new[1] <= cfg.y_hi))
+    move = alive & inside
+    q.x[move], q.y[move], q.ux[move], q.uy[move], q.psi[move] = new[:, move]
+    absorbed = alive & ~inside
+    q.w[absorbed] = 0.0
+    if commit:
+        q.hist = np.concatenate([f[None], p.hist[:3]], axis=0)
+    return q, nclamp, int(np.count_nonzero(absorbed))
+
+
+# --------------------------------------------------------------------------
+# Field solve
+# --------------------------------------------------------------------------
+
+def laplacian_eigenvalues(cfg) -> np.ndarray:
+    """Eigenvalues of the 5-point Laplacian with zero Dirichlet nodes on the
+    sine modes sin(pi p i / nx) sin(pi q j / ny), shape (ny-1, nx-1)."""
+    p = np.arange(1, cfg.nx)
+    q = np.arange(1, cfg.ny)
+    lx = -4.0 / cfg.hx ** 2 * np.sin(np.pi * p / (2 * cfg.nx)) ** 2
+    ly = -4.0 / cfg.hy ** 2 * np.sin(np.pi * q / (2 * cfg.ny)) ** 2
+    return ly[:, None] + lx[None, :]
+
+
+def poisson_solve(cfg, src: np.ndarray, shift: float = 0.0) -> np.ndarray:
+    """Solve (lap_h - shift) u = src on the interior nodes with u = 0 on the
+    boundary (fast Poisson solver by a type-I DST, Sec. III.B): transform,
+    divide by the eigenvalues, transform back.  shift = 0 is the Poisson
+    problem of the field equations; the predictor-corrector uses shift > 0."""
+    s = src[1:-1, 1:-1]
+    shat = scipy.fft.dstn(s, type=1)
+    u = np.zeros_like(src)
+    u[1:-1, 1:-1] = scipy.fft.idstn(
+        shat / (laplacian_eigenvalues(cfg) - shift), type=1)
+    return u
+
+
+def ddx(cfg, f: np.ndarray) -> np.ndarray:
+    """Centred x difference at interior nodes; boundary result set to 0."""
+    out = np.zeros_like(f)
+    out[1:-1, 1:-1] = (f[1:-1, 2:] - f[1:-1, :-2]) / (2.0 * cfg.hx)
+    return out
+
+
+def ddy(cfg, f: np.ndarray) -> np.ndarray:
+    out = np.zeros_like(f)
+    out[1:-1, 1:-1] = (f[2:, 1:-1] - f[:-2, 1:-1]) / (2.0 * cfg.hy)
+    return out
+
+
+def solve_psi_ez_bz(cfg, dep: dict) -> dict:
+    """Steps 4-6 of the slice routine: psi from eq. (psi), Ex-By and Ey+Bx
+    from eq. (exmby), Ez from eq. (ez), Bz from eq. (bz)."""
+    psi = poisson_solve(cfg, -dep["rho_mjz"])
+    ez = poisson_solve(cfg, ddx(cfg, dep["jx"]) + ddy(cfg, dep["jy"]))
+    bz = poisson_solve(cfg, ddy(cfg, dep["jx"]) - ddx(cfg, dep["jy"]))
+    return {"psi": psi, "exmby": -ddx(cfg, psi), "eypbx": -ddy(cfg, psi),
+            "ez": ez, "bz": bz}
+
+
+def pc_shift(cfg) -> float:
+    """Screening shift s of the predictor-corrector iteration.  A change dB
+    of Bx/By at slice k changes the trial u_perp at k+1 by
+    -dzeta*AB5[0]*dB, hence J_perp(k+1) and the centred d_zeta J_perp term
+    of the Bx/By source by (AB5[0]/2) * n/D * dB; for the unperturbed
+    plasma (n/D = n0) that is s = (1901/1440) n0."""
+    if getattr(cfg, "pc_shift", None) is not None:
+        return float(cfg.pc_shift)
+    return 0.5 * AB5[0] * cfg.n0
+
+
+def bxby_sources(cfg, jz_k, jx_prev, jy_prev, jx_next, jy_next):
+    """Right-hand sides of eq. (bxby) with d_zeta J_perp at slice k taken as
+    the centred difference (J_{k-1} - J_{k+1}) / (2 dzeta) (slice k-1 lies
+    at zeta + dzeta, slice k+1 at zeta - dzeta)."""
+    dz2 = 2.0 * cfg.dzeta
+    sbx = -ddy(cfg, jz_k) + (jy_prev - jy_next) / dz2
+    sby = ddx(cfg, jz_k) - (jx_prev - jx_next) / dz2
+    return zero_boundary(sbx), zero_boundary(sby)
+
+
+def solve_bxby(cfg, jz_k, jx_prev, jy_prev, jx_next, jy_next, bx_old, by_old):
+    """One corrector solve of eq. (bxby).  The equation lap B = S(B) is
+    written as (lap - s) B_new = S(B_old) - s B_old: it has the same
+    solution at the fixed point B_new = B_old, but the iteration contracts
+    (the unshifted map multiplies the longest sine modes by ~1.32/k^2 and
+    diverges)."""
+    s = pc_shift(cfg)
+    sbx, sby = bxby_sources(cfg, jz_k, jx_prev, jy_prev, jx_next, jy_next)
+    return (poisson_solve(cfg, sbx - s * bx_old, s),
+            poisson_solve(cfg, sby - s * by_old, s))
+
+
+# --------------------------------------------------------------------------
+# Beams
+# --------------------------------------------------------------------------
+
+def gaussian_beam_density(cfg, beam, k: int) -> np.ndarray:
+    """n_b of a rigid Gaussian beam sampled at the nodes of slice k (point
+    sample in zeta: zeroth-order longitudinal deposition)."""
+    x, y = node_coords(cfg)
+    gx = np.exp(-(x - beam.x0) ** 2 / (2.0 * beam.sigma_x ** 2))
+    gy = np.exp(-(y - beam.y0) ** 2 / (2.0 * beam.sigma_y ** 2))
+    return zero_boundary(beam.amp[k] * gy[:, None] * gx[None, :])
+
+
+def gaussian_beam_source(cfg, beam, k: int) -> dict:
+    """Rigid ultra-relativistic electron beam (v = c along z):
+    rho_b = Jz_b = -n_b, J_perp = 0, so rho_b - Jz_b = 0."""
+    nb = gaussian_beam_density(cfg, beam, k)
+    return {"rho": -nb, "jz": -nb}
+
+
+def beam_slice_index(cfg, zeta: np.ndarray) -> np.ndarray:
+    """Nearest slice of each beam particle (zeroth order in zeta)."""
+    return np.rint((cfg.zeta_hi - zeta) / cfg.dzeta).astype(np.int64)
+
+
+def particle_beam_source(cfg, b, k: int) -> dict:
+    """Deposit of the macro-particles of slice k (NGP in zeta, CIC
+    transversely): rho = q w S / (hx hy dzeta), Jz = rho v_z, with
+    rho - Jz = rho (1 + u_perp^2) / (gamma (gamma + u_z)) written so it does
+    not cancel; the transverse beam current is neglected."""
+    sel = (beam_slice_index(cfg, b.zeta) == k)
+    x, y = b.x[sel].astype(np.float64), b.y[sel].astype(np.float64)
+    ux, uy, uz = (b.ux[sel].astype(np.float64), b.uy[sel].astype(np.float64),
+                  b.uz[sel].astype(np.float64))
+    w = b.w[sel].astype(np.float64)
+    inside = (x >= cfg.x_lo) & (x <= cfg.x_hi) & (y >= cfg.y_lo) & (y <= cfg.y_hi)
+    x, y, ux, uy, uz, w = (a[inside] for a in (x, y, ux, uy, uz, w))
+    g = np.sqrt(1.0 + ux * ux + uy * uy + uz * uz)
+    rho = -w / (cfg.hx * cfg.hy * cfg.dzeta)
+    return {"rho": deposit_values(cfg, x, y, rho),
+            "jz": deposit_values(cfg, x, y, rho * uz / g),
+            "rho_mjz": deposit_values(cfg, x, y,
+                                      rho * (1.0 + ux * ux + uy * uy) /
+                                      (g * (g + uz)))}
+
+
+def beam_source(cfg, beam, k: int) -> dict:
+    if beam is None:
+        return {}
+    if hasattr(beam, "amp"):
+        return gaussian_beam_source(cfg, beam, k)
+    if callable(beam):
+        return beam(k)
+    return particle_beam_source(cfg, beam, k)
+
+
+# --------------------------------------------------------------------------
+# One slice and the box
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class SliceState:
+    """Everything slice k needs from earlier slices (Sec. V.B: J_perp of the
+    previous slice and Bx/By of the two previous slices, plus one slice of
+    plasma particles with its Adams-Bashforth history)."""
+    k: int
+    plasma: Plasma
+    jx_prev: np.ndarray
+    jy_prev: np.ndarray
+    bx_prev1: np.ndarray
+    by_prev1: np.ndarray
+    bx_prev2: np.ndarray
+    by_prev2: np.ndarray
+
+    def copy(self) -> "SliceState":
+        return SliceState(self.k, self.plasma.copy(),
+                          *(np.array(getattr(self, n), copy=True) for n in
+                            ("jx_prev", "jy_prev", "bx_prev1", "by_prev1",
+                             "bx_prev2", "by_prev2")))
+
+
+def initial_state(cfg) -> SliceState:
+    z = np.zeros((cfg.ny + 1, cfg.nx + 1))
+    return SliceState(0, init_plasma(cfg), z, z.copy(), z.copy(), z.copy(),
+                      z.copy(), z.copy())
+
+
+def total_deposit(cfg, p: Plasma, beam, k: int) -> dict:
+    """Steps 2-3 of the slice routine: plasma deposit, ion background and
+    the beam source of slice k."""
+    dep = add_ion_background(cfg, plasma_deposit(cfg, p))
+    for c, v in beam_source(cfg, beam, k).items():
+        dep[c] = dep[c] + v
+    return dep
+
+
+def predictor_corrector(cfg, st: SliceState, flds: dict, dep: dict):
+    """Bx/By predictor-corrector (Sec. III.B).  Initial guess by linear
+    extrapolation from the two previous slices, B0 = 2 B_{k-1} - B_{k-2}.
+    Each iteration trial-pushes a copy of the particles to slice k+1 with
+    the current B, deposits Jx, Jy there, solves eq. (bxby) (in the
+    screened form of ``solve_bxby``) and measures
+    r = ||B_new - B_old|| / ||B_new|| over both components (FP64).  It stops
+    when r < pc_tol (pc_tol > 0) or after pc_max_iter iterations.
+    Returns (bx, by, iterations, residual list, clamp count of the trials)."""
+    bx = 2.0 * st.bx_prev1 - st.bx_prev2
+    by = 2.0 * st.by_prev1 - st.by_prev2
+    res = []
+    nclamp = 0
+    it = 0
+    for it in range(1, cfg.pc_max_iter + 1):
+        trial_flds = dict(flds, bx=bx, by=by)
+        trial, nc, _ = ab5_push(cfg, st.plasma, trial_flds, commit=False)
+        nclamp += nc
+        jn = plasma_deposit(cfg, trial, ("jx", "jy"))
+        bx_new, by_new = solve_bxby(cfg, dep["jz"], st.jx_prev, st.jy_prev,
+                                    jn["jx"], jn["jy"], bx, by)
+        num = np.sum((bx_new - bx) ** 2) + np.sum((by_new - by) ** 2)
+        den = np.sum(bx_new ** 2) + np.sum(by_new ** 2)
+        r = np.sqrt(num / den) if den > 0 else (0.0 if num == 0 else np.inf)
+        res.append(float(r))
+        bx, by = bx_new, by_new
+        if cfg.pc_tol > 0 and r < cfg.pc_tol:
+            break
+    return bx, by, it, res, nclamp
+
+
+def advance_slice(cfg, st: SliceState, beam):
+    """Compute the fields of slice st.k and push the plasma to slice k+1
+    (the 2D slice routine of Sec. II, with the predictor-corrector as
+    step 7).  Returns (state at k+1, record of slice k)."""
+    k = st.k
+    dep = total_deposit(cfg, st.plasma, beam, k)
+    flds = solve_psi_ez_bz(cfg, dep)
+    bx, by, its, res, nclamp_pc = predictor_corrector(cfg, st, flds, dep)
+    flds["bx"], flds["by"] = bx, by
+    new_plasma, nclamp, nabs = ab5_push(cfg, st.plasma, flds, commit=True)
+    rec = dict(flds)
+    rec.update(dep)
+    rec["pc_iters"] = its
+    rec["pc_residuals"] = res
+    rec["n_clamped"] = nclamp
+    rec["n_absorbed"] = nabs
+    nxt = SliceState(k + 1, new_plasma, dep["jx"], dep["jy"], bx, by,
+                     st.bx_prev1, st.by_prev1)
+    return nxt, rec
+
+
+def run_box(cfg, beam, keep: Optional[Callable[[int, dict], dict]] = None,
+            state: Optional[SliceState] = None, k_end: Optional[int] = None):
+    """Run slices st.k .. k_end-1 (default: the whole box from the head).
+    ``keep(k, rec)`` selects what to retain per slice (default: all fields
+    and deposits).  Returns (list of kept records, final state)."""
+    st = initial_state(cfg) if state is None else state
+    k_end = cfg.nzeta if k_end is None else k_end
+    out = []
+    while st.k < k_end:
+        k = st.k
+        st, rec = advance_slice(cfg, st, beam)
+        out.append(rec if keep is None else keep(k, rec))
+    return out, st
+
+
+def stack(records: Sequence[dict], name: str) -> np.ndarray:
+    return np.stack([r[name] for r in records])

@@ -1,0 +1,196 @@
+"""Whole-slice-loop pins of the oracle: linear beam-driven wake theory,
+the blowout ion-column field, the x<->y mirror symmetry of a round beam,
+the predictor-corrector fixed point and the Ez = -d_zeta psi consistency
+of the field equations (Sec. II eqs. (psi)-(bz), slice routine steps 1-7)."""
+import numpy as np
+import pytest
+from scipy.integrate import quad
+from scipy.special import j0
+
+import workloads as W
+from oracle import qsp_oracle as O
+
+
+# ---------------------------------------------------------------- linear wake
+# Cold-fluid linear response to a rigid beam n_b = nb f(r) g(zeta) (electron
+# beam, immobile ions, normalised units): (d_zeta^2 + 1) dn = -n_b,
+# (lap - 1) psi = dn, Ez = -d_zeta psi.  With the beam truncated at the box
+# head zeta_hi this gives
+#   psi = -nb R(r) G(zeta),  Ez = -nb R(r) C(zeta),
+#   R = (lap - 1)^-1 f = -s^2 int_0^inf k J0(kr) exp(-k^2 s^2/2)/(1+k^2) dk,
+#   G = int_zeta^zeta_hi sin(z'-zeta) g(z') dz',  C = same with cos.
+
+def R_closed(r, sig):
+    return quad(lambda k: -sig ** 2 * k * j0(k * r) * np.exp(-k * k * sig * sig / 2)
+                / (1 + k * k), 0, 40, limit=400)[0]
+
+
+def linear_theory(cfg, nb, zc=-2.0, sz=1.0, sig=1.0):
+    x = cfg.x_lo + cfg.hx * np.arange(cfg.nx + 1)
+    R = np.array([R_closed(abs(v), sig) for v in x])
+    g = lambda t: np.exp(-(t - zc) ** 2 / (2 * sz ** 2))
+    C = np.array([quad(lambda t: np.cos(t - z) * g(t), z, cfg.zeta_hi)[0]
+                  for z in cfg.zeta()])
+    G = np.array([quad(lambda t: np.sin(t - z) * g(t), z, cfg.zeta_hi)[0]
+                  for z in cfg.zeta()])
+    return -nb * C[:, None] * R[None, :], -nb * G[:, None] * R[None, :]
+
+
+def c1_plane(nb, n=64, nz=64):
+    """Ez and psi in the y = 0 plane (all slices) from the oracle."""
+    cfg, _ = W.c1(nb)
+    cfg.nx = cfg.ny = n
+    cfg.nzeta, cfg.dzeta = nz, 8.0 / nz
+    beam = W.GaussianBeam(W.gaussian_envelope(cfg, nb, -2.0, 1.0), 1.0, 1.0)
+    j = cfg.ny // 2
+    recs, _ = O.run_box(cfg, beam, keep=lambda k, r: (r["ez"][j].copy(),
+                                                     r["psi"][j].copy()))
+    return cfg, np.stack([r[0] for r in recs]), np.stack([r[1] for r in recs])
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_r_closed_form_on_axis():
+    # R(0) = -(1/2) e^(1/2) E1(1/2) for sigma = 1
+    from scipy.special import exp1
+    assert abs(R_closed(0.0, 1.0) + 0.5 * np.exp(0.5) * exp1(0.5)) < 1e-10
+
+
+def test_linear_wake_matches_theory_c1():
+    cfg, ez, psi = c1_plane(0.01)
+    ez_th, psi_th = linear_theory(cfg, 0.01)
+    assert rel(ez, ez_th) < 0.05
+    assert rel(psi, psi_th) < 0.05
+    c = cfg.nx // 2
+    assert abs(ez[:, c].min() / ez_th[:, c].min() - 1) < 0.03
+
+
+def test_linear_wake_second_order_convergence():
+    nb = 1e-4      # deep in the linear regime: only discretisation error left
+    errs = []
+    for n in (64, 128):
+        cfg, ez, _ = c1_plane(nb, n, n)
+        errs.append(rel(ez, linear_theory(cfg, nb)[0]))
+    assert errs[0] < 0.05 and errs[0] / errs[1] > 3.0, errs
+
+
+def test_nonlinear_deviation_scales_with_amplitude():
+    _, e0, _ = c1_plane(1e-4)
+    base = e0 / 1e-4
+    d = [np.linalg.norm(c1_plane(nb)[1] / nb - base) for nb in (0.01, 0.005)]
+    assert 1.8 < d[0] / d[1] < 2.2
+
+
+# ---------------------------------------------------------------- blowout
+
+@pytest.mark.slow
+def test_blowout_ion_column_field():
+    cfg, beam = W.c2(n=128, nzeta=256)
+    j = cfg.ny // 2
+    recs, _ = O.run_box(cfg, beam, keep=lambda k, r: {
+        "exmby": r["exmby"][j].copy(), "ez": r["ez"][j].copy(),
+        "rho_mjz": r["rho_mjz"][j].copy(), "it": r["pc_iters"],
+        "res": r["pc_residuals"][-1]})
+    x = cfg.x_lo + cfg.hx * np.arange(cfg.nx + 1)
+    c = cfg.nx // 2
+
+    def radius(r):   # electron-free half-width on the axis row (rho-Jz = +n0)
+        n = 0
+        while abs(r["rho_mjz"][c + n + 1] - 1.0) < 0.05:
+            n += 1
+        return n
+
+    rb = [radius(r) for r in recs]
+    k = int(np.argmax(rb))
+    assert rb[k] * cfg.hx > 1.5            # r_b ~ 2 sqrt(n_b sigma_r^2) ~ 1.9
+    sel = slice(c - rb[k] // 2, c + rb[k] // 2 + 1)
+    slope = np.polyfit(x[sel], recs[k]["exmby"][sel], 1)[0]
+    assert abs(slope - 0.5) < 0.01
+    # Ez is flat across the bubble where it is strong
+    k2 = k + 48
+    sel2 = slice(c - rb[k2] // 2, c + rb[k2] // 2 + 1)
+    ez = recs[k2]["ez"][sel2]
+    assert np.ptp(ez) < 0.02 * np.abs(ez).max()
+    # the predictor-corrector met its tolerance within 5 iterations
+    assert all(r["it"] <= 5 for r in recs)
+    assert sum(r["res"] < cfg.pc_tol for r in recs) > 0.95 * len(recs)
+
+
+# ---------------------------------------------------------------- symmetry
+
+def test_mirror_symmetry_round_beam():
+    cfg, beam = W.small(n=32, nzeta=12, nb=1.0)
+    recs, _ = O.run_box(cfg, beam)
+    for r in recs[3:]:
+        s = np.abs(r["by"]).max()
+        assert np.abs(r["psi"] - r["psi"].T).max() < 1e-12 * np.abs(r["psi"]).max()
+        assert np.abs(r["exmby"] - r["eypbx"].T).max() < 1e-12 * np.abs(r["exmby"]).max()
+        assert np.abs(r["bx"] + r["by"].T).max() < 1e-12 * s
+        assert np.abs(r["bz"] + r["bz"].T).max() < 1e-12 * s
+        assert np.abs(r["ez"] - r["ez"].T).max() < 1e-12 * np.abs(r["ez"]).max()
+
+
+# ---------------------------------------------------------------- P-C
+
+def test_pc_converges_to_fixed_point_of_bxby_equation():
+    cfg, beam = W.small(n=32, nzeta=10, nb=1.0, pc_max_iter=40, pc_tol=1e-13)
+    st = O.initial_state(cfg)
+    for _ in range(8):
+        st, rec = O.advance_slice(cfg, st, beam)
+    prev = st.copy()
+    st, rec = O.advance_slice(cfg, st, beam)
+    assert rec["pc_residuals"][-1] < 1e-13
+    bx, by = rec["bx"], rec["by"]
+    trial, _, _ = O.ab5_push(cfg, prev.plasma, {**{k: rec[k] for k in
+                             ("exmby", "eypbx", "ez", "bz")}, "bx": bx, "by": by},
+                             commit=False)
+    jn = O.plasma_deposit(cfg, trial, ("jx", "jy"))
+    sbx, sby = O.bxby_sources(cfg, rec["jz"], prev.jx_prev, prev.jy_prev,
+                              jn["jx"], jn["jy"])
+    lap = lambda f: O.zero_boundary(np.pad(
+        (f[1:-1, 2:] - 2 * f[1:-1, 1:-1] + f[1:-1, :-2]) / cfg.hx ** 2 +
+        (f[2:, 1:-1] - 2 * f[1:-1, 1:-1] + f[:-2, 1:-1]) / cfg.hy ** 2, 1))
+    assert rel(lap(bx), sbx) < 1e-9 and rel(lap(by), sby) < 1e-9
+
+
+def test_unscreened_iteration_diverges_screened_contracts():
+    # the reading behind the screening shift: with s = 0 the corrector map
+    # amplifies the longest sine modes (~1.32/k^2 > 1) and the residual grows
+    cfg, beam = W.c1()
+    cfg.pc_max_iter, cfg.pc_tol = 6, 0.0
+    st = O.initial_state(cfg)
+    for _ in range(16):
+        st, rec = O.advance_slice(cfg, st, beam)
+    r = rec["pc_residuals"]
+    assert all(b < 0.1 * a for a, b in zip(r[:3], r[1:4]))
+    cfg.pc_shift = 0.0
+    _, rec0 = O.advance_slice(cfg, st, beam)
+    assert rec0["pc_residuals"][-1] > 1.0
+
+
+# ---------------------------------------------------------------- consistency
+
+def test_ez_equals_minus_dzeta_psi_linear():
+    cfg, beam = W.c1()
+    recs, _ = O.run_box(cfg, beam)
+    psi, ez = O.stack(recs, "psi"), O.stack(recs, "ez")
+    e = [rel(-(psi[k - 1] - psi[k + 1]) / (2 * cfg.dzeta), ez[k])
+         for k in range(1, cfg.nzeta - 1)]
+    assert np.median(e) < 0.02
+
+
+def test_particle_psi_tracks_grid_psi():
+    errs = []
+    for n, nz in ((32, 24), (64, 48)):
+        cfg, beam = W.small(n=n, nzeta=nz, nb=0.5)
+        st = O.initial_state(cfg)
+        e = []
+        for k in range(cfg.nzeta):
+            p = st.plasma
+            st, rec = O.advance_slice(cfg, st, beam)
+            g = O.gather(cfg, rec["psi"], p.x, p.y)
+            e.append(np.linalg.norm(p.psi - g) / np.linalg.norm(g) if k > 4 else 0)
+        errs.append(np.median(e[5:]))
+    assert errs[0] < 0.06 and errs[1] < errs[0] / 1.5, errs

@@ -1,0 +1,233 @@
+"""Seeded synthetic workloads for the quasi-static PIC slice loop.
+
+This module only *describes inputs*: grid and box geometry, plasma lattice
+density, beam envelopes and seeded random draws.  It holds none of the
+method's arithmetic (no deposit, push, source or solve), so both the FP64
+oracle under ``oracle/`` and the HIP product path may use it.
+
+The workloads follow the paper's reference setup (Sec. IV and the Appendix:
+Gaussian driver and witness beams in a uniform plasma with immobile ions,
+normalised units, domain (-8,8)^2 x (-7,5) k_p^-1, dt = 6 / omega_p) scaled to
+the five configurations the hot path is exercised on:
+
+* ``c1``  64^2 x 64 linear wake (n_b/n0 = 0.01), 3 fixed P-C iterations
+* ``c2``  512^2 x 1024 blowout wake (n_b/n0 = 10), P-C to 1e-4, <= 5 iterations
+* ``c3``  1024^2 x 1024 paper-scale step with 2 x 2^21 macro-particle beams
+* ``c4``  256^2 x 512 adjoint workload, per-slice amplitudes with 5% noise
+* ``c5``  1024^2 x 1024, 2x2 plasma lattice, adjoint with memory pressure
+
+All lengths are in units of k_p^-1, densities in units of n0.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+SEED = 210910277
+
+# Floor applied to 1 + Psi before it is used as a divisor (the paper leaves the
+# singular limit unspecified; both implementations clamp the same way).
+ONE_PLUS_PSI_FLOOR = 0.01
+
+
+@dataclasses.dataclass
+class BoxConfig:
+    """Geometry, plasma and solver parameters of one simulation box.
+
+    Nodes are x_i = x_lo + i*hx for i = 0..nx (same in y); nodes 0 and nx
+    carry the homogeneous Dirichlet boundary.  Slice k sits at
+    zeta_k = zeta_hi - k*dzeta, k = 0..nzeta-1 (slice 0 is the box head).
+    The plasma electrons start on a uniform lattice of (nx*ppc_x) x (ny*ppc_y)
+    sites at the centres of a ppc-times refined cell grid.
+    """
+    nx: int
+    ny: int
+    x_lo: float
+    x_hi: float
+    y_lo: float
+    y_hi: float
+    nzeta: int
+    zeta_hi: float
+    dzeta: float
+    ppc_x: int = 1
+    ppc_y: int = 1
+    n0: float = 1.0
+    pc_max_iter: int = 3
+    pc_tol: float = 0.0          # <= 0: always pc_max_iter iterations
+    pc_shift: Optional[float] = None   # None: the method's default screening
+    psi_floor: float = ONE_PLUS_PSI_FLOOR
+
+    @property
+    def hx(self) -> float:
+        return (self.x_hi - self.x_lo) / self.nx
+
+    @property
+    def hy(self) -> float:
+        return (self.y_hi - self.y_lo) / self.ny
+
+    @property
+    def n_particles(self) -> int:
+        return self.nx * self.ppc_x * self.ny * self.ppc_y
+
+    def zeta(self) -> np.ndarray:
+        return self.zeta_hi - self.dzeta * np.arange(self.nzeta)
+
+
+@dataclasses.dataclass
+class GaussianBeam:
+    """Rigid, ultra-relativistic electron beam with a Gaussian transverse
+    profile and an arbitrary per-slice peak density ``amp[k]`` (n_b/n0)."""
+    amp: np.ndarray          # [nzeta] float64
+    sigma_x: float
+    sigma_y: float
+    x0: float = 0.0
+    y0: float = 0.0
+
+
+@dataclasses.dataclass
+class ParticleBeam:
+    """Macro-particle electron beam (SoA, float32 like the GPU storage)."""
+    x: np.ndarray
+    y: np.ndarray
+    zeta: np.ndarray
+    ux: np.ndarray
+    uy: np.ndarray
+    uz: np.ndarray
+    w: np.ndarray            # number of physical electrons (units n0 k_p^-3)
+
+    def soa(self) -> np.ndarray:
+        return np.stack([self.x, self.y, self.zeta, self.ux, self.uy,
+                         self.uz, self.w]).astype(np.float32)
+
+
+def gaussian_envelope(cfg: BoxConfig, peak: float, zeta_c: float,
+                      sigma_z: float) -> np.ndarray:
+    z = cfg.zeta()
+    return peak * np.exp(-(z - zeta_c) ** 2 / (2.0 * sigma_z ** 2))
+
+
+# --------------------------------------------------------------------------
+# The five workloads
+# --------------------------------------------------------------------------
+
+def c1(nb: float = 0.01) -> tuple[BoxConfig, GaussianBeam]:
+    """64^2 x 64 linear wake: x,y in [-8,8], zeta in (-8,0], 1 ppc, rigid
+    driver n_b/n0 = nb, sigma = 1, centred 2 behind the head, 3 P-C steps."""
+    cfg = BoxConfig(nx=64, ny=64, x_lo=-8.0, x_hi=8.0, y_lo=-8.0, y_hi=8.0,
+                    nzeta=64, zeta_hi=0.0, dzeta=8.0 / 64,
+                    pc_max_iter=3, pc_tol=0.0)
+    beam = GaussianBeam(gaussian_envelope(cfg, nb, -2.0, 1.0), 1.0, 1.0)
+    return cfg, beam
+
+
+def c2(n: int = 512, nzeta: int = 1024) -> tuple[BoxConfig, GaussianBeam]:
+    """Blowout wake: [-6,6]^2, zeta in (-6,4], driver n_b/n0 = 10,
+    sigma_r = 0.3, sigma_z = 1.41 at zeta = 0, P-C to 1e-4 (max 5)."""
+    cfg = BoxConfig(nx=n, ny=n, x_lo=-6.0, x_hi=6.0, y_lo=-6.0, y_hi=6.0,
+                    nzeta=nzeta, zeta_hi=4.0, dzeta=10.0 / nzeta,
+                    pc_max_iter=5, pc_tol=1e-4)
+    beam = GaussianBeam(gaussian_envelope(cfg, 10.0, 0.0, 1.41), 0.3, 0.3)
+    return cfg, beam
+
+
+C3_DRIVER = dict(peak=5.0, sigma_r=0.25, sigma_z=1.0, zeta_c=0.0)
+C3_WITNESS = dict(peak=20.0, sigma_r=0.1, sigma_z=0.2, zeta_c=-5.0)
+C3_GAMMA = 2000.0
+BEAM_DT = 6.0     # beam time step, omega_p^-1 (Appendix)
+
+
+def c3_config(n: int = 1024, nzeta: int = 1024) -> BoxConfig:
+    return BoxConfig(nx=n, ny=n, x_lo=-8.0, x_hi=8.0, y_lo=-8.0, y_hi=8.0,
+                     nzeta=nzeta, zeta_hi=5.0, dzeta=12.0 / nzeta,
+                     pc_max_iter=5, pc_tol=1e-4)
+
+
+def gaussian_particle_beam(n: int, peak: float, sigma_r: float,
+                           sigma_z: float, zeta_c: float, gamma: float,
+                           rng: np.random.Generator) -> ParticleBeam:
+    """n fixed-weight macro-particles with normally distributed positions
+    whose density peaks at ``peak`` (n_b/n0); momenta ux = uy = 0,
+    uz = sqrt(gamma^2 - 1)."""
+    x = rng.normal(0.0, sigma_r, n)
+    y = rng.normal(0.0, sigma_r, n)
+    z = rng.normal(zeta_c, sigma_z, n)
+    total = peak * (2.0 * math.pi) ** 1.5 * sigma_r * sigma_r * sigma_z
+    uz = math.sqrt(gamma * gamma - 1.0)
+    return ParticleBeam(x=x, y=y, zeta=z, ux=np.zeros(n), uy=np.zeros(n),
+                        uz=np.full(n, uz), w=np.full(n, total / n))
+
+
+def c3(n: int = 1024, nzeta: int = 1024, n_per_beam: int = 2 ** 21,
+       seed: int = SEED) -> tuple[BoxConfig, ParticleBeam]:
+    """Paper-scale step: 1024^2 x 1024, 1 ppc, driver + witness beams of
+    ``n_per_beam`` macro-particles each, gamma = 2000."""
+    cfg = c3_config(n, nzeta)
+    rng = np.random.default_rng(seed)
+    d = gaussian_particle_beam(n_per_beam, C3_DRIVER["peak"],
+                               C3_DRIVER["sigma_r"], C3_DRIVER["sigma_z"],
+                               C3_DRIVER["zeta_c"], C3_GAMMA, rng)
+    w = gaussian_particle_beam(n_per_beam, C3_WITNESS["peak"],
+                               C3_WITNESS["sigma_r"], C3_WITNESS["sigma_z"],
+                               C3_WITNESS["zeta_c"], C3_GAMMA, rng)
+    beam = ParticleBeam(*(np.concatenate([getattr(d, f.name), getattr(w, f.name)])
+                          for f in dataclasses.fields(ParticleBeam)))
+    return cfg, beam
+
+
+def c4(n: int = 256, nzeta: int = 512, seed: int = SEED
+       ) -> tuple[BoxConfig, GaussianBeam]:
+    """Adjoint workload: [-6,6]^2, zeta in (-10,0], driver amplitudes
+    2*exp(-(zeta+3)^2/2)*(1 + 0.05 u), u ~ U(-1,1) seeded, sigma_r = 0.4,
+    3 fixed P-C iterations."""
+    cfg = BoxConfig(nx=n, ny=n, x_lo=-6.0, x_hi=6.0, y_lo=-6.0, y_hi=6.0,
+                    nzeta=nzeta, zeta_hi=0.0, dzeta=10.0 / nzeta,
+                    pc_max_iter=3, pc_tol=0.0)
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-1.0, 1.0, nzeta)
+    amp = gaussian_envelope(cfg, 2.0, -3.0, 1.0) * (1.0 + 0.05 * u)
+    return cfg, GaussianBeam(amp, 0.4, 0.4)
+
+
+C4_LOSS_SLICES = (400, 420)   # inclusive range of witness slices
+
+
+def c5(n: int = 1024, nzeta: int = 1024) -> tuple[BoxConfig, GaussianBeam]:
+    """Large adjoint: C3 geometry, 2x2 plasma lattice, driver 5*exp(-zeta^2/2),
+    sigma_x = sigma_y = 0.25, 3 fixed P-C iterations."""
+    cfg = c3_config(n, nzeta)
+    cfg.ppc_x = cfg.ppc_y = 2
+    cfg.pc_max_iter, cfg.pc_tol = 3, 0.0
+    amp = gaussian_envelope(cfg, C3_DRIVER["peak"], C3_DRIVER["zeta_c"],
+                            C3_DRIVER["sigma_z"])
+    return cfg, GaussianBeam(amp, 0.25, 0.25)
+
+
+def witness_profile(cfg: BoxConfig) -> np.ndarray:
+    """Loss weights n_w(x_i, y_j, zeta_k) of the C3 witness (peak 20,
+    sigma_r 0.1, sigma_z 0.2, centre -5), shape [nzeta, ny+1, nx+1]."""
+    x = cfg.x_lo + cfg.hx * np.arange(cfg.nx + 1)
+    y = cfg.y_lo + cfg.hy * np.arange(cfg.ny + 1)
+    z = cfg.zeta()
+    p = C3_WITNESS
+    gz = p["peak"] * np.exp(-(z - p["zeta_c"]) ** 2 / (2 * p["sigma_z"] ** 2))
+    gx = np.exp(-x ** 2 / (2 * p["sigma_r"] ** 2))
+    gy = np.exp(-y ** 2 / (2 * p["sigma_r"] ** 2))
+    return gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+
+
+def small(n: int = 32, nzeta: int = 24, ppc: int = 1, nb: float = 0.5,
+          sigma: float = 0.8, pc_max_iter: int = 3, pc_tol: float = 0.0,
+          extent: float = 6.0) -> tuple[BoxConfig, GaussianBeam]:
+    """A tiny moderately nonlinear box for fast unit and parity tests."""
+    cfg = BoxConfig(nx=n, ny=n, x_lo=-extent, x_hi=extent, y_lo=-extent,
+                    y_hi=extent, nzeta=nzeta, zeta_hi=0.0,
+                    dzeta=4.0 / nzeta, ppc_x=ppc, ppc_y=ppc,
+                    pc_max_iter=pc_max_iter, pc_tol=pc_tol)
+    beam = GaussianBeam(gaussian_envelope(cfg, nb, -1.0, 0.7), sigma, sigma)
+    return cfg, beam
+
+
+PRESETS = {"c1": c1, "c2": c2, "c4": c4, "c5": c5}
