@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the quasi-static PIC slice loop on one MI355X.
+
+One step = one full box of the per-slice loop (plasma reset to the lattice,
+then every slice: deposit, beam source, psi/Ez/Bz solves, Bx/By
+predictor-corrector, real push) on the blowout workload: 512 x 512 nodes
+over [-6, 6]^2, 1024 slices over 10 k_p^-1, 1 plasma electron per cell
+(262,144 particles), rigid Gaussian driver n_b/n0 = 10, sigma_r = 0.3,
+sigma_z = 1.41, predictor-corrector to 1e-4 (at most 5 iterations), FP32
+with FP64 deposition sums.  Inputs are synthetic and resident on the GPU
+before the timed region.
+
+Prints one JSON line: particle-slice updates/s (whole job), DST solves/s,
+the FP64 rate and FP32/FP64 ratio, the roofline of the dominant kernel (the
+fused gather + push + deposit, timed with HIP events on the library's stream
+inside the timed region) and the FP64 CPU oracle timed on a bounded sample
+of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+METRIC = "plasma particle-slice updates/s + DST solves/s; FP32 vs FP64; fwd+bwd/fwd ratio"
+
+
+def workload(name: str):
+    import workloads as W
+    if name == "c2":
+        cfg, beam = W.c2()
+        return cfg, beam, "c2_blowout_512x512x1024_1ppc"
+    if name == "c1":
+        cfg, beam = W.c1()
+        return cfg, beam, "c1_linear_64x64x64_1ppc"
+    if name == "c5fwd":
+        cfg, beam = W.c5()
+        return cfg, beam, "c5_forward_1024x1024x1024_4ppc"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def push_bytes(cfg, fsize: int) -> int:
+    """Algorithmic HBM bytes of one real push launch: every particle reads
+    its state (x, y, ux, uy, Psi, w) and 4 history slots x 5 quantities and
+    writes 5 state + 5 history values; the six field planes are read once
+    and the five FP64 deposit planes written once."""
+    n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
+    plane = cfg.nx * cfg.ny
+    return n_p * (26 + 10) * fsize + 6 * plane * fsize + 5 * plane * 8
+
+
+def run_gpu(cfg, beam, precision: str, steps: int, warmup: int, timing_every: int):
+    import torch
+    from paper_2109_10277_amd import qsp
+    box = qsp.Box(cfg, precision)
+    box.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
+    for _ in range(warmup):
+        box.init_plasma()
+        box.run_box()
+    torch.cuda.synchronize()
+    box.set_timing(timing_every)
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        box.init_plasma()
+        stats.append(box.run_box())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = box.kernel_times()
+    box.set_timing(0)
+    return box, (t1 - t0), stats, kt
+
+
+def standalone_solves(box, cfg, reps: int = 50) -> float:
+    """Batched (3-field) Dirichlet solves per second through the C ABI."""
+    import torch
+    src = torch.randn(3, cfg.ny + 1, cfg.nx + 1, dtype=box.fdtype, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        box.solve_poisson(src, dst)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        box.solve_poisson(src, dst)
+    torch.cuda.synchronize()
+    return 3 * reps / (time.perf_counter() - t0)
+
+
+def cpu_baseline(cfg, beam, n_slices: int) -> dict:
+    """The FP64 oracle on the host cores: the first n_slices slices of the
+    same box, from the unperturbed plasma."""
+    from oracle import qsp_oracle as O
+    st = O.initial_state(cfg)
+    c0, w0 = time.process_time(), time.perf_counter()
+    for _ in range(n_slices):
+        st, _ = O.advance_slice(cfg, st, beam)
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
+    return {"value": n_p * n_slices / wall, "unit": "particle-slice updates/s",
+            "cores": max(1, round(cpu / wall)), "kind": "oracle",
+            "sample": f"first {n_slices} of {cfg.nzeta} slices of the same box "
+                      f"({n_p} particles), FP64 NumPy/SciPy, {wall:.1f} s wall, "
+                      f"{len(os.sched_getaffinity(0))} host cores visible"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--timing-every", type=int, default=4,
+                    help="time the kernels of every n-th slice with HIP events")
+    ap.add_argument("--cpu-slices", type=int, default=12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the slice loop of one box is not "
+              "split across GPUs in this build (see DESIGN.md for how it would "
+              "shard); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    cfg, beam, wname = workload(args.workload)
+    n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
+    box, dt, stats, kt = run_gpu(cfg, beam, "fp32", args.steps, args.warmup,
+                                 args.timing_every)
+    updates = n_p * cfg.nzeta * args.steps
+    value = updates / dt
+    solves = sum(s["dst_solves"] for s in stats)
+    dst_ms = sum(kt[c][0] for c in ("row_fwd", "col", "row_inv"))
+    push_ms, push_n = kt["push"]
+    push_avg_ms = push_ms / max(push_n, 1)
+    bytes_launch = push_bytes(cfg, 4)
+    achieved = bytes_launch / (push_avg_ms * 1e-3) / 1e9
+    standalone = standalone_solves(box, cfg)
+    box.close()
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-slice updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wname, "nx": cfg.nx, "ny": cfg.ny,
+                   "slices": cfg.nzeta, "particles": n_p,
+                   "pc": f"<= {cfg.pc_max_iter} iterations, tol {cfg.pc_tol}",
+                   "deposit_sums": "f64"},
+        "dst_solves_per_s": solves / dt,
+        "dst_solves_per_s_standalone_batch3": standalone,
+        "pc_iterations_per_slice": sum(s["pc_iterations"] for s in stats) / (cfg.nzeta * args.steps),
+        "kernel_ms_per_step": {c: kt[c][0] / args.steps * args.timing_every for c in kt},
+        "fwd_bwd_over_fwd": None,
+        "roofline": {"bound": "hbm", "kernel": "gather+push+deposit (real push)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_launch": bytes_launch,
+                     "avg_launch_ms": push_avg_ms, "launches_timed": push_n},
+    }
+    if not args.no_fp64:
+        box64, dt64, _, _ = run_gpu(cfg, beam, "fp64", max(1, args.steps // 2), 1, 0)
+        box64.close()
+        v64 = n_p * cfg.nzeta * max(1, args.steps // 2) / dt64
+        out["fp64_value"] = v64
+        out["fp32_over_fp64"] = value / v64
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg, beam, args.cpu_slices)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

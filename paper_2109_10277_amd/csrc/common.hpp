@@ -1,0 +1,87 @@
+// Shared declarations of the libqsp runtime and its HIP kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+
+namespace qsp {
+
+// 256 threads = 4 wave64 wavefronts per workgroup everywhere.
+constexpr int kBlock = 256;
+
+// Largest number of output copies one slice can request (12 quantities as
+// full plane, centre row and axis node).
+constexpr int kMaxOut = 36;
+
+// Fifth-order Adams-Bashforth weights (numerators over 720) for
+// f_k, f_{k-1}, ..., f_{k-4}.
+constexpr double kAB5[5] = {1901.0 / 720.0, -2774.0 / 720.0, 2616.0 / 720.0,
+                            -1274.0 / 720.0, 251.0 / 720.0};
+
+struct DeviceError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+inline void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e != hipSuccess) {
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%s failed at %s:%d: %s", what, file, line,
+                  hipGetErrorString(e));
+    throw DeviceError(buf);
+  }
+}
+#define QSP_HIP(call) ::qsp::hip_check((call), #call, __FILE__, __LINE__)
+#define QSP_LAUNCH_CHECK() ::qsp::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+template <typename T>
+struct Cplx {
+  T re, im;
+};
+
+// ---------------------------------------------------------------------------
+// Grid geometry shared by all kernels.  Node arrays are stored [ny][nx]
+// (pitch nx): element (j, i) is node (i, j) for i, j in 0..n-1; node index 0
+// carries the Dirichlet boundary (always 0 for fields) and node index n is
+// implicit (0).  This makes each stored row the first half of the odd
+// extension a type-I sine transform needs.
+// ---------------------------------------------------------------------------
+struct Geom {
+  int nx, ny;            // cells = nodes per stored row/column
+  int lx, ly;            // log2(nx), log2(ny)
+  double x_lo, y_lo, hx, hy;
+};
+
+// Plasma lattice: (nx*ppc_x) x (ny*ppc_y) sites, particle p = I + J*nX.
+struct Lattice {
+  int nX, nY, ppc_x, ppc_y;
+  int64_t np;
+};
+
+// Per-slice twiddle / transform tables of one axis (device pointers).
+template <typename T>
+struct AxisTables {
+  const Cplx<T>* tw;     // e^{-2 pi i m / n}, m = 0..n-1
+  const T* pre;          // sin(pi j / n), j = 0..n-1
+  const double* lam;     // Laplacian eigenvalue of sine mode p, p = 0..n-1 (0 unused)
+};
+
+// Device-side scalars of the predictor-corrector and counters.
+struct DevCounters {
+  unsigned int pc_done;        // 1 once the current slice's P-C converged
+  unsigned int pc_iters;       // iterations done for the current slice
+  unsigned int blocks_arrived; // last-block-done counter of the residual
+  unsigned int nonfinite;      // sticky: non-finite residual or norm seen
+  double pc_resid;             // last residual of the current slice
+  double max_resid;            // largest final residual over slices
+  unsigned long long n_clamped;
+  unsigned long long n_absorbed;
+  unsigned long long n_dep_global;
+  unsigned long long pc_iterations;
+  unsigned long long pc_not_converged;
+};
+
+}  // namespace qsp

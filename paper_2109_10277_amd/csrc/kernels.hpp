@@ -1,0 +1,193 @@
+// Argument blocks and launchers of the libqsp HIP kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace qsp {
+
+// ---------------------------------------------------------------- DST solve
+template <typename T>
+struct SrcPEZ {             // psi, Ez, Bz sources of slice k
+  const double* rho_mjz;    // plasma + beam deposits (ions added here)
+  const double* jx;
+  const double* jy;
+  double n0;
+  T* out;                   // 3 planes [ny][nx]: psi, Ez, Bz (x-transformed)
+};
+
+template <typename T>
+struct SrcBxBy {            // Bx, By corrector sources
+  const double* jz;         // Jz of slice k (plasma + particle beam)
+  const double* jx_prev;    // J_perp of slice k-1
+  const double* jy_prev;
+  const double* jx_next;    // trial J_perp of slice k+1
+  const double* jy_next;
+  const T* bx;              // current iterate
+  const T* by;
+  double shift, dzeta;
+  double beam_amp;          // Gaussian beam amplitude of slice k (0 = none)
+  const double* bgx;        // Gaussian profile factors at the nodes
+  const double* bgy;
+  T* out;                   // 2 planes: Bx, By (x-transformed)
+};
+
+// Planes of FP64 scratch a kernel clears on the side (spread over its grid)
+// once their previous readers have finished.
+struct ZeroJob {
+  double* p[6];
+  int count;
+  size_t n;                 // elements per plane
+};
+
+template <typename T>
+struct ColArgs {
+  const T* in;              // nfield planes
+  T* out;                   // nfield planes
+  T* out_dy;                // optional: -d_y of field 0 (nullptr = none)
+  double shift[4];          // per field
+  int honor_done;           // skip when the P-C has converged
+  int w;                    // columns per workgroup (power of two, >= 2)
+  ZeroJob zero;
+};
+
+// B^(0) = 2 B_{k-1} - B_{k-2} and the opening of a slice's predictor-
+// corrector, done on the side of a row pass.
+template <typename T>
+struct GuessJob {
+  T* bx;
+  T* by;
+  const T* bx1;
+  const T* by1;
+  const T* bx2;
+  const T* by2;
+  DevCounters* ctr;         // nullptr = no guess job
+};
+
+template <typename T>
+struct RowInvArgs {
+  const T* in[4];
+  T* out[4];
+  T* out_dx[4];             // optional -d_x of the result
+  GuessJob<T> guess;
+};
+
+template <typename T>
+struct PCArgs {
+  const T* in;              // 2 planes from the column pass
+  T* bx;                    // iterate, updated in place
+  T* by;
+  double* partial;          // 2 doubles per workgroup
+  double tol;
+};
+
+template <typename T>
+void launch_src_fwd_pez(const Geom&, const SrcPEZ<T>&, const AxisTables<T>&, hipStream_t);
+template <typename T>
+void launch_src_fwd_bxby(const Geom&, const SrcBxBy<T>&, const AxisTables<T>&,
+                         const DevCounters*, hipStream_t);
+template <typename T>
+void launch_col_solve(const Geom&, const ColArgs<T>&, int nfield, const AxisTables<T>&,
+                      const double* lamx, const DevCounters*, hipStream_t);
+template <typename T>
+void launch_row_inv(const Geom&, const RowInvArgs<T>&, int nfield, const AxisTables<T>&,
+                    hipStream_t);
+template <typename T>
+void launch_row_inv_pc(const Geom&, const PCArgs<T>&, const AxisTables<T>&, DevCounters*,
+                       hipStream_t);
+int pc_partial_count(const Geom&);
+// column-strip width of a column pass over nfield planes
+template <typename T>
+int col_width(const Geom&, int nfield);
+
+// ---------------------------------------------------------------- particles
+template <typename T>
+struct Particles {          // SoA, lattice order
+  T* xi_x;                  // displacement from the lattice site, in cells
+  T* xi_y;
+  T* ux;
+  T* uy;
+  T* psi;
+  T* w;                     // density weight n0/(ppc_x ppc_y); 0 = absorbed
+  T* hist;                  // [4][5][np], slot s holds f of a slice = s mod 4
+};
+
+template <typename T>
+struct SliceFields {        // the six fields a particle sees
+  const T* exmby;
+  const T* eypbx;
+  const T* ez;
+  const T* bx;
+  const T* by;
+  const T* bz;
+};
+
+struct DepOut {
+  double* ch[5];            // rho-Jz, Jx, Jy, Jz, rho (rho may be null)
+};
+
+enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2 };
+
+template <typename T>
+struct PushArgs {
+  Particles<T> p;
+  SliceFields<T> f;
+  DepOut dep;
+  int k;                    // slice being left (history ring position)
+  double dzeta, hx, hy, psi_floor;
+  int tiled;                // 1: LDS tile histograms, 0: direct global atomics
+  int tile_rows;            // lattice rows per workgroup tile
+  // end-of-slice bookkeeping of the predictor-corrector (real push only)
+  int32_t* iters_out;
+  double* resid_out;
+  double pc_tol;
+  int pc_max_iter;
+};
+
+template <typename T>
+void launch_init_plasma(const Lattice&, const Particles<T>&, double w0, hipStream_t);
+template <typename T>
+void launch_push(const Geom&, const Lattice&, const PushArgs<T>&, PushMode, bool with_rho,
+                 DevCounters*, hipStream_t);
+template <typename T>
+void launch_import_state(const Geom&, const Lattice&, const Particles<T>&, const double* x,
+                         const double* y, const double* ux, const double* uy,
+                         const double* psi, const double* w, const double* hist, int k,
+                         hipStream_t);
+template <typename T>
+void launch_export_state(const Geom&, const Lattice&, const Particles<T>&, double* x,
+                         double* y, double* ux, double* uy, double* psi, double* w,
+                         double* hist, int k, hipStream_t);
+
+// ---------------------------------------------------------------- grid utils
+void launch_zero(double* p, size_t n, hipStream_t);
+template <typename T>
+void launch_zero_t(T* p, size_t n, hipStream_t);
+template <typename T>
+void launch_guess(const Geom&, T* bx, T* by, const T* bx1, const T* by1, const T* bx2,
+                  const T* by2, DevCounters*, hipStream_t);
+void launch_slice_end(DevCounters*, int32_t* iters_out, double* resid_out, double tol,
+                      int max_iter, hipStream_t);
+
+// copy a stored [ny][nx] grid into an [ny+1][nx+1] node array
+struct OutCopy {
+  const void* src[kMaxOut];
+  void* dst[kMaxOut];
+  int is_double[kMaxOut];   // source precision (the destination matches it)
+  int add_beam[kMaxOut];    // add -n_b (Jz, rho outputs of a Gaussian beam)
+  int add_ion[kMaxOut];     // add +n0 (rho-Jz, rho outputs)
+  int kind[kMaxOut];        // 0 full plane, 1 row ny/2, 2 axis node
+  int count;
+  double beam_amp, n0;
+  const double* bgx;
+  const double* bgy;
+};
+void launch_out_copy(const Geom&, const OutCopy&, hipStream_t);
+
+template <typename S, typename T>
+void launch_from_nodes(const Geom&, const S* src, T* dst, hipStream_t);  // [ny+1][nx+1] -> stored
+template <typename T>
+void launch_to_nodes(const Geom&, const T* src, double* dst, hipStream_t);    // stored -> [ny+1][nx+1]
+template <typename T>
+void launch_to_nodes_t(const Geom&, const T* src, T* dst, hipStream_t);
+
+}  // namespace qsp

@@ -1,0 +1,710 @@
+// Host runtime of libqsp: buffers, tables and the per-slice schedule of the
+// quasi-static PIC loop (HiPACE++, arXiv:2109.10277, Sec. II slice routine
+// with the Sec. III.B predictor-corrector for Bx/By).
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+namespace qsp {
+
+namespace {
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2i(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+bool finite(double v) { return std::isfinite(v); }
+
+}  // namespace
+
+double default_pc_shift(double n0) { return 0.5 * kAB5[0] * n0; }
+
+std::string validate(const qsp_config& c) {
+  if (!pow2(c.nx) || c.nx < 16 || c.nx > 2048) return "nx must be a power of two in [16, 2048]";
+  if (!pow2(c.ny) || c.ny < 16 || c.ny > 2048) return "ny must be a power of two in [16, 2048]";
+  if (!finite(c.x_lo) || !finite(c.x_hi) || !(c.x_hi > c.x_lo)) return "need finite x_lo < x_hi";
+  if (!finite(c.y_lo) || !finite(c.y_hi) || !(c.y_hi > c.y_lo)) return "need finite y_lo < y_hi";
+  if (c.nzeta < 1) return "nzeta must be >= 1";
+  if (c.precision != QSP_FP32 && c.precision != QSP_FP64) return "precision must be QSP_FP32 or QSP_FP64";
+  if (!finite(c.zeta_hi)) return "zeta_hi must be finite";
+  if (!finite(c.dzeta) || !(c.dzeta > 0)) return "dzeta must be finite and > 0";
+  if (!(c.ppc_x == 1 || c.ppc_x == 2 || c.ppc_x == 4)) return "ppc_x must be 1, 2 or 4";
+  if (!(c.ppc_y == 1 || c.ppc_y == 2 || c.ppc_y == 4)) return "ppc_y must be 1, 2 or 4";
+  if (!finite(c.n0) || !(c.n0 > 0)) return "n0 must be finite and > 0";
+  if (c.pc_max_iter < 1 || c.pc_max_iter > 1000) return "pc_max_iter must be in [1, 1000]";
+  if (!finite(c.pc_tol)) return "pc_tol must be finite";
+  if (!finite(c.pc_shift)) return "pc_shift must be finite (< 0 selects the default)";
+  if (!finite(c.psi_floor) || !(c.psi_floor > 0) || !(c.psi_floor < 1)) return "psi_floor must be in (0, 1)";
+  if (c.mem_cap_bytes < 0) return "mem_cap_bytes must be >= 0";
+  if (c.deposit_mode != 0 && c.deposit_mode != 1) return "deposit_mode must be 0 or 1";
+  return "";
+}
+
+int64_t device_bytes_needed(const qsp_config& c) {
+  const int64_t ts = c.precision == QSP_FP64 ? 8 : 4;
+  const int64_t plane = static_cast<int64_t>(c.nx) * c.ny;
+  const int64_t np = static_cast<int64_t>(c.nx) * c.ppc_x * c.ny * c.ppc_y;
+  int64_t b = 0;
+  b += plane * ts * (5 + 6 + 8);                 // fields, B history, DST scratch
+  b += plane * 8 * (3 * 5 + 2);                  // deposits, trial currents
+  b += np * ts * (6 + 20);                       // particle SoA + history
+  b += (c.nx + c.ny) * (3 * ts + 8 + 8) + 4096;  // tables, counters
+  b += static_cast<int64_t>(c.ny) * 16 + 64;     // residual partials
+  return b;
+}
+
+// HIP-event timers around kernel launches, per kernel class.
+class KernelTimer {
+ public:
+  ~KernelTimer() {
+    for (auto& e : pool_) (void)hipEventDestroy(e);
+    for (auto& p : pending_) {
+      (void)hipEventDestroy(p.a);
+      (void)hipEventDestroy(p.b);
+    }
+  }
+  void reset(int every) {
+    every_ = every;
+    std::fill(std::begin(ms_), std::end(ms_), 0.0);
+    std::fill(std::begin(n_), std::end(n_), 0);
+  }
+  bool active(int k) const { return every_ > 0 && k % every_ == 0; }
+  void begin(int cls, hipStream_t st) {
+    cur_ = {get(), get(), cls};
+    QSP_HIP(hipEventRecord(cur_.a, st));
+  }
+  void end(hipStream_t st) {
+    QSP_HIP(hipEventRecord(cur_.b, st));
+    pending_.push_back(cur_);
+  }
+  // synchronises on the recorded events and folds them into the totals
+  void collect() {
+    for (auto& p : pending_) {
+      QSP_HIP(hipEventSynchronize(p.b));
+      float ms = 0.f;
+      QSP_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+      ms_[p.cls] += ms;
+      n_[p.cls] += 1;
+      pool_.push_back(p.a);
+      pool_.push_back(p.b);
+    }
+    pending_.clear();
+  }
+  void read(qsp_kernel_times* out) {
+    collect();
+    for (int c = 0; c < QSP_NK; ++c) {
+      out->ms[c] = ms_[c];
+      out->launches[c] = n_[c];
+    }
+  }
+
+ private:
+  struct Pair {
+    hipEvent_t a, b;
+    int cls;
+  };
+  hipEvent_t get() {
+    if (pool_.empty()) {
+      hipEvent_t e;
+      QSP_HIP(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = pool_.back();
+    pool_.pop_back();
+    return e;
+  }
+  int every_ = 0;
+  double ms_[QSP_NK] = {};
+  int64_t n_[QSP_NK] = {};
+  Pair cur_{};
+  std::vector<Pair> pending_;
+  std::vector<hipEvent_t> pool_;
+};
+
+template <typename T>
+class Box final : public BoxBase {
+ public:
+  Box(const qsp_config& cfg, int device, hipStream_t st) : st_(st), device_(device) {
+    cfg_ = cfg;
+    geom_.nx = cfg.nx;
+    geom_.ny = cfg.ny;
+    geom_.lx = ilog2i(cfg.nx);
+    geom_.ly = ilog2i(cfg.ny);
+    geom_.x_lo = cfg.x_lo;
+    geom_.y_lo = cfg.y_lo;
+    geom_.hx = (cfg.x_hi - cfg.x_lo) / cfg.nx;
+    geom_.hy = (cfg.y_hi - cfg.y_lo) / cfg.ny;
+    lat_.ppc_x = cfg.ppc_x;
+    lat_.ppc_y = cfg.ppc_y;
+    lat_.nX = cfg.nx * cfg.ppc_x;
+    lat_.nY = cfg.ny * cfg.ppc_y;
+    lat_.np = static_cast<int64_t>(lat_.nX) * lat_.nY;
+    shift_ = cfg.pc_shift < 0 ? default_pc_shift(cfg.n0) : cfg.pc_shift;
+    tiled_ = cfg.deposit_mode == 0;
+    tile_rows_ = default_tile_rows();
+    QSP_HIP(hipSetDevice(device_));
+    try {
+      allocate();
+      build_tables();
+      QSP_HIP(hipEventCreate(&ev0_));
+      QSP_HIP(hipEventCreate(&ev1_));
+    } catch (...) {
+      release();
+      throw;
+    }
+  }
+
+  ~Box() override { release(); }
+
+  void set_deposit_tiled(bool on) override { tiled_ = on; }
+  void set_timing(int every) override {
+    timer_.collect();
+    timer_.reset(every);
+  }
+  void get_kernel_times(qsp_kernel_times* out) override { timer_.read(out); }
+
+  // ---------------------------------------------------------------- state
+  void init_plasma() override {
+    QSP_HIP(hipSetDevice(device_));
+    launch_init_plasma<T>(lat_, p_, cfg_.n0 / (cfg_.ppc_x * cfg_.ppc_y), st_);
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 2; ++c) launch_zero_t<T>(b_[b][c], plane(), st_);
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < 5; ++c) launch_zero(dep_[d][c], plane(), st_);
+    launch_zero(trial_[0], plane(), st_);
+    launch_zero(trial_[1], plane(), st_);
+    launch_zero_t<T>(t1_, 4 * plane(), st_);
+    launch_zero_t<T>(t2_, 4 * plane(), st_);
+    static_assert(sizeof(DevCounters) % sizeof(double) == 0, "counter block size");
+    launch_zero_t<double>(reinterpret_cast<double*>(ctr_), sizeof(DevCounters) / sizeof(double),
+                          st_);
+    cursor_ = 0;
+    dep_valid_ = false;
+    initialised_ = true;
+    slices_done_ = 0;
+    dst_solves_ = 0;
+    pushes_ = 0;
+  }
+
+  void set_beam_gaussian(const double* amp, double sx, double sy, double x0,
+                         double y0) override {
+    amp_.assign(amp, amp + cfg_.nzeta);
+    std::vector<double> gx(cfg_.nx + 1, 0.0), gy(cfg_.ny + 1, 0.0);
+    for (int i = 1; i < cfg_.nx; ++i) {
+      const double x = cfg_.x_lo + i * geom_.hx - x0;
+      gx[i] = std::exp(-x * x / (2.0 * sx * sx));
+    }
+    for (int j = 1; j < cfg_.ny; ++j) {
+      const double y = cfg_.y_lo + j * geom_.hy - y0;
+      gy[j] = std::exp(-y * y / (2.0 * sy * sy));
+    }
+    QSP_HIP(hipMemcpyAsync(bgx_, gx.data(), gx.size() * sizeof(double), hipMemcpyHostToDevice, st_));
+    QSP_HIP(hipMemcpyAsync(bgy_, gy.data(), gy.size() * sizeof(double), hipMemcpyHostToDevice, st_));
+    QSP_HIP(hipStreamSynchronize(st_));
+    has_gauss_ = true;
+  }
+
+  void get_stats(qsp_stats* s) override {
+    DevCounters c{};
+    QSP_HIP(hipMemcpyAsync(&c, ctr_, sizeof(c), hipMemcpyDeviceToHost, st_));
+    QSP_HIP(hipStreamSynchronize(st_));
+    std::memset(s, 0, sizeof(*s));
+    s->slices = slices_done_;
+    s->particle_pushes = pushes_;
+    s->pc_iterations = static_cast<int64_t>(c.pc_iterations);
+    s->pc_not_converged = static_cast<int64_t>(c.pc_not_converged);
+    s->n_clamped = static_cast<int64_t>(c.n_clamped);
+    s->n_absorbed = static_cast<int64_t>(c.n_absorbed);
+    s->n_deposit_global = static_cast<int64_t>(c.n_dep_global);
+    s->dst_solves = dst_solves_ + 2 * static_cast<int64_t>(c.pc_iterations);
+    s->max_pc_residual = c.max_resid;
+    s->elapsed_ms = last_ms_;
+    s->device_bytes = bytes_;
+    nonfinite_ = c.nonfinite != 0;
+  }
+
+  bool check_nonfinite() override {
+    DevCounters c{};
+    QSP_HIP(hipMemcpyAsync(&c, ctr_, sizeof(c), hipMemcpyDeviceToHost, st_));
+    QSP_HIP(hipStreamSynchronize(st_));
+    return c.nonfinite != 0;
+  }
+
+  void get_state(qsp_slice_state* d) override {
+    const size_t np = static_cast<size_t>(lat_.np);
+    const size_t nn = nodes();
+    double* tmp = nullptr;
+    const size_t tot = np * 26 + 6 * nn;
+    QSP_HIP(hipMalloc(&tmp, tot * sizeof(double)));
+    try {
+      double* q = tmp;
+      double *x = q, *y = q + np, *ux = q + 2 * np, *uy = q + 3 * np, *ps = q + 4 * np,
+             *w = q + 5 * np, *h = q + 6 * np;
+      double* g = q + 26 * np;
+      launch_export_state<T>(geom_, lat_, p_, x, y, ux, uy, ps, w, h, cursor_, st_);
+      to_nodes_d(dep_[ip_][1], g);
+      to_nodes_d(dep_[ip_][2], g + nn);
+      launch_to_nodes<T>(geom_, b_[i1_][0], g + 2 * nn, st_);
+      launch_to_nodes<T>(geom_, b_[i1_][1], g + 3 * nn, st_);
+      launch_to_nodes<T>(geom_, b_[i2_][0], g + 4 * nn, st_);
+      launch_to_nodes<T>(geom_, b_[i2_][1], g + 5 * nn, st_);
+      auto d2h = [&](double* dst, const double* src, size_t n) {
+        QSP_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, st_));
+      };
+      d2h(d->x, x, np);
+      d2h(d->y, y, np);
+      d2h(d->ux, ux, np);
+      d2h(d->uy, uy, np);
+      d2h(d->psi, ps, np);
+      d2h(d->w, w, np);
+      d2h(d->hist, h, 20 * np);
+      d2h(d->jx_prev, g, nn);
+      d2h(d->jy_prev, g + nn, nn);
+      d2h(d->bx_prev1, g + 2 * nn, nn);
+      d2h(d->by_prev1, g + 3 * nn, nn);
+      d2h(d->bx_prev2, g + 4 * nn, nn);
+      d2h(d->by_prev2, g + 5 * nn, nn);
+      QSP_HIP(hipStreamSynchronize(st_));
+      d->k = cursor_;
+    } catch (...) {
+      (void)hipFree(tmp);
+      throw;
+    }
+    QSP_HIP(hipFree(tmp));
+  }
+
+  void set_state(const qsp_slice_state* s) override {
+    const size_t np = static_cast<size_t>(lat_.np);
+    const size_t nn = nodes();
+    double* tmp = nullptr;
+    const size_t tot = np * 26 + 6 * nn;
+    QSP_HIP(hipMalloc(&tmp, tot * sizeof(double)));
+    try {
+      double* q = tmp;
+      auto h2d = [&](double* dst, const double* src, size_t n) {
+        QSP_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, st_));
+      };
+      h2d(q, s->x, np);
+      h2d(q + np, s->y, np);
+      h2d(q + 2 * np, s->ux, np);
+      h2d(q + 3 * np, s->uy, np);
+      h2d(q + 4 * np, s->psi, np);
+      h2d(q + 5 * np, s->w, np);
+      h2d(q + 6 * np, s->hist, 20 * np);
+      double* g = q + 26 * np;
+      h2d(g, s->jx_prev, nn);
+      h2d(g + nn, s->jy_prev, nn);
+      h2d(g + 2 * nn, s->bx_prev1, nn);
+      h2d(g + 3 * nn, s->by_prev1, nn);
+      h2d(g + 4 * nn, s->bx_prev2, nn);
+      h2d(g + 5 * nn, s->by_prev2, nn);
+      launch_import_state<T>(geom_, lat_, p_, q, q + np, q + 2 * np, q + 3 * np, q + 4 * np,
+                             q + 5 * np, q + 6 * np, s->k, st_);
+      for (int d = 0; d < 3; ++d)
+        for (int c = 0; c < 5; ++c) launch_zero(dep_[d][c], plane(), st_);
+      launch_zero(trial_[0], plane(), st_);
+      launch_zero(trial_[1], plane(), st_);
+      launch_from_nodes<double, double>(geom_, g, dep_[ip_][1], st_);
+      launch_from_nodes<double, double>(geom_, g + nn, dep_[ip_][2], st_);
+      launch_from_nodes<double, T>(geom_, g + 2 * nn, b_[i1_][0], st_);
+      launch_from_nodes<double, T>(geom_, g + 3 * nn, b_[i1_][1], st_);
+      launch_from_nodes<double, T>(geom_, g + 4 * nn, b_[i2_][0], st_);
+      launch_from_nodes<double, T>(geom_, g + 5 * nn, b_[i2_][1], st_);
+      QSP_HIP(hipStreamSynchronize(st_));
+    } catch (...) {
+      (void)hipFree(tmp);
+      throw;
+    }
+    QSP_HIP(hipFree(tmp));
+    cursor_ = s->k;
+    dep_valid_ = false;
+    initialised_ = true;
+  }
+
+  void solve_poisson(int nb, const void* src, void* dst, double shift) override {
+    QSP_HIP(hipSetDevice(device_));
+    const size_t pl = plane(), nn = nodes();
+    const T* s = static_cast<const T*>(src);
+    T* d = static_cast<T*>(dst);
+    for (int b = 0; b < nb; ++b) launch_from_nodes<T, T>(geom_, s + b * nn, t2_ + b * pl, st_);
+    RowInvArgs<T> r{};
+    for (int b = 0; b < nb; ++b) {
+      r.in[b] = t2_ + b * pl;
+      r.out[b] = t1_ + b * pl;
+    }
+    launch_row_inv<T>(geom_, r, nb, tx(), st_);
+    ColArgs<T> c{};
+    c.in = t1_;
+    c.out = t2_;
+    for (int b = 0; b < 4; ++b) c.shift[b] = shift;
+    c.w = col_width<T>(geom_, nb);
+    launch_col_solve<T>(geom_, c, nb, ty(), lamx_, ctr_, st_);
+    for (int b = 0; b < nb; ++b) {
+      r.in[b] = t2_ + b * pl;
+      r.out[b] = t1_ + b * pl;
+    }
+    launch_row_inv<T>(geom_, r, nb, tx(), st_);
+    for (int b = 0; b < nb; ++b) launch_to_nodes_t<T>(geom_, t1_ + b * pl, d + b * nn, st_);
+  }
+
+  // ---------------------------------------------------------------- loop
+  void advance_slice(const qsp_slice_out* out) override {
+    QSP_HIP(hipSetDevice(device_));
+    OutCopy oc{};
+    if (out) {
+      for (int q = 0; q < QSP_NQ; ++q)
+        if (out->q[q]) add_out(oc, q, out->q[q], 0);
+    }
+    step(oc, nullptr, nullptr);
+  }
+
+  void run_box(const qsp_box_out* out) override {
+    QSP_HIP(hipSetDevice(device_));
+    const int k0 = cursor_;
+    const int every = (out && out->stack_every > 0) ? out->stack_every : 1;
+    QSP_HIP(hipEventRecord(ev0_, st_));
+    while (cursor_ < cfg_.nzeta) {
+      const int rel = cursor_ - k0;
+      OutCopy oc{};
+      if (out) {
+        const size_t nn = nodes();
+        for (int q = 0; q < QSP_NQ; ++q) {
+          const size_t es = elem_size(q);
+          if (out->stack[q] && rel % every == 0)
+            add_out(oc, q, static_cast<char*>(out->stack[q]) + (rel / every) * nn * es, 0);
+          if (out->lineout[q])
+            add_out(oc, q, static_cast<char*>(out->lineout[q]) + rel * (cfg_.nx + 1) * es, 1);
+          if (out->axis[q]) add_out(oc, q, static_cast<char*>(out->axis[q]) + rel * es, 2);
+        }
+      }
+      step(oc, out && out->pc_iters ? out->pc_iters + rel : nullptr,
+           out && out->pc_resid ? out->pc_resid + rel : nullptr);
+    }
+    QSP_HIP(hipEventRecord(ev1_, st_));
+    QSP_HIP(hipEventSynchronize(ev1_));
+    float ms = 0.f;
+    QSP_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+    last_ms_ = ms;
+  }
+
+ private:
+  size_t plane() const { return static_cast<size_t>(cfg_.nx) * cfg_.ny; }
+
+  // Lattice rows per push workgroup (64 sites wide): as many rows as keep
+  // >= 1024 workgroups per launch, between 4 and 16.
+  int default_tile_rows() const {
+    const int tx = lat_.nX < 64 ? lat_.nX : 64;
+    int r = 16;
+    while (r > 4 && r * tx > kBlock && lat_.np / (static_cast<int64_t>(tx) * r) < 1024) r >>= 1;
+    if (const char* e = std::getenv("QSP_TILE_ROWS")) {   // tuning override
+      const int v = std::atoi(e);
+      if (v >= 1 && v <= 16 && (v & (v - 1)) == 0 && v * tx >= kBlock) r = v;
+    }
+    return r < lat_.nY ? r : lat_.nY;
+  }
+  size_t nodes() const { return static_cast<size_t>(cfg_.nx + 1) * (cfg_.ny + 1); }
+  size_t elem_size(int q) const { return q < QSP_RHO_MJZ ? sizeof(T) : sizeof(double); }
+
+  template <typename U>
+  U* alloc(size_t n) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(n * sizeof(U), 256);
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory) throw std::bad_alloc();
+    QSP_HIP(e);
+    allocs_.push_back(p);
+    bytes_ += static_cast<int64_t>(bytes);
+    return static_cast<U*>(p);
+  }
+
+  void release() {
+    (void)hipStreamSynchronize(st_);
+    for (void* p : allocs_) (void)hipFree(p);
+    allocs_.clear();
+    if (ev0_) (void)hipEventDestroy(ev0_);
+    if (ev1_) (void)hipEventDestroy(ev1_);
+    ev0_ = ev1_ = nullptr;
+  }
+
+  void allocate() {
+    const size_t pl = plane();
+    psi_ = alloc<T>(pl);
+    exmby_ = alloc<T>(pl);
+    eypbx_ = alloc<T>(pl);
+    ez_ = alloc<T>(pl);
+    bz_ = alloc<T>(pl);
+    for (int b = 0; b < 3; ++b)
+      for (int c = 0; c < 2; ++c) b_[b][c] = alloc<T>(pl);
+    t1_ = alloc<T>(4 * pl);
+    t2_ = alloc<T>(4 * pl);
+    for (int d = 0; d < 3; ++d)
+      for (int c = 0; c < 5; ++c) dep_[d][c] = alloc<double>(pl);
+    trial_[0] = alloc<double>(pl);
+    trial_[1] = alloc<double>(pl);
+    const size_t np = static_cast<size_t>(lat_.np);
+    p_.xi_x = alloc<T>(np);
+    p_.xi_y = alloc<T>(np);
+    p_.ux = alloc<T>(np);
+    p_.uy = alloc<T>(np);
+    p_.psi = alloc<T>(np);
+    p_.w = alloc<T>(np);
+    p_.hist = alloc<T>(20 * np);
+    twx_ = alloc<Cplx<T>>(cfg_.nx);
+    prex_ = alloc<T>(cfg_.nx);
+    lamx_ = alloc<double>(cfg_.nx);
+    twy_ = alloc<Cplx<T>>(cfg_.ny);
+    prey_ = alloc<T>(cfg_.ny);
+    lamy_ = alloc<double>(cfg_.ny);
+    bgx_ = alloc<double>(cfg_.nx + 1);
+    bgy_ = alloc<double>(cfg_.ny + 1);
+    ctr_ = alloc<DevCounters>(1);
+    partial_ = alloc<double>(2 * static_cast<size_t>(pc_partial_count(geom_)) + 2);
+    if (cfg_.mem_cap_bytes > 0 && bytes_ > cfg_.mem_cap_bytes) throw std::bad_alloc();
+  }
+
+  void axis_tables(int n, double h, Cplx<T>* tw, T* pre, double* lam) {
+    std::vector<Cplx<T>> htw(n);
+    std::vector<T> hpre(n);
+    std::vector<double> hlam(n);
+    const double pi = 3.14159265358979323846;
+    for (int m = 0; m < n; ++m) {
+      htw[m].re = static_cast<T>(std::cos(-2.0 * pi * m / n));
+      htw[m].im = static_cast<T>(std::sin(-2.0 * pi * m / n));
+      hpre[m] = static_cast<T>(std::sin(pi * m / n));
+      const double s = std::sin(pi * m / (2.0 * n));
+      hlam[m] = -4.0 / (h * h) * s * s;
+    }
+    QSP_HIP(hipMemcpy(tw, htw.data(), n * sizeof(Cplx<T>), hipMemcpyHostToDevice));
+    QSP_HIP(hipMemcpy(pre, hpre.data(), n * sizeof(T), hipMemcpyHostToDevice));
+    QSP_HIP(hipMemcpy(lam, hlam.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  }
+
+  void build_tables() {
+    axis_tables(cfg_.nx, geom_.hx, twx_, prex_, lamx_);
+    axis_tables(cfg_.ny, geom_.hy, twy_, prey_, lamy_);
+    std::vector<double> z(std::max(cfg_.nx, cfg_.ny) + 1, 0.0);
+    QSP_HIP(hipMemcpy(bgx_, z.data(), (cfg_.nx + 1) * sizeof(double), hipMemcpyHostToDevice));
+    QSP_HIP(hipMemcpy(bgy_, z.data(), (cfg_.ny + 1) * sizeof(double), hipMemcpyHostToDevice));
+    QSP_HIP(hipMemset(ctr_, 0, sizeof(DevCounters)));
+    QSP_HIP(hipDeviceSynchronize());
+  }
+
+  AxisTables<T> tx() const { return {twx_, prex_, lamx_}; }
+  AxisTables<T> ty() const { return {twy_, prey_, lamy_}; }
+
+  void to_nodes_d(const double* src, double* dst) { launch_to_nodes<double>(geom_, src, dst, st_); }
+
+  void add_out(OutCopy& oc, int q, void* dst, int kind) {
+    if (oc.count >= kMaxOut) throw std::runtime_error("too many outputs");
+    const int i = oc.count++;
+    oc.dst[i] = dst;
+    oc.kind[i] = kind;
+    oc.is_double[i] = (q >= QSP_RHO_MJZ) || sizeof(T) == 8;
+    oc.add_beam[i] = 0;
+    oc.add_ion[i] = 0;
+    double* const* dc = dep_[ic_];
+    switch (q) {
+      case QSP_PSI: oc.src[i] = psi_; break;
+      case QSP_EXMBY: oc.src[i] = exmby_; break;
+      case QSP_EYPBX: oc.src[i] = eypbx_; break;
+      case QSP_EZ: oc.src[i] = ez_; break;
+      case QSP_BX: oc.src[i] = b_[ik_][0]; break;
+      case QSP_BY: oc.src[i] = b_[ik_][1]; break;
+      case QSP_BZ: oc.src[i] = bz_; break;
+      case QSP_RHO_MJZ: oc.src[i] = dc[0]; oc.add_ion[i] = 1; break;
+      case QSP_JX: oc.src[i] = dc[1]; break;
+      case QSP_JY: oc.src[i] = dc[2]; break;
+      case QSP_JZ: oc.src[i] = dc[3]; oc.add_beam[i] = 1; break;
+      case QSP_RHO: oc.src[i] = dc[4]; oc.add_beam[i] = 1; oc.add_ion[i] = 1; break;
+      default: throw std::runtime_error("bad output id");
+    }
+  }
+
+  SliceFields<T> fields(const T* bx, const T* by) const {
+    return {exmby_, eypbx_, ez_, bx, by, bz_};
+  }
+
+  // one slice: the 2D slice routine followed by the real push to k+1
+  void step(OutCopy& oc, int32_t* iters_out, double* resid_out) {
+    const int k = cursor_;
+    const double amp = has_gauss_ ? amp_[k] : 0.0;
+    double* const* dp = dep_[ip_];
+    double* const* dc = dep_[ic_];
+    double* const* dn = dep_[in_];
+    const size_t pl = plane();
+    if (!dep_valid_) {
+      timed(QSP_K_OTHER, [&] {
+        for (int c = 0; c < 5; ++c) launch_zero(dc[c], pl, st_);
+      });
+      PushArgs<T> a = push_args(fields(b_[ik_][0], b_[ik_][1]), dc, k);
+      timed(QSP_K_OTHER, [&] { launch_push<T>(geom_, lat_, a, kDepositOnly, true, ctr_, st_); });
+      dep_valid_ = true;
+    }
+    T* bxk = b_[ik_][0];
+    T* byk = b_[ik_][1];
+    // psi, Ez, Bz (Sec. II steps 4-6)
+    {
+      SrcPEZ<T> s{dc[0], dc[1], dc[2], cfg_.n0, t1_};
+      timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_pez<T>(geom_, s, tx(), st_); });
+      ColArgs<T> c{};
+      c.in = t1_;
+      c.out = t2_;
+      c.out_dy = t2_ + 3 * pl;
+      c.shift[0] = c.shift[1] = c.shift[2] = 0.0;
+      c.honor_done = 0;
+      c.w = col_width<T>(geom_, 3);
+      // the deposit planes of slice k+1 are free: clear them for the real push
+      for (int q = 0; q < 5; ++q) c.zero.p[q] = dn[q];
+      c.zero.count = 5;
+      c.zero.n = pl;
+      timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 3, ty(), lamx_, ctr_, st_); });
+      RowInvArgs<T> r{};
+      r.in[0] = t2_;
+      r.out[0] = psi_;
+      r.out_dx[0] = exmby_;
+      r.in[1] = t2_ + 3 * pl;
+      r.out[1] = eypbx_;
+      r.in[2] = t2_ + pl;
+      r.out[2] = ez_;
+      r.in[3] = t2_ + 2 * pl;
+      r.out[3] = bz_;
+      // Bx/By initial guess of the predictor-corrector rides along
+      r.guess = {bxk, byk, b_[i1_][0], b_[i1_][1], b_[i2_][0], b_[i2_][1], ctr_};
+      timed(QSP_K_ROW_INV, [&] { launch_row_inv<T>(geom_, r, 4, tx(), st_); });
+      dst_solves_ += 3;
+    }
+    // Bx/By predictor-corrector (Sec. II step 7, Sec. III.B)
+    for (int m = 0; m < cfg_.pc_max_iter; ++m) {
+      PushArgs<T> a = push_args(fields(bxk, byk), trial_, k);
+      timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, false, ctr_, st_); });
+      SrcBxBy<T> s{};
+      s.jz = dc[3];
+      s.jx_prev = dp[1];
+      s.jy_prev = dp[2];
+      s.jx_next = trial_[0];
+      s.jy_next = trial_[1];
+      s.bx = bxk;
+      s.by = byk;
+      s.shift = shift_;
+      s.dzeta = cfg_.dzeta;
+      s.beam_amp = amp;
+      s.bgx = bgx_;
+      s.bgy = bgy_;
+      s.out = t1_;
+      timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_bxby<T>(geom_, s, tx(), ctr_, st_); });
+      ColArgs<T> c{};
+      c.in = t1_;
+      c.out = t2_;
+      c.out_dy = nullptr;
+      c.shift[0] = c.shift[1] = shift_;
+      c.honor_done = 1;
+      c.w = col_width<T>(geom_, 2);
+      // the trial currents have been read: clear them for the next trial
+      c.zero.p[0] = trial_[0];
+      c.zero.p[1] = trial_[1];
+      c.zero.count = 2;
+      c.zero.n = pl;
+      timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
+      PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol};
+      timed(QSP_K_ROW_INV, [&] { launch_row_inv_pc<T>(geom_, pc, tx(), ctr_, st_); });
+    }
+    // outputs of slice k
+    oc.beam_amp = amp;
+    oc.n0 = cfg_.n0;
+    oc.bgx = bgx_;
+    oc.bgy = bgy_;
+    if (oc.count) timed(QSP_K_OTHER, [&] { launch_out_copy(geom_, oc, st_); });
+    // real push to slice k+1 with deposit there (Sec. II step 1 of the next
+    // slice); it also closes the predictor-corrector bookkeeping of slice k
+    if (k + 1 < cfg_.nzeta) {
+      PushArgs<T> a = push_args(fields(bxk, byk), dn, k);
+      a.iters_out = iters_out;
+      a.resid_out = resid_out;
+      timed(QSP_K_PUSH, [&] { launch_push<T>(geom_, lat_, a, kPushReal, true, ctr_, st_); });
+      pushes_ += lat_.np;
+    } else {
+      timed(QSP_K_OTHER, [&] {
+        launch_slice_end(ctr_, iters_out, resid_out, cfg_.pc_tol, cfg_.pc_max_iter, st_);
+      });
+    }
+    // hand-off: J_perp of k becomes the previous slice's, B rotates
+    const int old_p = ip_;
+    ip_ = ic_;
+    ic_ = in_;
+    in_ = old_p;
+    const int old2 = i2_;
+    i2_ = i1_;
+    i1_ = ik_;
+    ik_ = old2;
+    ++cursor_;
+    ++slices_done_;
+  }
+
+  PushArgs<T> push_args(const SliceFields<T>& f, double* const* ch, int k) {
+    PushArgs<T> a{};
+    a.p = p_;
+    a.f = f;
+    for (int c = 0; c < 5; ++c) a.dep.ch[c] = ch[c];
+    a.k = k;
+    a.dzeta = cfg_.dzeta;
+    a.hx = geom_.hx;
+    a.hy = geom_.hy;
+    a.psi_floor = cfg_.psi_floor;
+    a.tiled = tiled_ ? 1 : 0;
+    a.tile_rows = tile_rows_;
+    a.pc_tol = cfg_.pc_tol;
+    a.pc_max_iter = cfg_.pc_max_iter;
+    return a;
+  }
+
+  // brackets one launch with timer events when slice k is sampled
+  template <typename F>
+  void timed(int cls, F&& launch) {
+    const bool on = timer_.active(cursor_);
+    if (on) timer_.begin(cls, st_);
+    launch();
+    if (on) timer_.end(st_);
+  }
+
+  hipStream_t st_;
+  int device_;
+  KernelTimer timer_;
+  std::vector<void*> allocs_;
+  int64_t bytes_ = 0;
+  T *psi_ = nullptr, *exmby_ = nullptr, *eypbx_ = nullptr, *ez_ = nullptr, *bz_ = nullptr;
+  T* b_[3][2] = {};
+  T *t1_ = nullptr, *t2_ = nullptr;
+  double* dep_[3][5] = {};
+  double* trial_[2] = {};
+  Particles<T> p_{};
+  Cplx<T>* twx_ = nullptr;
+  Cplx<T>* twy_ = nullptr;
+  T *prex_ = nullptr, *prey_ = nullptr;
+  double *lamx_ = nullptr, *lamy_ = nullptr, *bgx_ = nullptr, *bgy_ = nullptr;
+  DevCounters* ctr_ = nullptr;
+  double* partial_ = nullptr;
+  std::vector<double> amp_;
+  bool has_gauss_ = false;
+  double shift_ = 0.0;
+  int ip_ = 0, ic_ = 1, in_ = 2;   // deposit buffers of slices k-1, k, k+1
+  int ik_ = 0, i1_ = 1, i2_ = 2;   // B buffers of slices k, k-1, k-2
+  bool dep_valid_ = false;
+  bool tiled_ = true;
+  int tile_rows_ = 16;
+  bool nonfinite_ = false;
+  hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+  double last_ms_ = 0.0;
+  int64_t slices_done_ = 0, dst_solves_ = 0, pushes_ = 0;
+};
+
+std::unique_ptr<BoxBase> make_box(const qsp_config& cfg, int device, hipStream_t stream) {
+  if (cfg.precision == QSP_FP64) return std::make_unique<Box<double>>(cfg, device, stream);
+  return std::make_unique<Box<float>>(cfg, device, stream);
+}
+
+}  // namespace qsp

@@ -1,0 +1,57 @@
+// Host runtime of libqsp: one simulation box on one GPU.
+#pragma once
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/qsp.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace qsp {
+
+// Host-side check of a configuration; returns an empty string when valid.
+std::string validate(const qsp_config& c);
+
+// Default screening shift of the predictor-corrector iteration: the linear
+// response of the centred d_zeta J_perp term to a change of Bx/By through one
+// trial Adams-Bashforth step, (AB5_0 / 2) * n0.
+double default_pc_shift(double n0);
+
+class BoxBase {
+ public:
+  virtual ~BoxBase() = default;
+  virtual void init_plasma() = 0;
+  virtual void set_beam_gaussian(const double* amp, double sx, double sy, double x0,
+                                 double y0) = 0;
+  virtual void advance_slice(const qsp_slice_out* out) = 0;
+  virtual void run_box(const qsp_box_out* out) = 0;
+  virtual void get_stats(qsp_stats* s) = 0;
+  virtual void get_state(qsp_slice_state* dst) = 0;
+  virtual void set_state(const qsp_slice_state* src) = 0;
+  virtual void set_deposit_tiled(bool on) = 0;
+  virtual void solve_poisson(int nbatch, const void* src, void* dst, double shift) = 0;
+  virtual void set_timing(int every) = 0;
+  virtual void get_kernel_times(qsp_kernel_times* out) = 0;
+  // synchronises; true if a non-finite residual or norm was met
+  virtual bool check_nonfinite() = 0;
+  int cursor() const { return cursor_; }
+  bool initialised() const { return initialised_; }
+  int64_t n_particles() const { return lat_.np; }
+  const qsp_config& config() const { return cfg_; }
+
+ protected:
+  qsp_config cfg_{};
+  Geom geom_{};
+  Lattice lat_{};
+  int cursor_ = 0;
+  bool initialised_ = false;
+};
+
+std::unique_ptr<BoxBase> make_box(const qsp_config& cfg, int device, hipStream_t stream);
+
+// bytes a context of this configuration will hold on the device
+int64_t device_bytes_needed(const qsp_config& cfg);
+
+}  // namespace qsp

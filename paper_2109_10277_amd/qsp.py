@@ -1,0 +1,342 @@
+"""ctypes binding of libqsp (include/qsp.h).
+
+Argument marshalling only: every step of the slice loop runs in the HIP
+kernels of libqsp.so.  PyTorch supplies device memory (tensors whose
+``data_ptr()`` is passed across the C ABI) and the HIP stream.  The library
+must have been built (``paper_2109_10277_amd/build.py``); loading fails
+loudly otherwise - there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqsp.so")
+
+QSP_OK, QSP_ERR_INVALID_ARG, QSP_ERR_BAD_STATE, QSP_ERR_OUT_OF_MEMORY, \
+    QSP_ERR_DEVICE, QSP_ERR_NONFINITE = range(6)
+QSP_FP32, QSP_FP64 = 0, 1
+
+QUANTITIES = ("psi", "exmby", "eypbx", "ez", "bx", "by", "bz",
+              "rho_mjz", "jx", "jy", "jz", "rho")
+QID = {q: i for i, q in enumerate(QUANTITIES)}
+NQ = len(QUANTITIES)
+FIELD_QUANTITIES = QUANTITIES[:7]
+
+
+class QspError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_status_name(status)}: {msg}")
+        self.status = status
+
+
+def _status_name(s: int) -> str:
+    return {0: "QSP_OK", 1: "QSP_ERR_INVALID_ARG", 2: "QSP_ERR_BAD_STATE",
+            3: "QSP_ERR_OUT_OF_MEMORY", 4: "QSP_ERR_DEVICE",
+            5: "QSP_ERR_NONFINITE"}.get(s, f"status {s}")
+
+
+class Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
+                ("x_lo", C.c_double), ("x_hi", C.c_double),
+                ("y_lo", C.c_double), ("y_hi", C.c_double),
+                ("nzeta", C.c_int32), ("precision", C.c_int32),
+                ("zeta_hi", C.c_double), ("dzeta", C.c_double),
+                ("ppc_x", C.c_int32), ("ppc_y", C.c_int32),
+                ("n0", C.c_double),
+                ("pc_max_iter", C.c_int32), ("deposit_mode", C.c_int32),
+                ("pc_tol", C.c_double), ("pc_shift", C.c_double),
+                ("psi_floor", C.c_double), ("mem_cap_bytes", C.c_int64)]
+
+
+class SliceOut(C.Structure):
+    _fields_ = [("q", C.c_void_p * NQ)]
+
+
+class BoxOut(C.Structure):
+    _fields_ = [("stack", C.c_void_p * NQ), ("stack_every", C.c_int32),
+                ("reserved0", C.c_int32), ("lineout", C.c_void_p * NQ),
+                ("axis", C.c_void_p * NQ), ("pc_iters", C.c_void_p),
+                ("pc_resid", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("slices", C.c_int64), ("particle_pushes", C.c_int64),
+                ("pc_iterations", C.c_int64), ("pc_not_converged", C.c_int64),
+                ("n_clamped", C.c_int64), ("n_absorbed", C.c_int64),
+                ("n_deposit_global", C.c_int64), ("dst_solves", C.c_int64),
+                ("max_pc_residual", C.c_double), ("elapsed_ms", C.c_double),
+                ("device_bytes", C.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_DP = C.POINTER(C.c_double)
+
+KERNEL_CLASSES = ("push", "trial", "row_fwd", "col", "row_inv", "other")
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("ms", C.c_double * 6), ("launches", C.c_int64 * 6)]
+
+
+class SliceState(C.Structure):
+    _fields_ = [("k", C.c_int32), ("reserved0", C.c_int32), ("np", C.c_int64),
+                ("x", _DP), ("y", _DP), ("ux", _DP), ("uy", _DP), ("psi", _DP),
+                ("w", _DP), ("hist", _DP), ("jx_prev", _DP), ("jy_prev", _DP),
+                ("bx_prev1", _DP), ("by_prev1", _DP), ("bx_prev2", _DP),
+                ("by_prev2", _DP)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load libqsp.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python paper_2109_10277_amd/build.py`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        sig = {
+            "qsp_validate_config": [C.POINTER(Config), C.c_char_p, C.c_size_t],
+            "qsp_create": [C.POINTER(Config), C.c_int, vp, C.POINTER(vp)],
+            "qsp_destroy": [vp],
+            "qsp_init_plasma": [vp],
+            "qsp_set_beam_gaussian": [vp, _DP, d, d, d, d],
+            "qsp_set_beam_particles": [vp, i64, vp, d],
+            "qsp_get_beam_particles": [vp, i64, vp],
+            "qsp_get_beam_count": [vp, C.POINTER(i64)],
+            "qsp_advance_slice": [vp, C.POINTER(SliceOut)],
+            "qsp_run_box": [vp, C.POINTER(BoxOut), C.POINTER(Stats)],
+            "qsp_get_stats": [vp, C.POINTER(Stats)],
+            "qsp_get_slice_state": [vp, C.POINTER(SliceState)],
+            "qsp_set_slice_state": [vp, C.POINTER(SliceState)],
+            "qsp_solve_poisson": [vp, i32, vp, vp, d],
+            "qsp_get_info": [vp, C.POINTER(i64), C.POINTER(i32)],
+            "qsp_set_timing": [vp, i32],
+            "qsp_get_kernel_times": [vp, C.POINTER(KernelTimes)],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = C.c_int
+        L.qsp_status_string.argtypes = [C.c_int]
+        L.qsp_status_string.restype = C.c_char_p
+        L.qsp_last_error.argtypes = [vp]
+        L.qsp_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def make_config(cfg, precision: str = "fp32", deposit_mode: int = 0,
+                mem_cap_bytes: int = 0) -> Config:
+    """Build the C config from any object with the BoxConfig attributes."""
+    c = Config()
+    c.nx, c.ny = cfg.nx, cfg.ny
+    c.x_lo, c.x_hi, c.y_lo, c.y_hi = cfg.x_lo, cfg.x_hi, cfg.y_lo, cfg.y_hi
+    c.nzeta = cfg.nzeta
+    c.precision = {"fp32": QSP_FP32, "fp64": QSP_FP64}[precision]
+    c.zeta_hi, c.dzeta = cfg.zeta_hi, cfg.dzeta
+    c.ppc_x, c.ppc_y = cfg.ppc_x, cfg.ppc_y
+    c.n0 = cfg.n0
+    c.pc_max_iter = cfg.pc_max_iter
+    c.deposit_mode = deposit_mode
+    c.pc_tol = cfg.pc_tol
+    shift = getattr(cfg, "pc_shift", None)
+    c.pc_shift = -1.0 if shift is None else float(shift)
+    c.psi_floor = cfg.psi_floor
+    c.mem_cap_bytes = mem_cap_bytes
+    return c
+
+
+def validate_config(cfg, precision: str = "fp32", **kw) -> tuple[bool, str]:
+    c = make_config(cfg, precision, **kw) if not isinstance(cfg, Config) else cfg
+    buf = C.create_string_buffer(256)
+    st = lib().qsp_validate_config(C.byref(c), buf, 256)
+    return st == QSP_OK, buf.value.decode()
+
+
+def _check(st: int, ctx=None):
+    if st != QSP_OK:
+        msg = lib().qsp_last_error(ctx).decode()
+        raise QspError(st, msg)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class Box:
+    """One simulation box on one GPU (a libqsp context).
+
+    ``cfg`` is any object with the attributes of ``workloads.BoxConfig``.
+    All device tensors passed in must live on this machine's device and be
+    contiguous; fields use the box precision, deposits float64.
+    """
+
+    def __init__(self, cfg, precision: str = "fp32", device: int = 0,
+                 stream=None, deposit_mode: int = 0, mem_cap_bytes: int = 0):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.precision = precision
+        self.device = torch.device("cuda", device)
+        self.fdtype = torch.float32 if precision == "fp32" else torch.float64
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self._c = make_config(cfg, precision, deposit_mode, mem_cap_bytes)
+        h = C.c_void_p()
+        st = lib().qsp_create(C.byref(self._c), device, C.c_void_p(stream.cuda_stream),
+                              C.byref(h))
+        _check(st, None)
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().qsp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- helpers
+    def _call(self, name, *args):
+        _check(getattr(lib(), name)(self._h, *args), self._h)
+
+    def node_shape(self):
+        return (self.cfg.ny + 1, self.cfg.nx + 1)
+
+    def dtype_of(self, q: str):
+        return self.fdtype if QID[q] < 7 else self.torch.float64
+
+    def empty(self, q: str, *lead):
+        return self.torch.zeros(*lead, *self.node_shape(), dtype=self.dtype_of(q),
+                                device=self.device)
+
+    @property
+    def n_particles(self) -> int:
+        n = C.c_int64()
+        k = C.c_int32()
+        self._call("qsp_get_info", C.byref(n), C.byref(k))
+        return n.value
+
+    @property
+    def cursor(self) -> int:
+        n = C.c_int64()
+        k = C.c_int32()
+        self._call("qsp_get_info", C.byref(n), C.byref(k))
+        return k.value
+
+    # -- entry points
+    def init_plasma(self):
+        self._call("qsp_init_plasma")
+
+    def set_beam_gaussian(self, amp, sx, sy, x0=0.0, y0=0.0):
+        a = np.ascontiguousarray(amp, dtype=np.float64)
+        if a.shape != (self.cfg.nzeta,):
+            raise ValueError("amp must have shape [nzeta]")
+        self._call("qsp_set_beam_gaussian", a.ctypes.data_as(_DP), float(sx), float(sy),
+                   float(x0), float(y0))
+
+    def advance_slice(self, outputs: Optional[Dict[str, object]] = None):
+        so = SliceOut()
+        for q, t in (outputs or {}).items():
+            self._check_out(q, t, self.node_shape())
+            so.q[QID[q]] = _ptr(t)
+        self._call("qsp_advance_slice", C.byref(so))
+
+    def run_box(self, stack=None, stack_every: int = 1, lineout=None, axis=None,
+                pc_iters=None, pc_resid=None) -> dict:
+        bo = BoxOut()
+        bo.stack_every = stack_every
+        for q, t in (stack or {}).items():
+            bo.stack[QID[q]] = _ptr(t)
+        for q, t in (lineout or {}).items():
+            bo.lineout[QID[q]] = _ptr(t)
+        for q, t in (axis or {}).items():
+            bo.axis[QID[q]] = _ptr(t)
+        bo.pc_iters = _ptr(pc_iters)
+        bo.pc_resid = _ptr(pc_resid)
+        st = Stats()
+        self._call("qsp_run_box", C.byref(bo), C.byref(st))
+        return st.as_dict()
+
+    def stats(self) -> dict:
+        st = Stats()
+        self._call("qsp_get_stats", C.byref(st))
+        return st.as_dict()
+
+    def set_timing(self, every: int):
+        self._call("qsp_set_timing", int(every))
+
+    def kernel_times(self) -> dict:
+        kt = KernelTimes()
+        self._call("qsp_get_kernel_times", C.byref(kt))
+        return {c: (kt.ms[i], kt.launches[i]) for i, c in enumerate(KERNEL_CLASSES)}
+
+    def solve_poisson(self, src, dst, shift: float = 0.0):
+        nb = src.shape[0]
+        self._call("qsp_solve_poisson", int(nb), C.c_void_p(_ptr(src)),
+                   C.c_void_p(_ptr(dst)), float(shift))
+
+    def _state_struct(self, arrs: dict, k: int) -> SliceState:
+        s = SliceState()
+        s.k = k
+        s.np = arrs["x"].size
+        for name in ("x", "y", "ux", "uy", "psi", "w", "hist", "jx_prev", "jy_prev",
+                     "bx_prev1", "by_prev1", "bx_prev2", "by_prev2"):
+            a = arrs[name]
+            assert a.dtype == np.float64 and a.flags.c_contiguous
+            setattr(s, name, a.ctypes.data_as(_DP))
+        return s
+
+    def get_state(self) -> dict:
+        n = self.n_particles
+        nn = self.node_shape()
+        arrs = {k: np.zeros(n) for k in ("x", "y", "ux", "uy", "psi", "w")}
+        arrs["hist"] = np.zeros((4, 5, n))
+        for k in ("jx_prev", "jy_prev", "bx_prev1", "by_prev1", "bx_prev2", "by_prev2"):
+            arrs[k] = np.zeros(nn)
+        s = self._state_struct(arrs, 0)
+        self._call("qsp_get_slice_state", C.byref(s))
+        arrs["k"] = s.k
+        return arrs
+
+    def set_state(self, k: int, arrs: dict):
+        a = {name: np.ascontiguousarray(v, dtype=np.float64) for name, v in arrs.items()
+             if name != "k"}
+        s = self._state_struct(a, k)
+        self._call("qsp_set_slice_state", C.byref(s))
+
+    def _check_out(self, q, t, shape):
+        if tuple(t.shape[-2:]) != tuple(shape):
+            raise ValueError(f"output {q}: expected trailing shape {shape}")
+        if t.dtype != self.dtype_of(q) or t.device != self.device:
+            raise ValueError(f"output {q}: wrong dtype/device")
+
+
+def status_string(s: int) -> str:
+    return lib().qsp_status_string(s).decode()
