@@ -378,6 +378,51 @@ def particle_beam_source(cfg, b, k: int) -> dict:
                                       (g * (g + uz)))}
 
 
+def beam_push_slice(cfg, b, k: int, flds: dict, dt: float) -> None:
+    """Advance the macro-particles of slice k by one time step dt with the
+    slice-k fields (Sec. III.A: beam gather and push run per slice inside the
+    loop; Sec. III.B: a second-order symplectic integrator).  Reading:
+    drift - kick - drift, the kick a Boris step (electric half kick,
+    magnetic rotation, electric half kick) for an electron (q = -1):
+
+      x_h   = x + dt/2 u_perp/gamma,   zeta_h = zeta + dt/2 (u_z/gamma - 1)
+      E, B gathered (CIC) at x_h from the slice's fields, with
+      E_perp = (Ex-By + By, Ey+Bx - Bx); zero outside the box
+      u-    = u + q dt/2 E;  t = q dt/2 B/gamma(u-);  s = 2t/(1+t.t)
+      u'    = u- + u- x t;   u+ = u- + u' x s;   u_new = u+ + q dt/2 E
+      x_new = x_h + dt/2 u_perp_new/gamma_new,  zeta likewise.
+
+    The particle keeps its slice for the gather.  Mutates ``b`` in place."""
+    sel = np.nonzero(beam_slice_index(cfg, b.zeta) == k)[0]
+    if sel.size == 0:
+        return
+    x, y, z = b.x[sel].astype(np.float64), b.y[sel].astype(np.float64), b.zeta[sel].astype(np.float64)
+    u = np.stack([b.ux[sel], b.uy[sel], b.uz[sel]]).astype(np.float64)
+    g0 = np.sqrt(1.0 + np.sum(u * u, axis=0))
+    xh = x + 0.5 * dt * u[0] / g0
+    yh = y + 0.5 * dt * u[1] / g0
+    zh = z + 0.5 * dt * (u[2] / g0 - 1.0)
+    inside = (xh >= cfg.x_lo) & (xh <= cfg.x_hi) & (yh >= cfg.y_lo) & (yh <= cfg.y_hi)
+    xs, ys = np.clip(xh, cfg.x_lo, cfg.x_hi), np.clip(yh, cfg.y_lo, cfg.y_hi)
+    gat = {k2: np.where(inside, gather(cfg, flds[k2], xs, ys), 0.0)
+           for k2 in ("exmby", "eypbx", "ez", "bx", "by", "bz")}
+    E = np.stack([gat["exmby"] + gat["by"], gat["eypbx"] - gat["bx"], gat["ez"]])
+    B = np.stack([gat["bx"], gat["by"], gat["bz"]])
+    q = -1.0
+    um = u + 0.5 * q * dt * E
+    gm = np.sqrt(1.0 + np.sum(um * um, axis=0))
+    t = 0.5 * q * dt * B / gm
+    sv = 2.0 * t / (1.0 + np.sum(t * t, axis=0))
+    up = um + np.cross(um, t, axis=0)
+    upl = um + np.cross(up, sv, axis=0)
+    un = upl + 0.5 * q * dt * E
+    g1 = np.sqrt(1.0 + np.sum(un * un, axis=0))
+    b.x[sel] = xh + 0.5 * dt * un[0] / g1
+    b.y[sel] = yh + 0.5 * dt * un[1] / g1
+    b.zeta[sel] = zh + 0.5 * dt * (un[2] / g1 - 1.0)
+    b.ux[sel], b.uy[sel], b.uz[sel] = un
+
+
 def beam_source(cfg, beam, k: int) -> dict:
     if beam is None:
         return {}
@@ -462,12 +507,16 @@ def predictor_corrector(cfg, st: SliceState, flds: dict, dep: dict):
 def advance_slice(cfg, st: SliceState, beam):
     """Compute the fields of slice st.k and push the plasma to slice k+1
     (the 2D slice routine of Sec. II, with the predictor-corrector as
-    step 7).  Returns (state at k+1, record of slice k)."""
+    step 7).  A macro-particle beam with a non-zero ``dt`` also has its
+    slice-k particles pushed by one time step once the slice's fields are
+    final (mutating the beam).  Returns (state at k+1, record of slice k)."""
     k = st.k
     dep = total_deposit(cfg, st.plasma, beam, k)
     flds = solve_psi_ez_bz(cfg, dep)
     bx, by, its, res, nclamp_pc = predictor_corrector(cfg, st, flds, dep)
     flds["bx"], flds["by"] = bx, by
+    if beam is not None and hasattr(beam, "zeta") and getattr(beam, "dt", 0.0):
+        beam_push_slice(cfg, beam, k, flds, beam.dt)
     new_plasma, nclamp, nabs = ab5_push(cfg, st.plasma, flds, commit=True)
     rec = dict(flds)
     rec.update(dep)

@@ -97,6 +97,7 @@ class ParticleBeam:
     uy: np.ndarray
     uz: np.ndarray
     w: np.ndarray            # number of physical electrons (units n0 k_p^-3)
+    dt: float = 0.0          # time step of the per-slice beam push (0: no push)
 
     def soa(self) -> np.ndarray:
         return np.stack([self.x, self.y, self.zeta, self.ux, self.uy,
@@ -160,6 +161,12 @@ def gaussian_particle_beam(n: int, peak: float, sigma_r: float,
                         uz=np.full(n, uz), w=np.full(n, total / n))
 
 
+def copy_beam(b: ParticleBeam) -> ParticleBeam:
+    return ParticleBeam(*(np.array(getattr(b, f.name), copy=True)
+                          if isinstance(getattr(b, f.name), np.ndarray) else getattr(b, f.name)
+                          for f in dataclasses.fields(ParticleBeam)))
+
+
 def c3(n: int = 1024, nzeta: int = 1024, n_per_beam: int = 2 ** 21,
        seed: int = SEED) -> tuple[BoxConfig, ParticleBeam]:
     """Paper-scale step: 1024^2 x 1024, 1 ppc, driver + witness beams of
@@ -173,7 +180,26 @@ def c3(n: int = 1024, nzeta: int = 1024, n_per_beam: int = 2 ** 21,
                                C3_WITNESS["sigma_r"], C3_WITNESS["sigma_z"],
                                C3_WITNESS["zeta_c"], C3_GAMMA, rng)
     beam = ParticleBeam(*(np.concatenate([getattr(d, f.name), getattr(w, f.name)])
-                          for f in dataclasses.fields(ParticleBeam)))
+                          for f in dataclasses.fields(ParticleBeam)[:7]), dt=BEAM_DT)
+    return cfg, beam
+
+
+def small_particle_beam(n: int = 64, nzeta: int = 64, n_per_beam: int = 4096,
+                        seed: int = SEED) -> tuple[BoxConfig, ParticleBeam]:
+    """A reduced C3 for tests: 64^2 nodes over [-8,8]^2, zeta in (-3,5]
+    (dzeta = 0.125), driver (peak 2, sigma_r 0.6, sigma_z 0.8 at 3) and
+    witness (peak 5, sigma_r 0.4, sigma_z 0.3 at 0) with n_per_beam
+    macro-particles each, gamma = 2000, values representable in float32,
+    4 fixed P-C iterations."""
+    cfg = BoxConfig(nx=n, ny=n, x_lo=-8.0, x_hi=8.0, y_lo=-8.0, y_hi=8.0,
+                    nzeta=nzeta, zeta_hi=5.0, dzeta=8.0 / nzeta,
+                    pc_max_iter=4, pc_tol=0.0)
+    rng = np.random.default_rng(seed)
+    d = gaussian_particle_beam(n_per_beam, 2.0, 0.6, 0.8, 3.0, C3_GAMMA, rng)
+    w = gaussian_particle_beam(n_per_beam, 5.0, 0.4, 0.3, 0.0, C3_GAMMA, rng)
+    beam = ParticleBeam(*(np.concatenate([getattr(d, f.name), getattr(w, f.name)])
+                          .astype(np.float32).astype(np.float64)
+                          for f in dataclasses.fields(ParticleBeam)[:7]), dt=BEAM_DT)
     return cfg, beam
 
 
