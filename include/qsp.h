@@ -205,17 +205,20 @@ qsp_status qsp_set_beam_gaussian(qsp_ctx ctx, const double* amp, double sx,
 /* Macro-particle electron beam (Sec. III.A: beam particles sorted per slice
  * and deposited inside the slice loop).  soa: device array [7][n] of float,
  * rows x, y, zeta, ux, uy, uz, w (w = physical electrons per macro-particle,
- * in n0 k_p^-3).  The context copies the particles, sorted by their nearest
- * slice (NGP in zeta); particles outside the box in zeta are dropped.  Each
+ * in n0 k_p^-3).  The context copies the particles, stably sorted by their
+ * nearest slice (NGP in zeta); particles outside the box in zeta are kept,
+ * sorted last, and neither deposit nor move.  Each
  * slice deposits its beam particles (CIC transversely) before the field
  * solves and, once the slice's fields are final, advances them by one
- * time step dt with a leapfrog (drift-kick-drift) push.  n = 0 removes the
- * particle beam.  Replaces any previous particle beam. */
+ * time step dt (drift-kick-drift, Boris kick; dt = 0: no push).  n = 0
+ * removes the particle beam.  Replaces any previous particle beam.  A beam
+ * pushed during a box is sorted again by qsp_init_plasma.  Synchronises. */
 qsp_status qsp_set_beam_particles(qsp_ctx ctx, int64_t n, const float* soa,
                                   double dt);
 
 /* Copies the particle beam back (device array [7][n] of float in the sorted
- * order; n must equal the stored count, see qsp_get_beam_count). */
+ * order; n must equal the stored count, see qsp_get_beam_count).
+ * Synchronises. */
 qsp_status qsp_get_beam_particles(qsp_ctx ctx, int64_t n, float* soa);
 qsp_status qsp_get_beam_count(qsp_ctx ctx, int64_t* n);
 

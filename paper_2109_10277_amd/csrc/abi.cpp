@@ -127,25 +127,29 @@ qsp_status qsp_set_beam_gaussian(qsp_ctx ctx, const double* amp, double sx, doub
 
 qsp_status qsp_set_beam_particles(qsp_ctx ctx, int64_t n, const float* soa, double dt) {
   return guarded(ctx, [&] {
-    (void)n;
-    (void)soa;
-    (void)dt;
-    return fail(ctx, QSP_ERR_INVALID_ARG, "particle beams are not available in this build");
+    if (n < 0 || n > 2147483647LL) return fail(ctx, QSP_ERR_INVALID_ARG, "n must be in [0, 2^31)");
+    if (n > 0 && !soa) return fail(ctx, QSP_ERR_INVALID_ARG, "null particle array");
+    if (!std::isfinite(dt)) return fail(ctx, QSP_ERR_INVALID_ARG, "dt must be finite");
+    ctx->box->set_beam_particles(n, soa, dt);
+    return QSP_OK;
   });
 }
 
 qsp_status qsp_get_beam_particles(qsp_ctx ctx, int64_t n, float* soa) {
   return guarded(ctx, [&] {
-    (void)n;
-    (void)soa;
-    return fail(ctx, QSP_ERR_BAD_STATE, "no particle beam");
+    if (ctx->box->beam_count() == 0) return fail(ctx, QSP_ERR_BAD_STATE, "no particle beam");
+    if (n != ctx->box->beam_count())
+      return fail(ctx, QSP_ERR_INVALID_ARG, "n does not match the stored particle count");
+    if (!soa) return fail(ctx, QSP_ERR_INVALID_ARG, "null particle array");
+    ctx->box->get_beam_particles(soa);
+    return QSP_OK;
   });
 }
 
 qsp_status qsp_get_beam_count(qsp_ctx ctx, int64_t* n) {
   return guarded(ctx, [&] {
     if (!n) return fail(ctx, QSP_ERR_INVALID_ARG, "null output");
-    *n = 0;
+    *n = ctx->box->beam_count();
     return QSP_OK;
   });
 }

@@ -128,6 +128,11 @@ void launch_to_nodes_t(const Geom& g, const T* src, T* dst, hipStream_t st) {
   QSP_LAUNCH_CHECK();
 }
 
+void launch_zero_int(int* p, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero<int>, grid_for(n), dim3(kBlock), 0, st, p, n);
+  QSP_LAUNCH_CHECK();
+}
+
 void launch_zero(double* p, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_zero<double>, grid_for(n), dim3(kBlock), 0, st, p, n);
   QSP_LAUNCH_CHECK();

@@ -1,6 +1,8 @@
 // Argument blocks and launchers of the libqsp HIP kernels.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace qsp {
@@ -189,5 +191,29 @@ template <typename T>
 void launch_to_nodes(const Geom&, const T* src, double* dst, hipStream_t);    // stored -> [ny+1][nx+1]
 template <typename T>
 void launch_to_nodes_t(const Geom&, const T* src, T* dst, hipStream_t);
+
+// ---------------------------------------------------------------- beams
+struct BeamScratch {
+  int* keys_in;
+  int* keys_out;
+  int* idx_in;
+  int* idx_out;
+  int* counts;          // nzeta + 1
+  void* temp;           // radix-sort scratch
+  size_t temp_bytes;
+};
+
+// Stable sort of a [7][n] float SoA beam by nearest slice; offsets[k] is the
+// first sorted particle of slice k (offsets[nzeta] = particles inside the
+// box, offsets[nzeta+1] = n).  Synchronises the stream.
+void beam_sort(const float* in, float* out, int64_t n, double zeta_hi, double dzeta, int nzeta,
+               BeamScratch& s, std::vector<int64_t>& offsets, hipStream_t st);
+size_t beam_sort_temp_bytes(int64_t n, int nzeta);
+void launch_beam_deposit(const Geom&, const float* soa, int64_t n, int64_t start, int64_t count,
+                         double dzeta, double* rho_mjz, double* jz, double* rho, hipStream_t);
+template <typename T>
+void launch_beam_push(const Geom&, float* soa, int64_t n, int64_t start, int64_t count,
+                      const SliceFields<T>& f, double dt, hipStream_t);
+void launch_zero_int(int* p, size_t n, hipStream_t);
 
 }  // namespace qsp

@@ -159,7 +159,10 @@ class Box final : public BoxBase {
     }
   }
 
-  ~Box() override { release(); }
+  ~Box() override {
+    free_beam();
+    release();
+  }
 
   void set_deposit_tiled(bool on) override { tiled_ = on; }
   void set_timing(int every) override {
@@ -171,6 +174,14 @@ class Box final : public BoxBase {
   // ---------------------------------------------------------------- state
   void init_plasma() override {
     QSP_HIP(hipSetDevice(device_));
+    if (beam_n_ > 0 && beam_dirty_) {
+      // a pushed beam is re-sorted by slice before the next box
+      QSP_HIP(hipMemcpyAsync(beam_tmp_, beam_soa_, 7 * beam_n_ * sizeof(float),
+                             hipMemcpyDeviceToDevice, st_));
+      beam_sort(beam_tmp_, beam_soa_, beam_n_, cfg_.zeta_hi, cfg_.dzeta, cfg_.nzeta, bs_,
+                beam_off_, st_);
+      beam_dirty_ = false;
+    }
     launch_init_plasma<T>(lat_, p_, cfg_.n0 / (cfg_.ppc_x * cfg_.ppc_y), st_);
     for (int b = 0; b < 3; ++b)
       for (int c = 0; c < 2; ++c) launch_zero_t<T>(b_[b][c], plane(), st_);
@@ -208,6 +219,36 @@ class Box final : public BoxBase {
     QSP_HIP(hipStreamSynchronize(st_));
     has_gauss_ = true;
   }
+
+  void set_beam_particles(int64_t n, const float* soa, double dt) override {
+    QSP_HIP(hipSetDevice(device_));
+    free_beam();
+    if (n == 0) return;
+    const int nz = cfg_.nzeta;
+    const size_t temp = beam_sort_temp_bytes(n, nz);
+    const int64_t need = n * (14 * 4 + 16) + (nz + 1) * 4 + static_cast<int64_t>(temp);
+    if (cfg_.mem_cap_bytes > 0 && bytes_ + need > cfg_.mem_cap_bytes) throw std::bad_alloc();
+    beam_soa_ = beam_alloc<float>(7 * n);
+    beam_tmp_ = beam_alloc<float>(7 * n);
+    bs_.keys_in = beam_alloc<int>(n);
+    bs_.keys_out = beam_alloc<int>(n);
+    bs_.idx_in = beam_alloc<int>(n);
+    bs_.idx_out = beam_alloc<int>(n);
+    bs_.counts = beam_alloc<int>(nz + 1);
+    bs_.temp = beam_alloc<unsigned char>(temp);
+    bs_.temp_bytes = temp;
+    beam_n_ = n;
+    beam_dt_ = dt;
+    beam_sort(soa, beam_soa_, n, cfg_.zeta_hi, cfg_.dzeta, nz, bs_, beam_off_, st_);
+    beam_dirty_ = false;
+  }
+
+  void get_beam_particles(float* soa) override {
+    QSP_HIP(hipMemcpyAsync(soa, beam_soa_, 7 * beam_n_ * sizeof(float), hipMemcpyDeviceToDevice, st_));
+    QSP_HIP(hipStreamSynchronize(st_));
+  }
+
+  int64_t beam_count() const override { return beam_n_; }
 
   void get_stats(qsp_stats* s) override {
     DevCounters c{};
@@ -422,6 +463,31 @@ class Box final : public BoxBase {
     return static_cast<U*>(p);
   }
 
+  template <typename U>
+  U* beam_alloc(size_t n) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(n * sizeof(U), 256);
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory) throw std::bad_alloc();
+    QSP_HIP(e);
+    beam_allocs_.push_back(p);
+    bytes_ += static_cast<int64_t>(bytes);
+    beam_bytes_ += static_cast<int64_t>(bytes);
+    return static_cast<U*>(p);
+  }
+
+  void free_beam() {
+    (void)hipStreamSynchronize(st_);
+    for (void* p : beam_allocs_) (void)hipFree(p);
+    beam_allocs_.clear();
+    bytes_ -= beam_bytes_;
+    beam_bytes_ = 0;
+    beam_n_ = 0;
+    beam_soa_ = beam_tmp_ = nullptr;
+    bs_ = BeamScratch{};
+    beam_off_.clear();
+  }
+
   void release() {
     (void)hipStreamSynchronize(st_);
     for (void* p : allocs_) (void)hipFree(p);
@@ -547,6 +613,14 @@ class Box final : public BoxBase {
     }
     T* bxk = b_[ik_][0];
     T* byk = b_[ik_][1];
+    const int64_t b0 = beam_n_ ? beam_off_[k] : 0;
+    const int64_t bcount = beam_n_ ? beam_off_[k + 1] - beam_off_[k] : 0;
+    // beam deposit of slice k (Sec. II step 3)
+    if (bcount > 0)
+      timed(QSP_K_OTHER, [&] {
+        launch_beam_deposit(geom_, beam_soa_, beam_n_, b0, bcount, cfg_.dzeta, dc[0], dc[3], dc[4],
+                            st_);
+      });
     // psi, Ez, Bz (Sec. II steps 4-6)
     {
       SrcPEZ<T> s{dc[0], dc[1], dc[2], cfg_.n0, t1_};
@@ -613,6 +687,13 @@ class Box final : public BoxBase {
       PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol};
       timed(QSP_K_ROW_INV, [&] { launch_row_inv_pc<T>(geom_, pc, tx(), ctr_, st_); });
     }
+    // beam particles of slice k take their time step in the final fields
+    if (bcount > 0 && beam_dt_ != 0.0) {
+      timed(QSP_K_OTHER, [&] {
+        launch_beam_push<T>(geom_, beam_soa_, beam_n_, b0, bcount, fields(bxk, byk), beam_dt_, st_);
+      });
+      beam_dirty_ = true;
+    }
     // outputs of slice k
     oc.beam_amp = amp;
     oc.n0 = cfg_.n0;
@@ -674,6 +755,16 @@ class Box final : public BoxBase {
   hipStream_t st_;
   int device_;
   KernelTimer timer_;
+  // macro-particle beam (sorted by slice)
+  std::vector<void*> beam_allocs_;
+  int64_t beam_bytes_ = 0;
+  float* beam_soa_ = nullptr;
+  float* beam_tmp_ = nullptr;
+  int64_t beam_n_ = 0;
+  double beam_dt_ = 0.0;
+  bool beam_dirty_ = false;
+  BeamScratch bs_{};
+  std::vector<int64_t> beam_off_;
   std::vector<void*> allocs_;
   int64_t bytes_ = 0;
   T *psi_ = nullptr, *exmby_ = nullptr, *eypbx_ = nullptr, *ez_ = nullptr, *bz_ = nullptr;

@@ -31,6 +31,9 @@ class BoxBase {
   virtual void get_state(qsp_slice_state* dst) = 0;
   virtual void set_state(const qsp_slice_state* src) = 0;
   virtual void set_deposit_tiled(bool on) = 0;
+  virtual void set_beam_particles(int64_t n, const float* soa, double dt) = 0;
+  virtual void get_beam_particles(float* soa) = 0;
+  virtual int64_t beam_count() const = 0;
   virtual void solve_poisson(int nbatch, const void* src, void* dst, double shift) = 0;
   virtual void set_timing(int every) = 0;
   virtual void get_kernel_times(qsp_kernel_times* out) = 0;

@@ -261,6 +261,26 @@ class Box:
         self._call("qsp_set_beam_gaussian", a.ctypes.data_as(_DP), float(sx), float(sy),
                    float(x0), float(y0))
 
+    def set_beam_particles(self, soa, dt: float = 0.0):
+        """soa: contiguous float32 device tensor [7, n] (x, y, zeta, ux, uy, uz, w)."""
+        if soa is None:
+            self._call("qsp_set_beam_particles", 0, None, float(dt))
+            return
+        if soa.dtype != self.torch.float32 or soa.dim() != 2 or soa.shape[0] != 7:
+            raise ValueError("soa must be float32 [7, n]")
+        self._call("qsp_set_beam_particles", int(soa.shape[1]), C.c_void_p(_ptr(soa)), float(dt))
+
+    def beam_count(self) -> int:
+        n = C.c_int64()
+        self._call("qsp_get_beam_count", C.byref(n))
+        return n.value
+
+    def get_beam_particles(self):
+        n = self.beam_count()
+        out = self.torch.empty(7, n, dtype=self.torch.float32, device=self.device)
+        self._call("qsp_get_beam_particles", n, C.c_void_p(_ptr(out)))
+        return out
+
     def advance_slice(self, outputs: Optional[Dict[str, object]] = None):
         so = SliceOut()
         for q, t in (outputs or {}).items():

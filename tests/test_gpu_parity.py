@@ -200,3 +200,54 @@ def test_mem_cap_is_enforced():
     with pytest.raises(qsp.QspError) as e:
         qsp.Box(cfg, "fp32", mem_cap_bytes=1024)
     assert e.value.status == qsp.QSP_ERR_OUT_OF_MEMORY
+
+
+# ------------------------------------------------------------------ particle beams
+
+def run_particle_beam_box(cfg, beam, prec):
+    with Q().Box(cfg, prec) as box:
+        box.set_beam_particles(torch.tensor(beam.soa(), device="cuda"), beam.dt)
+        box.init_plasma()
+        stack = {q: box.empty(q, cfg.nzeta) for q in FIELD_NAMES + DEPOSIT_NAMES}
+        iters = torch.zeros(cfg.nzeta, dtype=torch.int32, device="cuda")
+        box.run_box(stack=stack, pc_iters=iters)
+        after = box.get_beam_particles().double().cpu().numpy()
+        return {q: to_np(t) for q, t in stack.items()}, after
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_particle_beam_box_matches_oracle(prec):
+    cfg, beam = W.small_particle_beam()
+    print(f"particle beam box {prec}", flush=True)
+    keys = O.beam_slice_index(cfg, beam.zeta)
+    order = np.argsort(np.where((keys >= 0) & (keys < cfg.nzeta), keys, cfg.nzeta), kind="stable")
+    b = W.copy_beam(beam)
+    recs, _ = O.run_box(cfg, b)
+    got, after = run_particle_beam_box(cfg, beam, prec)
+    ref = {q: O.stack(recs, q) for q in FIELD_NAMES + DEPOSIT_NAMES}
+    errs = field_errors(got, ref)
+    print("  rel-L2", {q: f"{e:.1e}" for q, e in errs.items()})
+    tol = 1e-9 if prec == "fp64" else 1e-3
+    assert all(e < tol for e in errs.values()), errs
+    # the beam after its per-slice push, in the library's slice-sorted order
+    ref_b = np.stack([getattr(b, n)[order] for n in ("x", "y", "zeta", "ux", "uy", "uz", "w")])
+    assert after.shape == ref_b.shape
+    for c, name in enumerate(("x", "y", "zeta", "ux", "uy", "uz", "w")):
+        scale = np.abs(ref_b[c]).max()
+        d = np.abs(after[c] - ref_b[c]).max()
+        assert d <= (2e-6 if prec == "fp64" else 2e-4) * scale + 1e-12, (name, d, scale)
+
+
+def test_beam_sort_and_counts():
+    cfg, beam = W.small_particle_beam()
+    with Q().Box(cfg, "fp32") as box:
+        box.set_beam_particles(torch.tensor(beam.soa(), device="cuda"), 0.0)
+        assert box.beam_count() == beam.x.size
+        got = box.get_beam_particles().cpu().numpy()
+    keys = O.beam_slice_index(cfg, got[2].astype(np.float64))
+    keys = np.where((keys >= 0) & (keys < cfg.nzeta), keys, cfg.nzeta)
+    assert np.all(np.diff(keys) >= 0)
+    ref_keys = O.beam_slice_index(cfg, beam.zeta)
+    ref_keys = np.where((ref_keys >= 0) & (ref_keys < cfg.nzeta), ref_keys, cfg.nzeta)
+    order = np.argsort(ref_keys, kind="stable")
+    assert np.array_equal(got, beam.soa()[:, order])
