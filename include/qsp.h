@@ -256,6 +256,47 @@ qsp_status qsp_set_slice_state(qsp_ctx ctx, const qsp_slice_state* src);
 qsp_status qsp_solve_poisson(qsp_ctx ctx, int32_t nbatch, const void* src, void* dst,
                              double shift);
 
+/* Cotangent weights of a recorded run for qsp_run_box_adjoint: the loss is
+ *   L = sum_{k = k_lo}^{n-1} sum_F < w_F[k - k_lo], F_k >
+ * over the interior nodes, F in psi, Ex-By, Ey+Bx, Ez, Bx, By, Bz of slice
+ * k (n = slices of the record).
+ *   w[q]  q = QSP_PSI .. QSP_BZ: device array [n - k_lo][ny+1][nx+1] in the
+ *         context precision, or NULL for a zero weight.  Boundary nodes
+ *         are ignored. */
+typedef struct {
+  int32_t k_lo;
+  int32_t reserved0;
+  const void* w[7];
+} qsp_box_cotangent;
+
+/* Checkpointed forward pass for the adjoint.  Runs slices 0 .. n_slices-1
+ * of the slice loop (Sec. II, with the Sec. III.B predictor-corrector)
+ * from the state left by qsp_init_plasma, writes the requested outputs like
+ * qsp_run_box (relative slice index = k), keeps the full slice state
+ * (particles, Adams-Bashforth history, J_perp of the previous slice, Bx/By
+ * of the two previous slices) every ckpt_every slices in device memory and
+ * the per-slice record of the last chunk of slices.  Device memory grows by
+ * about ceil(n_slices/ckpt_every) slice states plus ckpt_every records;
+ * mem_cap_bytes applies.  Requires the cursor at 0, a Gaussian beam, and no
+ * macro-particle beam that moves (dt != 0); 1 <= n_slices <= nzeta,
+ * ckpt_every >= 1.  Synchronises. */
+qsp_status qsp_run_box_record(qsp_ctx ctx, int32_t n_slices, int32_t ckpt_every,
+                              const qsp_box_out* out, qsp_stats* stats);
+
+/* Reverse pass of the last qsp_run_box_record: the gradient of the loss of
+ * `cot` with respect to the Gaussian beam's per-slice amplitudes and its
+ * transverse sizes.  Each chunk of slices is recomputed from its checkpoint
+ * (the predictor-corrector takes the iteration counts of that recompute)
+ * and then transposed slice by slice in reverse order.  Outputs (device,
+ * FP64, overwritten): grad_amp [nzeta] (zero for slices >= n_slices),
+ * grad_sigma [2] (d/d sx, d/d sy), loss [1] or NULL (L evaluated on the
+ * recomputed fields).  The record is consumed: afterwards the plasma state
+ * is an intermediate one and qsp_init_plasma is required before the next
+ * run.  Errors: no valid record -> QSP_ERR_BAD_STATE; k_lo outside
+ * [0, n_slices) or NULL outputs -> QSP_ERR_INVALID_ARG.  Synchronises. */
+qsp_status qsp_run_box_adjoint(qsp_ctx ctx, const qsp_box_cotangent* cot, double* grad_amp,
+                               double* grad_sigma, double* loss);
+
 /* Kernel classes of the per-kernel device timers. */
 enum {
   QSP_K_PUSH = 0,        /* real gather + push + deposit (one per slice)      */

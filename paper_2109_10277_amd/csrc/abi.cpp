@@ -178,6 +178,46 @@ qsp_status qsp_run_box(qsp_ctx ctx, const qsp_box_out* out, qsp_stats* stats) {
   });
 }
 
+qsp_status qsp_run_box_record(qsp_ctx ctx, int32_t n_slices, int32_t ckpt_every,
+                              const qsp_box_out* out, qsp_stats* stats) {
+  return guarded(ctx, [&] {
+    const qsp::BoxBase& b = *ctx->box;
+    if (!b.initialised() || b.cursor() != 0)
+      return fail(ctx, QSP_ERR_BAD_STATE, "record needs the plasma initialised at slice 0");
+    if (n_slices < 1 || n_slices > b.config().nzeta)
+      return fail(ctx, QSP_ERR_INVALID_ARG, "n_slices must be in [1, nzeta]");
+    if (ckpt_every < 1) return fail(ctx, QSP_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+    if (out && out->stack_every < 0) return fail(ctx, QSP_ERR_INVALID_ARG, "stack_every < 0");
+    if (!b.has_gaussian_beam())
+      return fail(ctx, QSP_ERR_BAD_STATE, "the adjoint needs a Gaussian beam (qsp_set_beam_gaussian)");
+    if (b.has_moving_beam())
+      return fail(ctx, QSP_ERR_BAD_STATE, "the adjoint does not transpose a moving particle beam");
+    const qsp_config& c = b.config();
+    if (c.mem_cap_bytes > 0 && qsp::device_bytes_needed(c) + b.adjoint_bytes(n_slices, ckpt_every) >
+                                   c.mem_cap_bytes)
+      return fail(ctx, QSP_ERR_OUT_OF_MEMORY, "checkpoints and tape exceed mem_cap_bytes");
+    ctx->box->record(n_slices, ckpt_every, out);
+    if (stats) ctx->box->get_stats(stats);
+    if (ctx->box->check_nonfinite())
+      return fail(ctx, QSP_ERR_NONFINITE, "non-finite predictor-corrector residual");
+    return QSP_OK;
+  });
+}
+
+qsp_status qsp_run_box_adjoint(qsp_ctx ctx, const qsp_box_cotangent* cot, double* grad_amp,
+                               double* grad_sigma, double* loss) {
+  return guarded(ctx, [&] {
+    if (!ctx->box->recorded())
+      return fail(ctx, QSP_ERR_BAD_STATE, "no recorded forward pass (qsp_run_box_record)");
+    if (!cot || !grad_amp || !grad_sigma)
+      return fail(ctx, QSP_ERR_INVALID_ARG, "null cotangent or gradient output");
+    if (cot->k_lo < 0 || cot->k_lo >= ctx->box->recorded_slices())
+      return fail(ctx, QSP_ERR_INVALID_ARG, "k_lo outside the recorded slices");
+    ctx->box->adjoint(cot, grad_amp, grad_sigma, loss);
+    return QSP_OK;
+  });
+}
+
 qsp_status qsp_get_stats(qsp_ctx ctx, qsp_stats* stats) {
   return guarded(ctx, [&] {
     if (!stats) return fail(ctx, QSP_ERR_INVALID_ARG, "null stats");

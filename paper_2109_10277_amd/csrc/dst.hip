@@ -348,8 +348,14 @@ __device__ inline void guess_job(const GuessJob<T>& q, size_t n) {
     q.ctr->pc_resid = 0.0;
   }
   for (size_t i = bid * blockDim.x + threadIdx.x; i < n; i += stride) {
-    q.bx[i] = T(2) * q.bx1[i] - q.bx2[i];
-    q.by[i] = T(2) * q.by1[i] - q.by2[i];
+    const T vx = T(2) * q.bx1[i] - q.bx2[i];
+    const T vy = T(2) * q.by1[i] - q.by2[i];
+    q.bx[i] = vx;
+    q.by[i] = vy;
+    if (q.tape_bx) {
+      q.tape_bx[i] = vx;
+      q.tape_by[i] = vy;
+    }
   }
 }
 
@@ -649,6 +655,8 @@ k_row_inv_pc(Geom g, PCArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     dsum += d * d;
     nsum += static_cast<double>(u) * static_cast<double>(u);
     b[j * n + i] = u;
+    T* tp = fld == 0 ? a.tape_bx : a.tape_by;
+    if (tp) tp[j * n + i] = u;
   }
   // workgroup reduction
   for (int off = 32; off > 0; off >>= 1) {

@@ -63,6 +63,8 @@ struct GuessJob {
   const T* bx2;
   const T* by2;
   DevCounters* ctr;         // nullptr = no guess job
+  T* tape_bx;               // optional copy of B^0 for the adjoint
+  T* tape_by;
 };
 
 template <typename T>
@@ -80,6 +82,8 @@ struct PCArgs {
   T* by;
   double* partial;          // 2 doubles per workgroup
   double tol;
+  T* tape_bx;               // optional copy of the new iterate for the adjoint
+  T* tape_by;
 };
 
 template <typename T>
@@ -215,5 +219,114 @@ template <typename T>
 void launch_beam_push(const Geom&, float* soa, int64_t n, int64_t start, int64_t count,
                       const SliceFields<T>& f, double dt, hipStream_t);
 void launch_zero_int(int* p, size_t n, hipStream_t);
+
+// ---------------------------------------------------------------- adjoint
+template <typename T>
+struct AdjPushArgs {
+  Particles<T> p;           // taped state of slice k
+  SliceFields<T> f;         // fields of the push being transposed
+  T* lam_y;                 // [5][np]
+  T* lam_ring;              // [4][5][np], slot s = adjoint of history slot s
+  const T* lsb_x;           // trial: solved adjoint sources of the corrector
+  const T* lsb_y;
+  double* lam_F[6];         // scatter targets: Ex-By, Ey+Bx, Ez, Bx, By, Bz
+  int k;
+  double dzeta, hx, hy, psi_floor, inv2dz;
+};
+
+template <typename T>
+struct AdjDepArgs {
+  Particles<T> p;
+  const double* lam_dep[4]; // rho-Jz, Jx, Jy, Jz
+  T* lam_y;
+  double psi_floor;
+};
+
+template <typename T>
+struct AdjSeedArgs {
+  const T* cot[7];          // node layout cotangents (QSP_PSI .. QSP_BZ), may be null
+  const double* extra[7];   // stored-layout additions, may be null
+  double* out[7];
+  double* zero[3];          // planes cleared alongside, may be null
+};
+
+template <typename T>
+struct AdjPCGridArgs {
+  const T* lsb_x;
+  const T* lsb_y;
+  double* lam_jz;
+  double* jp_x;
+  double* jp_y;
+  double* lam_bx;
+  double* lam_by;
+  double shift, inv2dz;
+};
+
+template <typename T>
+struct AdjDepGridArgs {
+  const T* lpsi;
+  const T* lez;
+  const T* lbz;
+  const double* lam_jz;
+  const double* carry_jx;
+  const double* carry_jy;
+  double* lam_r;
+  double* lam_jx;
+  double* lam_jy;
+  const double* bgx;
+  const double* bgy;
+  const double* dbgx;
+  const double* dbgy;
+  double* grad_amp;
+  double* grad_sigma;
+  double amp;
+  int k;
+};
+
+template <typename T>
+struct AdjSrcArgs {
+  const double* p0[3];
+  const double* p1[3];
+  const double* p2[3];
+  double c0[3], c1[3], c2[3];
+  T* out[3];
+  int count;
+};
+
+template <typename T>
+struct LossArgs {
+  const T* cot[7];
+  const T* field[7];
+  double* loss;
+};
+
+template <typename T, typename U>
+struct CopyPlanes {
+  const T* src[8];
+  U* dst[8];
+};
+
+template <typename T>
+void launch_adj_push(const Geom&, const Lattice&, const AdjPushArgs<T>&, bool trial, hipStream_t);
+template <typename T>
+void launch_adj_deposit(const Geom&, const Lattice&, const AdjDepArgs<T>&, hipStream_t);
+template <typename T>
+void launch_adj_seed(const Geom&, const AdjSeedArgs<T>&, hipStream_t);
+template <typename T>
+void launch_adj_pc_grid(const Geom&, const AdjPCGridArgs<T>&, hipStream_t);
+void launch_adj_guess(size_t n, const double* lam_b0x, const double* lam_b0y, const double* c2x,
+                      const double* c2y, double* b1x, double* b1y, double* b2x, double* b2y,
+                      hipStream_t);
+template <typename T>
+void launch_adj_dep_grid(const Geom&, const AdjDepGridArgs<T>&, hipStream_t);
+template <typename T>
+void launch_adj_source(const Geom&, const AdjSrcArgs<T>&, hipStream_t);
+template <typename T>
+void launch_loss(const Geom&, const LossArgs<T>&, hipStream_t);
+template <typename T>
+void launch_copy_particles(const Lattice&, const Particles<T>& src, const Particles<T>& dst,
+                           hipStream_t);
+template <typename T, typename U>
+void launch_copy_planes(size_t n, int count, const CopyPlanes<T, U>&, hipStream_t);
 
 }  // namespace qsp

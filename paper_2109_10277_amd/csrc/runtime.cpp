@@ -126,6 +126,24 @@ class KernelTimer {
   std::vector<hipEvent_t> pool_;
 };
 
+// Per-slice record of the forward pass kept for the reverse pass: the state
+// at the start of the slice, its fields and every predictor-corrector
+// iterate B^0 .. B^M.
+template <typename T>
+struct TapeSlot {
+  Particles<T> p;
+  T* f[5];        // psi, Ex-By, Ey+Bx, Ez, Bz
+  T* b;           // [pc_max_iter + 1][2][plane]
+};
+
+// Full slice state at the start of a chunk of slices.
+template <typename T>
+struct Checkpoint {
+  Particles<T> p;
+  double* j[2];   // J_perp of the previous slice
+  T* b[4];        // Bx, By of the previous slice, then of the one before
+};
+
 template <typename T>
 class Box final : public BoxBase {
  public:
@@ -161,6 +179,7 @@ class Box final : public BoxBase {
 
   ~Box() override {
     free_beam();
+    free_adjoint();
     release();
   }
 
@@ -174,6 +193,7 @@ class Box final : public BoxBase {
   // ---------------------------------------------------------------- state
   void init_plasma() override {
     QSP_HIP(hipSetDevice(device_));
+    rec_valid_ = false;
     if (beam_n_ > 0 && beam_dirty_) {
       // a pushed beam is re-sorted by slice before the next box
       QSP_HIP(hipMemcpyAsync(beam_tmp_, beam_soa_, 7 * beam_n_ * sizeof(float),
@@ -204,24 +224,32 @@ class Box final : public BoxBase {
 
   void set_beam_gaussian(const double* amp, double sx, double sy, double x0,
                          double y0) override {
+    rec_valid_ = false;
     amp_.assign(amp, amp + cfg_.nzeta);
+    // profile factors and their derivatives with respect to sigma
     std::vector<double> gx(cfg_.nx + 1, 0.0), gy(cfg_.ny + 1, 0.0);
+    std::vector<double> dgx(cfg_.nx + 1, 0.0), dgy(cfg_.ny + 1, 0.0);
     for (int i = 1; i < cfg_.nx; ++i) {
       const double x = cfg_.x_lo + i * geom_.hx - x0;
       gx[i] = std::exp(-x * x / (2.0 * sx * sx));
+      dgx[i] = gx[i] * x * x / (sx * sx * sx);
     }
     for (int j = 1; j < cfg_.ny; ++j) {
       const double y = cfg_.y_lo + j * geom_.hy - y0;
       gy[j] = std::exp(-y * y / (2.0 * sy * sy));
+      dgy[j] = gy[j] * y * y / (sy * sy * sy);
     }
     QSP_HIP(hipMemcpyAsync(bgx_, gx.data(), gx.size() * sizeof(double), hipMemcpyHostToDevice, st_));
     QSP_HIP(hipMemcpyAsync(bgy_, gy.data(), gy.size() * sizeof(double), hipMemcpyHostToDevice, st_));
+    QSP_HIP(hipMemcpyAsync(dbgx_, dgx.data(), dgx.size() * sizeof(double), hipMemcpyHostToDevice, st_));
+    QSP_HIP(hipMemcpyAsync(dbgy_, dgy.data(), dgy.size() * sizeof(double), hipMemcpyHostToDevice, st_));
     QSP_HIP(hipStreamSynchronize(st_));
     has_gauss_ = true;
   }
 
   void set_beam_particles(int64_t n, const float* soa, double dt) override {
     QSP_HIP(hipSetDevice(device_));
+    rec_valid_ = false;
     free_beam();
     if (n == 0) return;
     const int nz = cfg_.nzeta;
@@ -239,6 +267,7 @@ class Box final : public BoxBase {
     bs_.temp_bytes = temp;
     beam_n_ = n;
     beam_dt_ = dt;
+    moving_beam_ = dt != 0.0;
     beam_sort(soa, beam_soa_, n, cfg_.zeta_hi, cfg_.dzeta, nz, bs_, beam_off_, st_);
     beam_dirty_ = false;
   }
@@ -365,6 +394,7 @@ class Box final : public BoxBase {
     cursor_ = s->k;
     dep_valid_ = false;
     initialised_ = true;
+    rec_valid_ = false;
   }
 
   void solve_poisson(int nb, const void* src, void* dst, double shift) override {
@@ -396,6 +426,7 @@ class Box final : public BoxBase {
   // ---------------------------------------------------------------- loop
   void advance_slice(const qsp_slice_out* out) override {
     QSP_HIP(hipSetDevice(device_));
+    rec_valid_ = false;
     OutCopy oc{};
     if (out) {
       for (int q = 0; q < QSP_NQ; ++q)
@@ -406,23 +437,12 @@ class Box final : public BoxBase {
 
   void run_box(const qsp_box_out* out) override {
     QSP_HIP(hipSetDevice(device_));
+    rec_valid_ = false;
     const int k0 = cursor_;
-    const int every = (out && out->stack_every > 0) ? out->stack_every : 1;
     QSP_HIP(hipEventRecord(ev0_, st_));
     while (cursor_ < cfg_.nzeta) {
       const int rel = cursor_ - k0;
-      OutCopy oc{};
-      if (out) {
-        const size_t nn = nodes();
-        for (int q = 0; q < QSP_NQ; ++q) {
-          const size_t es = elem_size(q);
-          if (out->stack[q] && rel % every == 0)
-            add_out(oc, q, static_cast<char*>(out->stack[q]) + (rel / every) * nn * es, 0);
-          if (out->lineout[q])
-            add_out(oc, q, static_cast<char*>(out->lineout[q]) + rel * (cfg_.nx + 1) * es, 1);
-          if (out->axis[q]) add_out(oc, q, static_cast<char*>(out->axis[q]) + rel * es, 2);
-        }
-      }
+      OutCopy oc = box_outputs(out, rel);
       step(oc, out && out->pc_iters ? out->pc_iters + rel : nullptr,
            out && out->pc_resid ? out->pc_resid + rel : nullptr);
     }
@@ -433,8 +453,436 @@ class Box final : public BoxBase {
     last_ms_ = ms;
   }
 
+  // ---------------------------------------------------------------- adjoint
+  // Device bytes of the checkpoints, the tape of one chunk and the reverse
+  // work space for a record of n_slices slices with checkpoints every K.
+  int64_t adjoint_bytes(int n_slices, int K) const override {
+    const int64_t ts = sizeof(T), pl = static_cast<int64_t>(plane()), np = lat_.np;
+    const int64_t nck = (n_slices - 1) / K;
+    const int64_t slots = std::min(K, n_slices);
+    const int64_t part = 26 * np * ts;
+    const int64_t ck = part + 2 * pl * 8 + 4 * pl * ts;
+    const int64_t slot = part + 5 * pl * ts + 2 * (cfg_.pc_max_iter + 1) * pl * ts;
+    const int64_t work = 25 * np * ts + 18 * pl * 8 + 4 * static_cast<int64_t>(cfg_.nzeta) + 1024;
+    return nck * ck + slots * slot + work + 256 * (8 * (nck + slots) + 32);
+  }
+
+  void record(int n_slices, int K, const qsp_box_out* out) override {
+    QSP_HIP(hipSetDevice(device_));
+    rec_valid_ = false;
+    ensure_adjoint(n_slices, K);
+    const int last0 = ((n_slices - 1) / K) * K;   // first slice of the last chunk
+    QSP_HIP(hipEventRecord(ev0_, st_));
+    while (cursor_ < n_slices) {
+      const int k = cursor_;
+      if (k % K == 0 && k < last0) save_checkpoint(k / K);
+      OutCopy oc = box_outputs(out, k);
+      TapeSlot<T>* slot = k >= last0 ? &tape_[k - last0] : nullptr;
+      taped_step(oc, slot, out && out->pc_resid ? out->pc_resid + k : nullptr);
+    }
+    if (out && out->pc_iters)
+      QSP_HIP(hipMemcpyAsync(out->pc_iters, iters_dev_, n_slices * sizeof(int32_t),
+                             hipMemcpyDeviceToDevice, st_));
+    read_iterations(last0, n_slices);
+    QSP_HIP(hipEventRecord(ev1_, st_));
+    QSP_HIP(hipEventSynchronize(ev1_));
+    float ms = 0.f;
+    QSP_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+    last_ms_ = ms;
+    rec_slices_ = n_slices;
+    rec_K_ = K;
+    rec_valid_ = true;
+  }
+
+  void adjoint(const qsp_box_cotangent* cot, double* grad_amp, double* grad_sigma,
+               double* loss) override {
+    QSP_HIP(hipSetDevice(device_));
+    const int n_slices = rec_slices_, K = rec_K_;
+    const int nchunks = (n_slices - 1) / K + 1;
+    const size_t pl = plane(), np = static_cast<size_t>(lat_.np);
+    QSP_HIP(hipEventRecord(ev0_, st_));
+    launch_zero(grad_amp, cfg_.nzeta, st_);
+    launch_zero(grad_sigma, 2, st_);
+    if (loss) launch_zero(loss, 1, st_);
+    launch_zero_t<T>(lam_y_, 5 * np, st_);
+    launch_zero_t<T>(lam_ring_, 20 * np, st_);
+    for (double* q : {carry_j_[0], carry_j_[1], carry_b1_[0], carry_b1_[1], carry_b2_[0], carry_b2_[1]})
+      launch_zero(q, pl, st_);
+    for (int c = nchunks - 1; c >= 0; --c) {
+      const int k0 = c * K, k1 = std::min(k0 + K, n_slices);
+      if (c != nchunks - 1) {
+        // recompute the chunk from its checkpoint, taping every slice
+        restore_checkpoint(c);
+        while (cursor_ < k1) {
+          OutCopy oc{};
+          taped_step(oc, &tape_[cursor_ - k0], nullptr);
+        }
+        read_iterations(k0, k1);
+      }
+      for (int k = k1 - 1; k >= k0; --k)
+        reverse_slice(k, tape_[k - k0], cot, k == n_slices - 1, grad_amp, grad_sigma, loss);
+    }
+    QSP_HIP(hipEventRecord(ev1_, st_));
+    QSP_HIP(hipEventSynchronize(ev1_));
+    float ms = 0.f;
+    QSP_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+    last_ms_ = ms;
+    // the tape and the plasma now hold an intermediate state
+    rec_valid_ = false;
+    initialised_ = false;
+  }
+
  private:
   size_t plane() const { return static_cast<size_t>(cfg_.nx) * cfg_.ny; }
+
+  // output copies of slice rel (relative to the first slice of the run)
+  OutCopy box_outputs(const qsp_box_out* out, int rel) {
+    OutCopy oc{};
+    if (!out) return oc;
+    const int every = out->stack_every > 0 ? out->stack_every : 1;
+    const size_t nn = nodes();
+    for (int q = 0; q < QSP_NQ; ++q) {
+      const size_t es = elem_size(q);
+      if (out->stack[q] && rel % every == 0)
+        add_out(oc, q, static_cast<char*>(out->stack[q]) + (rel / every) * nn * es, 0);
+      if (out->lineout[q])
+        add_out(oc, q, static_cast<char*>(out->lineout[q]) + rel * (cfg_.nx + 1) * es, 1);
+      if (out->axis[q]) add_out(oc, q, static_cast<char*>(out->axis[q]) + rel * es, 2);
+    }
+    return oc;
+  }
+
+  // ------------------------------------------------------- adjoint storage
+  template <typename U>
+  U* adj_alloc(size_t n) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(n * sizeof(U), 256);
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory) throw std::bad_alloc();
+    QSP_HIP(e);
+    adj_allocs_.push_back(p);
+    bytes_ += static_cast<int64_t>(bytes);
+    adj_bytes_ += static_cast<int64_t>(bytes);
+    return static_cast<U*>(p);
+  }
+
+  void free_adjoint() {
+    (void)hipStreamSynchronize(st_);
+    for (void* p : adj_allocs_) (void)hipFree(p);
+    adj_allocs_.clear();
+    bytes_ -= adj_bytes_;
+    adj_bytes_ = 0;
+    ckpt_.clear();
+    tape_.clear();
+    adj_shape_ = {0, 0};
+    rec_valid_ = false;
+  }
+
+  Particles<T> alloc_particles() {
+    const size_t np = static_cast<size_t>(lat_.np);
+    Particles<T> q{};
+    T* base = adj_alloc<T>(26 * np);
+    q.xi_x = base;
+    q.xi_y = base + np;
+    q.ux = base + 2 * np;
+    q.uy = base + 3 * np;
+    q.psi = base + 4 * np;
+    q.w = base + 5 * np;
+    q.hist = base + 6 * np;
+    return q;
+  }
+
+  // (re)allocates checkpoints, tape and reverse work space for (n_slices, K)
+  void ensure_adjoint(int n_slices, int K) {
+    const int nck = (n_slices - 1) / K;
+    const int slots = std::min(K, n_slices);
+    if (adj_shape_.first == nck && adj_shape_.second == slots) return;
+    free_adjoint();
+    if (cfg_.mem_cap_bytes > 0 && bytes_ + adjoint_bytes(n_slices, K) > cfg_.mem_cap_bytes)
+      throw std::bad_alloc();
+    try {
+      const size_t pl = plane(), np = static_cast<size_t>(lat_.np);
+      for (int c = 0; c < nck; ++c) {
+        Checkpoint<T> ck{};
+        ck.p = alloc_particles();
+        double* j = adj_alloc<double>(2 * pl);
+        ck.j[0] = j;
+        ck.j[1] = j + pl;
+        T* b = adj_alloc<T>(4 * pl);
+        for (int q = 0; q < 4; ++q) ck.b[q] = b + q * pl;
+        ckpt_.push_back(ck);
+      }
+      for (int s = 0; s < slots; ++s) {
+        TapeSlot<T> ts{};
+        ts.p = alloc_particles();
+        T* f = adj_alloc<T>(5 * pl);
+        for (int q = 0; q < 5; ++q) ts.f[q] = f + q * pl;
+        ts.b = adj_alloc<T>(2 * static_cast<size_t>(cfg_.pc_max_iter + 1) * pl);
+        tape_.push_back(ts);
+      }
+      lam_y_ = adj_alloc<T>(5 * np);
+      lam_ring_ = adj_alloc<T>(20 * np);
+      double* w = adj_alloc<double>(18 * pl);
+      for (int q = 0; q < 6; ++q) lam_f_[q] = w + q * pl;
+      lam_psi_ = w + 6 * pl;
+      lam_jz_ = w + 7 * pl;
+      jp_[0] = w + 8 * pl;
+      jp_[1] = w + 9 * pl;
+      carry_j_[0] = w + 10 * pl;
+      carry_j_[1] = w + 11 * pl;
+      carry_b1_[0] = w + 12 * pl;
+      carry_b1_[1] = w + 13 * pl;
+      carry_b2_[0] = w + 14 * pl;
+      carry_b2_[1] = w + 15 * pl;
+      lam_b_[0] = w + 16 * pl;
+      lam_b_[1] = w + 17 * pl;
+      iters_dev_ = adj_alloc<int32_t>(cfg_.nzeta);
+      iters_host_.assign(cfg_.nzeta, 0);
+    } catch (...) {
+      free_adjoint();
+      throw;
+    }
+    if (cfg_.mem_cap_bytes > 0 && bytes_ > cfg_.mem_cap_bytes) {
+      free_adjoint();
+      throw std::bad_alloc();
+    }
+    adj_shape_ = {nck, slots};
+  }
+
+  void save_checkpoint(int c) {
+    Checkpoint<T>& ck = ckpt_[c];
+    launch_copy_particles<T>(lat_, p_, ck.p, st_);
+    CopyPlanes<double, double> j{};
+    j.src[0] = dep_[ip_][1];
+    j.src[1] = dep_[ip_][2];
+    j.dst[0] = ck.j[0];
+    j.dst[1] = ck.j[1];
+    launch_copy_planes<double, double>(plane(), 2, j, st_);
+    CopyPlanes<T, T> b{};
+    b.src[0] = b_[i1_][0];
+    b.src[1] = b_[i1_][1];
+    b.src[2] = b_[i2_][0];
+    b.src[3] = b_[i2_][1];
+    for (int q = 0; q < 4; ++q) b.dst[q] = ck.b[q];
+    launch_copy_planes<T, T>(plane(), 4, b, st_);
+  }
+
+  void restore_checkpoint(int c) {
+    const Checkpoint<T>& ck = ckpt_[c];
+    launch_copy_particles<T>(lat_, ck.p, p_, st_);
+    CopyPlanes<double, double> j{};
+    j.src[0] = ck.j[0];
+    j.src[1] = ck.j[1];
+    j.dst[0] = dep_[ip_][1];
+    j.dst[1] = dep_[ip_][2];
+    launch_copy_planes<double, double>(plane(), 2, j, st_);
+    CopyPlanes<T, T> b{};
+    for (int q = 0; q < 4; ++q) b.src[q] = ck.b[q];
+    b.dst[0] = b_[i1_][0];
+    b.dst[1] = b_[i1_][1];
+    b.dst[2] = b_[i2_][0];
+    b.dst[3] = b_[i2_][1];
+    launch_copy_planes<T, T>(plane(), 4, b, st_);
+    cursor_ = c * rec_K_;
+    dep_valid_ = false;
+  }
+
+  // one forward slice; with a tape slot, also records what the reverse pass
+  // of this slice reads
+  void taped_step(OutCopy& oc, TapeSlot<T>* slot, double* resid_out) {
+    const int k = cursor_;
+    if (slot) launch_copy_particles<T>(lat_, p_, slot->p, st_);
+    tape_slot_ = slot;
+    step(oc, iters_dev_ + k, resid_out);
+    tape_slot_ = nullptr;
+    if (slot) {
+      CopyPlanes<T, T> f{};
+      const T* src[5] = {psi_, exmby_, eypbx_, ez_, bz_};
+      for (int q = 0; q < 5; ++q) {
+        f.src[q] = src[q];
+        f.dst[q] = slot->f[q];
+      }
+      launch_copy_planes<T, T>(plane(), 5, f, st_);
+    }
+  }
+
+  void read_iterations(int k0, int k1) {
+    QSP_HIP(hipMemcpyAsync(iters_host_.data() + k0, iters_dev_ + k0, (k1 - k0) * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, st_));
+    QSP_HIP(hipStreamSynchronize(st_));
+  }
+
+  T* tape_b(const TapeSlot<T>& t, int m, int c) const {
+    return t.b + (2 * static_cast<size_t>(m) + c) * plane();
+  }
+
+  // (lap - shift)^-1 of nb planes staged in t2_; the solutions land in t1_
+  void adj_solve(int nb, double shift) {
+    const size_t pl = plane();
+    RowInvArgs<T> r{};
+    for (int b = 0; b < nb; ++b) {
+      r.in[b] = t2_ + b * pl;
+      r.out[b] = t1_ + b * pl;
+    }
+    launch_row_inv<T>(geom_, r, nb, tx(), st_);
+    ColArgs<T> c{};
+    c.in = t1_;
+    c.out = t2_;
+    for (int b = 0; b < 4; ++b) c.shift[b] = shift;
+    c.honor_done = 0;
+    c.w = col_width<T>(geom_, nb);
+    launch_col_solve<T>(geom_, c, nb, ty(), lamx_, ctr_, st_);
+    launch_row_inv<T>(geom_, r, nb, tx(), st_);
+  }
+
+  // Reverse pass of slice k: the transpose of step() taken in the opposite
+  // order (real push, predictor-corrector iterations M-1 .. 0, initial
+  // guess, psi/Ez/Bz solves, deposit), handing the adjoints of the state,
+  // J_perp and B of slice k on to slice k-1.
+  void reverse_slice(int k, const TapeSlot<T>& t, const qsp_box_cotangent* cot, bool last,
+                     double* grad_amp, double* grad_sigma, double* loss) {
+    const size_t pl = plane(), nn = nodes();
+    const int M = iters_host_[k];
+    if (M < 1 || M > cfg_.pc_max_iter)
+      throw std::runtime_error("recorded predictor-corrector iteration count out of range");
+    const bool has_cot = cot && k >= cot->k_lo;
+    const T* bxM = tape_b(t, M, 0);
+    const T* byM = tape_b(t, M, 1);
+    // seed: cotangents of slice k, plus what slice k+1 handed to B_k
+    {
+      AdjSeedArgs<T> a{};
+      for (int c = 0; c < 7; ++c)
+        a.cot[c] = has_cot && cot->w[c]
+                       ? static_cast<const T*>(cot->w[c]) + static_cast<size_t>(k - cot->k_lo) * nn
+                       : nullptr;
+      a.extra[QSP_BX] = carry_b1_[0];
+      a.extra[QSP_BY] = carry_b1_[1];
+      a.out[QSP_PSI] = lam_psi_;
+      for (int c = 1; c < 7; ++c) a.out[c] = lam_f_[c - 1];
+      a.zero[0] = lam_jz_;
+      a.zero[1] = jp_[0];
+      a.zero[2] = jp_[1];
+      launch_adj_seed<T>(geom_, a, st_);
+      if (has_cot && loss) {
+        LossArgs<T> l{};
+        const T* fld[7] = {t.f[0], t.f[1], t.f[2], t.f[3], bxM, byM, t.f[4]};
+        for (int c = 0; c < 7; ++c) {
+          l.cot[c] = a.cot[c];
+          l.field[c] = fld[c];
+        }
+        l.loss = loss;
+        launch_loss<T>(geom_, l, st_);
+      }
+    }
+    AdjPushArgs<T> pa{};
+    pa.p = t.p;
+    pa.lam_y = lam_y_;
+    pa.lam_ring = lam_ring_;
+    pa.k = k;
+    pa.dzeta = cfg_.dzeta;
+    pa.hx = geom_.hx;
+    pa.hy = geom_.hy;
+    pa.psi_floor = cfg_.psi_floor;
+    pa.inv2dz = 0.5 / cfg_.dzeta;
+    // real push k -> k+1 (none after the last recorded slice)
+    if (!last) {
+      pa.f = {t.f[1], t.f[2], t.f[3], bxM, byM, t.f[4]};
+      for (int c = 0; c < 6; ++c) pa.lam_F[c] = lam_f_[c];
+      launch_adj_push<T>(geom_, lat_, pa, false, st_);
+    }
+    // predictor-corrector iterations in reverse
+    const double* lbx = lam_f_[3];
+    const double* lby = lam_f_[4];
+    for (int m = M - 1; m >= 0; --m) {
+      AdjSrcArgs<T> s{};
+      s.count = 2;
+      s.p0[0] = lbx;
+      s.p0[1] = lby;
+      s.c0[0] = s.c0[1] = 1.0;
+      s.out[0] = t2_;
+      s.out[1] = t2_ + pl;
+      launch_adj_source<T>(geom_, s, st_);
+      adj_solve(2, shift_);
+      AdjPCGridArgs<T> g{};
+      g.lsb_x = t1_;
+      g.lsb_y = t1_ + pl;
+      g.lam_jz = lam_jz_;
+      g.jp_x = jp_[0];
+      g.jp_y = jp_[1];
+      g.lam_bx = lam_b_[0];
+      g.lam_by = lam_b_[1];
+      g.shift = shift_;
+      g.inv2dz = 0.5 / cfg_.dzeta;
+      launch_adj_pc_grid<T>(geom_, g, st_);
+      pa.f = {t.f[1], t.f[2], t.f[3], tape_b(t, m, 0), tape_b(t, m, 1), t.f[4]};
+      pa.lsb_x = t1_;
+      pa.lsb_y = t1_ + pl;
+      pa.lam_F[0] = lam_f_[0];
+      pa.lam_F[1] = lam_f_[1];
+      pa.lam_F[2] = lam_f_[2];
+      pa.lam_F[3] = lam_b_[0];
+      pa.lam_F[4] = lam_b_[1];
+      pa.lam_F[5] = lam_f_[5];
+      launch_adj_push<T>(geom_, lat_, pa, true, st_);
+      lbx = lam_b_[0];
+      lby = lam_b_[1];
+    }
+    // initial guess B^0 = 2 B_{k-1} - B_{k-2}
+    launch_adj_guess(pl, lbx, lby, carry_b2_[0], carry_b2_[1], carry_b1_[0], carry_b1_[1],
+                     carry_b2_[0], carry_b2_[1], st_);
+    // psi (with Ex-By = -d_x psi, Ey+Bx = -d_y psi), Ez and Bz solves
+    {
+      AdjSrcArgs<T> s{};
+      s.count = 3;
+      s.p0[0] = lam_psi_;
+      s.p1[0] = lam_f_[0];
+      s.p2[0] = lam_f_[1];
+      s.c0[0] = s.c1[0] = s.c2[0] = 1.0;
+      s.p0[1] = lam_f_[2];
+      s.c0[1] = 1.0;
+      s.p0[2] = lam_f_[5];
+      s.c0[2] = 1.0;
+      for (int q = 0; q < 3; ++q) s.out[q] = t2_ + q * pl;
+      launch_adj_source<T>(geom_, s, st_);
+      adj_solve(3, 0.0);
+    }
+    // adjoints of the deposit channels of slice k and the beam gradient
+    {
+      AdjDepGridArgs<T> d{};
+      d.lpsi = t1_;
+      d.lez = t1_ + pl;
+      d.lbz = t1_ + 2 * pl;
+      d.lam_jz = lam_jz_;
+      d.carry_jx = carry_j_[0];
+      d.carry_jy = carry_j_[1];
+      d.lam_r = lam_psi_;
+      d.lam_jx = carry_j_[0];
+      d.lam_jy = carry_j_[1];
+      d.bgx = bgx_;
+      d.bgy = bgy_;
+      d.dbgx = dbgx_;
+      d.dbgy = dbgy_;
+      d.grad_amp = grad_amp;
+      d.grad_sigma = grad_sigma;
+      d.amp = has_gauss_ ? amp_[k] : 0.0;
+      d.k = k;
+      launch_adj_dep_grid<T>(geom_, d, st_);
+    }
+    {
+      AdjDepArgs<T> a{};
+      a.p = t.p;
+      a.lam_dep[0] = lam_psi_;
+      a.lam_dep[1] = carry_j_[0];
+      a.lam_dep[2] = carry_j_[1];
+      a.lam_dep[3] = lam_jz_;
+      a.lam_y = lam_y_;
+      a.psi_floor = cfg_.psi_floor;
+      launch_adj_deposit<T>(geom_, lat_, a, st_);
+    }
+    // the adjoint of J_perp_{k-1} collected here is slice k-1's carry
+    std::swap(carry_j_[0], jp_[0]);
+    std::swap(carry_j_[1], jp_[1]);
+  }
 
   // Lattice rows per push workgroup (64 sites wide): as many rows as keep
   // >= 1024 workgroups per launch, between 4 and 16.
@@ -483,6 +931,7 @@ class Box final : public BoxBase {
     bytes_ -= beam_bytes_;
     beam_bytes_ = 0;
     beam_n_ = 0;
+    moving_beam_ = false;
     beam_soa_ = beam_tmp_ = nullptr;
     bs_ = BeamScratch{};
     beam_off_.clear();
@@ -528,6 +977,8 @@ class Box final : public BoxBase {
     lamy_ = alloc<double>(cfg_.ny);
     bgx_ = alloc<double>(cfg_.nx + 1);
     bgy_ = alloc<double>(cfg_.ny + 1);
+    dbgx_ = alloc<double>(cfg_.nx + 1);
+    dbgy_ = alloc<double>(cfg_.ny + 1);
     ctr_ = alloc<DevCounters>(1);
     partial_ = alloc<double>(2 * static_cast<size_t>(pc_partial_count(geom_)) + 2);
     if (cfg_.mem_cap_bytes > 0 && bytes_ > cfg_.mem_cap_bytes) throw std::bad_alloc();
@@ -556,6 +1007,8 @@ class Box final : public BoxBase {
     std::vector<double> z(std::max(cfg_.nx, cfg_.ny) + 1, 0.0);
     QSP_HIP(hipMemcpy(bgx_, z.data(), (cfg_.nx + 1) * sizeof(double), hipMemcpyHostToDevice));
     QSP_HIP(hipMemcpy(bgy_, z.data(), (cfg_.ny + 1) * sizeof(double), hipMemcpyHostToDevice));
+    QSP_HIP(hipMemcpy(dbgx_, z.data(), (cfg_.nx + 1) * sizeof(double), hipMemcpyHostToDevice));
+    QSP_HIP(hipMemcpy(dbgy_, z.data(), (cfg_.ny + 1) * sizeof(double), hipMemcpyHostToDevice));
     QSP_HIP(hipMemset(ctr_, 0, sizeof(DevCounters)));
     QSP_HIP(hipDeviceSynchronize());
   }
@@ -648,7 +1101,9 @@ class Box final : public BoxBase {
       r.in[3] = t2_ + 2 * pl;
       r.out[3] = bz_;
       // Bx/By initial guess of the predictor-corrector rides along
-      r.guess = {bxk, byk, b_[i1_][0], b_[i1_][1], b_[i2_][0], b_[i2_][1], ctr_};
+      r.guess = {bxk, byk, b_[i1_][0], b_[i1_][1], b_[i2_][0], b_[i2_][1], ctr_,
+                 tape_slot_ ? tape_b(*tape_slot_, 0, 0) : nullptr,
+                 tape_slot_ ? tape_b(*tape_slot_, 0, 1) : nullptr};
       timed(QSP_K_ROW_INV, [&] { launch_row_inv<T>(geom_, r, 4, tx(), st_); });
       dst_solves_ += 3;
     }
@@ -684,7 +1139,9 @@ class Box final : public BoxBase {
       c.zero.count = 2;
       c.zero.n = pl;
       timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
-      PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol};
+      PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol,
+                   tape_slot_ ? tape_b(*tape_slot_, m + 1, 0) : nullptr,
+                   tape_slot_ ? tape_b(*tape_slot_, m + 1, 1) : nullptr};
       timed(QSP_K_ROW_INV, [&] { launch_row_inv_pc<T>(geom_, pc, tx(), ctr_, st_); });
     }
     // beam particles of slice k take their time step in the final fields
@@ -777,10 +1234,28 @@ class Box final : public BoxBase {
   Cplx<T>* twy_ = nullptr;
   T *prex_ = nullptr, *prey_ = nullptr;
   double *lamx_ = nullptr, *lamy_ = nullptr, *bgx_ = nullptr, *bgy_ = nullptr;
+  double *dbgx_ = nullptr, *dbgy_ = nullptr;
+  // adjoint: checkpoints, tape of one chunk, reverse work space
+  std::vector<void*> adj_allocs_;
+  int64_t adj_bytes_ = 0;
+  std::pair<int, int> adj_shape_{0, 0};
+  std::vector<Checkpoint<T>> ckpt_;
+  std::vector<TapeSlot<T>> tape_;
+  TapeSlot<T>* tape_slot_ = nullptr;
+  int rec_K_ = 1;
+  int32_t* iters_dev_ = nullptr;
+  std::vector<int32_t> iters_host_;
+  T *lam_y_ = nullptr, *lam_ring_ = nullptr;
+  double* lam_f_[6] = {};
+  double *lam_psi_ = nullptr, *lam_jz_ = nullptr;
+  double* jp_[2] = {};
+  double* carry_j_[2] = {};
+  double* carry_b1_[2] = {};
+  double* carry_b2_[2] = {};
+  double* lam_b_[2] = {};
   DevCounters* ctr_ = nullptr;
   double* partial_ = nullptr;
   std::vector<double> amp_;
-  bool has_gauss_ = false;
   double shift_ = 0.0;
   int ip_ = 0, ic_ = 1, in_ = 2;   // deposit buffers of slices k-1, k, k+1
   int ik_ = 0, i1_ = 1, i2_ = 2;   // B buffers of slices k, k-1, k-2

@@ -39,6 +39,15 @@ class BoxBase {
   virtual void get_kernel_times(qsp_kernel_times* out) = 0;
   // synchronises; true if a non-finite residual or norm was met
   virtual bool check_nonfinite() = 0;
+  // checkpointed forward of slices 0 .. n_slices-1 and its reverse pass
+  virtual void record(int n_slices, int ckpt_every, const qsp_box_out* out) = 0;
+  virtual void adjoint(const qsp_box_cotangent* cot, double* grad_amp, double* grad_sigma,
+                       double* loss) = 0;
+  virtual int64_t adjoint_bytes(int n_slices, int ckpt_every) const = 0;
+  bool recorded() const { return rec_valid_; }
+  int recorded_slices() const { return rec_slices_; }
+  bool has_gaussian_beam() const { return has_gauss_; }
+  bool has_moving_beam() const { return moving_beam_; }
   int cursor() const { return cursor_; }
   bool initialised() const { return initialised_; }
   int64_t n_particles() const { return lat_.np; }
@@ -50,6 +59,10 @@ class BoxBase {
   Lattice lat_{};
   int cursor_ = 0;
   bool initialised_ = false;
+  bool rec_valid_ = false;
+  int rec_slices_ = 0;
+  bool has_gauss_ = false;
+  bool moving_beam_ = false;
 };
 
 std::unique_ptr<BoxBase> make_box(const qsp_config& cfg, int device, hipStream_t stream);

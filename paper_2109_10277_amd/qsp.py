@@ -64,6 +64,10 @@ class BoxOut(C.Structure):
                 ("pc_resid", C.c_void_p)]
 
 
+class Cotangent(C.Structure):
+    _fields_ = [("k_lo", C.c_int32), ("reserved0", C.c_int32), ("w", C.c_void_p * 7)]
+
+
 class Stats(C.Structure):
     _fields_ = [("slices", C.c_int64), ("particle_pushes", C.c_int64),
                 ("pc_iterations", C.c_int64), ("pc_not_converged", C.c_int64),
@@ -123,6 +127,8 @@ def lib() -> C.CDLL:
             "qsp_get_info": [vp, C.POINTER(i64), C.POINTER(i32)],
             "qsp_set_timing": [vp, i32],
             "qsp_get_kernel_times": [vp, C.POINTER(KernelTimes)],
+            "qsp_run_box_record": [vp, i32, i32, C.POINTER(BoxOut), C.POINTER(Stats)],
+            "qsp_run_box_adjoint": [vp, C.POINTER(Cotangent), vp, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -290,6 +296,13 @@ class Box:
 
     def run_box(self, stack=None, stack_every: int = 1, lineout=None, axis=None,
                 pc_iters=None, pc_resid=None) -> dict:
+        bo = self._box_out(stack, stack_every, lineout, axis, pc_iters, pc_resid)
+        st = Stats()
+        self._call("qsp_run_box", C.byref(bo), C.byref(st))
+        return st.as_dict()
+
+    @staticmethod
+    def _box_out(stack, stack_every, lineout, axis, pc_iters, pc_resid) -> BoxOut:
         bo = BoxOut()
         bo.stack_every = stack_every
         for q, t in (stack or {}).items():
@@ -300,9 +313,37 @@ class Box:
             bo.axis[QID[q]] = _ptr(t)
         bo.pc_iters = _ptr(pc_iters)
         bo.pc_resid = _ptr(pc_resid)
+        return bo
+
+    def record(self, n_slices: int, ckpt_every: int, stack=None, stack_every: int = 1,
+               lineout=None, axis=None, pc_iters=None, pc_resid=None) -> dict:
+        """Checkpointed forward pass of slices 0 .. n_slices-1 for ``adjoint``
+        (outputs as in ``run_box``)."""
+        bo = self._box_out(stack, stack_every, lineout, axis, pc_iters, pc_resid)
         st = Stats()
-        self._call("qsp_run_box", C.byref(bo), C.byref(st))
+        self._call("qsp_run_box_record", int(n_slices), int(ckpt_every), C.byref(bo),
+                   C.byref(st))
         return st.as_dict()
+
+    def adjoint(self, k_lo: int, cot: Dict[str, object]):
+        """Reverse pass of the last ``record``.  ``cot[q]``: device tensor
+        [n_slices - k_lo, ny+1, nx+1] (box precision) for field q.  Returns
+        (grad_amp [nzeta], grad_sigma [2], loss [1]) as float64 tensors."""
+        torch = self.torch
+        c = Cotangent()
+        c.k_lo = int(k_lo)
+        for q, t in cot.items():
+            if QID[q] >= 7:
+                raise ValueError(f"{q} is not a field")
+            if t.dtype != self.fdtype or t.device != self.device:
+                raise ValueError(f"cotangent {q}: wrong dtype/device")
+            c.w[QID[q]] = _ptr(t)
+        ga = torch.empty(self.cfg.nzeta, dtype=torch.float64, device=self.device)
+        gs = torch.empty(2, dtype=torch.float64, device=self.device)
+        loss = torch.empty(1, dtype=torch.float64, device=self.device)
+        self._call("qsp_run_box_adjoint", C.byref(c), C.c_void_p(_ptr(ga)), C.c_void_p(_ptr(gs)),
+                   C.c_void_p(_ptr(loss)))
+        return ga, gs, loss
 
     def stats(self) -> dict:
         st = Stats()
@@ -360,3 +401,59 @@ class Box:
 
 def status_string(s: int) -> str:
     return lib().qsp_status_string(s).decode()
+
+
+def _wake_fn():
+    import torch
+
+    class WakeFn(torch.autograd.Function):
+        """Wakefields of slices k_lo .. n_slices-1 as a differentiable
+        function of the Gaussian drive beam: per-slice amplitudes ``amp``
+        [nzeta] and transverse sizes ``sigma_x``, ``sigma_y``.
+
+        forward: set the beam, reset the plasma, checkpointed forward pass
+        (``Box.record``); returns [n_slices - k_lo, len(fields), ny+1, nx+1]
+        in the box precision.  backward: ``Box.adjoint`` with the incoming
+        gradient as cotangent.  One backward per forward (the record is
+        consumed)."""
+
+        @staticmethod
+        def forward(ctx, amp, sigma_x, sigma_y, box, n_slices, k_lo, fields, ckpt_every,
+                    x0=0.0, y0=0.0):
+            box.set_beam_gaussian(amp.detach().double().cpu().numpy(), float(sigma_x),
+                                  float(sigma_y), x0, y0)
+            box.init_plasma()
+            stack = {q: box.empty(q, n_slices) for q in fields}
+            box.record(n_slices, ckpt_every, stack=stack)
+            out = torch.stack([stack[q][k_lo:] for q in fields], dim=1)
+            ctx.box, ctx.fields, ctx.k_lo = box, tuple(fields), k_lo
+            ctx.amp_meta = (amp.dtype, amp.device)
+            ctx.sig_meta = [(s.dtype, s.device) if torch.is_tensor(s) else None
+                            for s in (sigma_x, sigma_y)]
+            return out
+
+        @staticmethod
+        def backward(ctx, g):
+            cot = {q: g[:, i].contiguous().to(ctx.box.fdtype) for i, q in enumerate(ctx.fields)}
+            ga, gs, _ = ctx.box.adjoint(ctx.k_lo, cot)
+            dt, dev = ctx.amp_meta
+            gsig = []
+            for i, meta in enumerate(ctx.sig_meta):
+                gsig.append(None if meta is None else gs[i].to(dtype=meta[0], device=meta[1]))
+            return (ga.to(dtype=dt, device=dev), gsig[0], gsig[1], None, None, None, None, None,
+                    None, None)
+
+    return WakeFn
+
+
+_WAKE = None
+
+
+def wake_fields(amp, sigma_x, sigma_y, box: "Box", n_slices: int, k_lo: int = 0,
+                fields=("ez",), ckpt_every: int = 16, x0: float = 0.0, y0: float = 0.0):
+    """Differentiable wakefields (see WakeFn)."""
+    global _WAKE
+    if _WAKE is None:
+        _WAKE = _wake_fn()
+    return _WAKE.apply(amp, sigma_x, sigma_y, box, n_slices, k_lo, tuple(fields), ckpt_every,
+                       x0, y0)

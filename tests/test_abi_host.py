@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 STRUCTS = {
     "qsp_config": Q.Config, "qsp_slice_out": Q.SliceOut, "qsp_box_out": Q.BoxOut,
     "qsp_stats": Q.Stats, "qsp_slice_state": Q.SliceState,
-    "qsp_kernel_times": Q.KernelTimes,
+    "qsp_kernel_times": Q.KernelTimes, "qsp_box_cotangent": Q.Cotangent,
 }
 
 
@@ -110,5 +110,7 @@ def test_status_strings():
 def test_null_context_is_an_error_not_a_crash():
     lib = Q.lib()
     assert lib.qsp_init_plasma(None) == Q.QSP_ERR_INVALID_ARG
+    assert lib.qsp_run_box_record(None, 1, 1, None, None) == Q.QSP_ERR_INVALID_ARG
+    assert lib.qsp_run_box_adjoint(None, None, None, None, None) == Q.QSP_ERR_INVALID_ARG
     assert lib.qsp_destroy(None) == Q.QSP_OK
     assert lib.qsp_last_error(None)
