@@ -92,6 +92,76 @@ def standalone_solves(box, cfg, reps: int = 50) -> float:
     return 3 * reps / (time.perf_counter() - t0)
 
 
+def adjoint_leg(name: str, precision: str, ckpt_every: int, reps: int = 2) -> dict:
+    """Forward+backward / forward on the adjoint workloads.
+
+    c4: 256 x 256 nodes, 512 slices, 1 plasma electron per cell, loss = mean
+    on-axis Ez over slices 400..420, gradients over 512 amplitudes and the
+    two beam sizes.  c5: 1024 x 1024 nodes, 2 x 2 electrons per cell (4.19M),
+    loss = witness-weighted Ez integral over the slices the witness covers.
+    Forward = the plain slice loop over the same slices; forward+backward =
+    checkpointed record + reverse pass (with the per-chunk recompute)."""
+    import torch
+    import workloads as W
+    from paper_2109_10277_amd import qsp
+    box_dtype = torch.float32 if precision == "fp32" else torch.float64
+    if name == "c4":
+        cfg, beam = W.c4()
+        k_lo, k_hi = W.C4_LOSS_SLICES
+        n = k_hi + 1
+        wts = torch.zeros(n - k_lo, cfg.ny + 1, cfg.nx + 1, dtype=box_dtype, device="cuda")
+        wts[:, cfg.ny // 2, cfg.nx // 2] = 1.0 / (n - k_lo)
+    else:
+        cfg, beam = W.c5()
+        k_lo, gz, gy, gx = W.witness_factors(cfg)
+        n = k_lo + len(gz)
+        dv = cfg.hx * cfg.hy * cfg.dzeta
+        t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
+        wts = (t(gz * dv)[:, None, None] * t(gy)[None, :, None] * t(gx)[None, None, :]).to(box_dtype)
+    box = qsp.Box(cfg, precision)
+    box.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
+    cot = {"ez": wts}
+    n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
+
+    def forward():
+        box.init_plasma()
+        for _ in range(n):
+            box.advance_slice()
+
+    def fwd_bwd():
+        box.init_plasma()
+        box.record(n, ckpt_every)
+        return box.adjoint(k_lo, cot)
+
+    fwd_bwd()                                    # allocation + warm-up
+    forward()
+    torch.cuda.synchronize()
+    t_f = t_r = t_a = 0.0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        forward()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        box.init_plasma()
+        box.record(n, ckpt_every)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        ga, gs, loss = box.adjoint(k_lo, cot)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        t_f, t_r, t_a = t_f + t1 - t0, t_r + t2 - t1, t_a + t3 - t2
+    mem = box.stats()["device_bytes"]
+    box.close()
+    return {"workload": f"{name}_{cfg.nx}x{cfg.ny}_{n}slices_{n_p}particles",
+            "precision": precision, "ckpt_every": ckpt_every,
+            "fwd_ms": t_f / reps * 1e3, "record_ms": t_r / reps * 1e3,
+            "reverse_ms": t_a / reps * 1e3,
+            "fwd_bwd_over_fwd": (t_r + t_a) / t_f,
+            "fwd_bwd_updates_per_s": n_p * n / ((t_r + t_a) / reps),
+            "device_bytes": mem, "loss": float(loss.cpu()[0]),
+            "grad_sigma": gs.cpu().tolist()}
+
+
 def cpu_baseline(cfg, beam, n_slices: int) -> dict:
     """The FP64 oracle on the host cores: the first n_slices slices of the
     same box, from the unperturbed plasma."""
@@ -121,6 +191,11 @@ def main():
     ap.add_argument("--cpu-slices", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint legs and print their JSON")
+    ap.add_argument("--adjoint-c5", default="",
+                    help="comma-separated checkpoint intervals for the c5 adjoint leg")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the slice loop of one box is not "
@@ -128,6 +203,12 @@ def main():
               "shard); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.adjoint_only:
+        legs = [] if args.no_adjoint else [adjoint_leg("c4", "fp32", 32)]
+        legs += [adjoint_leg("c5", "fp32", int(K), reps=1)
+                 for K in filter(None, args.adjoint_c5.split(","))]
+        print(json.dumps({"adjoint": legs}))
+        return
     cfg, beam, wname = workload(args.workload)
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     box, dt, stats, kt = run_gpu(cfg, beam, "fp32", args.steps, args.warmup,
@@ -158,6 +239,7 @@ def main():
         "pc_iterations_per_slice": sum(s["pc_iterations"] for s in stats) / (cfg.nzeta * args.steps),
         "kernel_ms_per_step": {c: kt[c][0] / args.steps * args.timing_every for c in kt},
         "fwd_bwd_over_fwd": None,
+        "adjoint": None,
         "roofline": {"bound": "hbm", "kernel": "gather+push+deposit (real push)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -170,6 +252,12 @@ def main():
         v64 = n_p * cfg.nzeta * max(1, args.steps // 2) / dt64
         out["fp64_value"] = v64
         out["fp32_over_fp64"] = value / v64
+    if not args.no_adjoint:
+        adj = adjoint_leg("c4", "fp32", 32)
+        out["fwd_bwd_over_fwd"] = adj["fwd_bwd_over_fwd"]
+        out["adjoint"] = [adj]
+        for K in filter(None, args.adjoint_c5.split(",")):
+            out["adjoint"].append(adjoint_leg("c5", "fp32", int(K), reps=1))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, beam, args.cpu_slices)
     print(json.dumps(out))

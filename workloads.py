@@ -140,6 +140,23 @@ C3_GAMMA = 2000.0
 BEAM_DT = 6.0     # beam time step, omega_p^-1 (Appendix)
 
 
+def witness_factors(cfg: BoxConfig, rel_cut: float = 1e-10):
+    """Separable factors of ``witness_profile`` restricted to the slices
+    where the longitudinal factor exceeds rel_cut * peak: returns
+    (k_lo, gz [k_hi-k_lo+1], gy [ny+1], gx [nx+1]) with
+    n_w[k, j, i] = gz[k - k_lo] * gy[j] * gx[i]."""
+    x = cfg.x_lo + cfg.hx * np.arange(cfg.nx + 1)
+    y = cfg.y_lo + cfg.hy * np.arange(cfg.ny + 1)
+    z = cfg.zeta()
+    p = C3_WITNESS
+    gz = p["peak"] * np.exp(-(z - p["zeta_c"]) ** 2 / (2 * p["sigma_z"] ** 2))
+    keep = np.nonzero(gz > rel_cut * p["peak"])[0]
+    k_lo, k_hi = int(keep[0]), int(keep[-1])
+    gx = np.exp(-x ** 2 / (2 * p["sigma_r"] ** 2))
+    gy = np.exp(-y ** 2 / (2 * p["sigma_r"] ** 2))
+    return k_lo, gz[k_lo:k_hi + 1], gy, gx
+
+
 def c3_config(n: int = 1024, nzeta: int = 1024) -> BoxConfig:
     return BoxConfig(nx=n, ny=n, x_lo=-8.0, x_hi=8.0, y_lo=-8.0, y_hi=8.0,
                      nzeta=nzeta, zeta_hi=5.0, dzeta=12.0 / nzeta,
