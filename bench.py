@@ -28,6 +28,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+# HBM bytes per real-push launch at c2 FP32 from the FETCH_SIZE / WRITE_SIZE
+# counter runs (scaled by a 256 MiB copy), valid for the push kernel source
+# with this sha256 prefix
+PUSH_TRAFFIC = {"source": "paper_2109_10277_amd/csrc/particles.hip",
+                "sha256_prefix": "8a04a4635963ef38", "workload": "c2", "bytes": 68.53e6,
+                "summary": "profiles/hbm_traffic_c2_blowout_512x512x1024_fp32.md"}
+
+
+def push_traffic(workload_name: str):
+    """Counter-measured bytes per launch, or None once the kernel changed."""
+    import hashlib
+    if not workload_name.startswith(PUSH_TRAFFIC["workload"] + "_"):
+        return None
+    with open(os.path.join(ROOT, PUSH_TRAFFIC["source"]), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    return PUSH_TRAFFIC["bytes"] if sha.startswith(PUSH_TRAFFIC["sha256_prefix"]) else None
 METRIC = "plasma particle-slice updates/s + DST solves/s; FP32 vs FP64; fwd+bwd/fwd ratio"
 
 
@@ -192,6 +209,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB five times "
+                         "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint legs and print their JSON")
     ap.add_argument("--adjoint-c5", default="",
@@ -203,6 +223,17 @@ def main():
               "shard); rerun with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
     if args.adjoint_only:
         legs = [] if args.no_adjoint else [adjoint_leg("c4", "fp32", 32)]
         legs += [adjoint_leg("c5", "fp32", int(K), reps=1)
@@ -218,7 +249,7 @@ def main():
     solves = sum(s["dst_solves"] for s in stats)
     dst_ms = sum(kt[c][0] for c in ("row_fwd", "col", "row_inv"))
     push_ms, push_n = kt["push"]
-    push_avg_ms = push_ms / max(push_n, 1)
+    push_avg_ms = push_ms / max(push_n, 1) if push_n else float("nan")
     bytes_launch = push_bytes(cfg, 4)
     achieved = bytes_launch / (push_avg_ms * 1e-3) / 1e9
     standalone = standalone_solves(box, cfg)
@@ -242,7 +273,7 @@ def main():
         "adjoint": None,
         "roofline": {"bound": "hbm", "kernel": "gather+push+deposit (real push)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": push_traffic(wname),
                      "bytes_per_launch": bytes_launch,
                      "avg_launch_ms": push_avg_ms, "launches_timed": push_n},
     }

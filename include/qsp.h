@@ -216,6 +216,17 @@ qsp_status qsp_set_beam_gaussian(qsp_ctx ctx, const double* amp, double sx,
 qsp_status qsp_set_beam_particles(qsp_ctx ctx, int64_t n, const float* soa,
                                   double dt);
 
+/* Explicit drive-beam current of slice k (Sec. II step 3, the beam as a
+ * given source): an ultra-relativistic beam with rho_b = Jz_b = jz and
+ * J_perp,b = 0, added to the plasma deposit of slice k together with any
+ * Gaussian or macro-particle beam.  jz: device array [ny+1][nx+1] of double
+ * in node layout (copied; boundary entries ignored), or NULL to remove the
+ * current of slice k; k = -1 with jz = NULL removes every slice's current.
+ * Each stored slice holds nx*ny doubles of device memory (mem_cap_bytes
+ * applies).  Errors: k outside [0, nzeta) (other than the -1 form) ->
+ * QSP_ERR_INVALID_ARG. */
+qsp_status qsp_set_beam_current(qsp_ctx ctx, int32_t k, const double* jz);
+
 /* Copies the particle beam back (device array [7][n] of float in the sorted
  * order; n must equal the stored count, see qsp_get_beam_count).
  * Synchronises. */

@@ -164,6 +164,19 @@ qsp_status qsp_advance_slice(qsp_ctx ctx, const qsp_slice_out* out) {
   });
 }
 
+qsp_status qsp_set_beam_current(qsp_ctx ctx, int32_t k, const double* jz) {
+  return guarded(ctx, [&] {
+    if (k == -1 && !jz) {
+      ctx->box->clear_beam_currents();
+      return QSP_OK;
+    }
+    if (k < 0 || k >= ctx->box->config().nzeta)
+      return fail(ctx, QSP_ERR_INVALID_ARG, "slice index outside [0, nzeta)");
+    ctx->box->set_beam_current(k, jz);
+    return QSP_OK;
+  });
+}
+
 qsp_status qsp_run_box(qsp_ctx ctx, const qsp_box_out* out, qsp_stats* stats) {
   return guarded(ctx, [&] {
     if (!ctx->box->initialised()) return fail(ctx, QSP_ERR_BAD_STATE, "plasma not initialised");

@@ -38,6 +38,17 @@ __global__ void k_guess(size_t n, T* bx, T* by, const T* bx1, const T* by1, cons
   }
 }
 
+// explicit beam current of a slice: an ultra-relativistic beam has
+// rho_b = Jz_b, so the plane is added to both channels
+__global__ void k_add_current(size_t n, const double* src, double* jz, double* rho) {
+  for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<size_t>(gridDim.x) * blockDim.x) {
+    const double v = src[i];
+    jz[i] += v;
+    rho[i] += v;
+  }
+}
+
 __global__ void k_slice_end(DevCounters* ctr, int32_t* iters_out, double* resid_out,
                             double tol, int max_iter) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -150,6 +161,11 @@ void launch_guess(const Geom& g, T* bx, T* by, const T* bx1, const T* by1, const
   const size_t n = static_cast<size_t>(g.nx) * g.ny;
   hipLaunchKernelGGL(k_guess<T>, grid_for(n), dim3(kBlock), 0, st, n, bx, by, bx1, by1, bx2,
                      by2, ctr);
+  QSP_LAUNCH_CHECK();
+}
+
+void launch_add_current(size_t n, const double* src, double* jz, double* rho, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_current, grid_for(n), dim3(kBlock), 0, st, n, src, jz, rho);
   QSP_LAUNCH_CHECK();
 }
 

@@ -188,6 +188,7 @@ struct OutCopy {
   const double* bgy;
 };
 void launch_out_copy(const Geom&, const OutCopy&, hipStream_t);
+void launch_add_current(size_t n, const double* src, double* jz, double* rho, hipStream_t);
 
 template <typename S, typename T>
 void launch_from_nodes(const Geom&, const S* src, T* dst, hipStream_t);  // [ny+1][nx+1] -> stored

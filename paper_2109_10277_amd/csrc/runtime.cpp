@@ -180,6 +180,7 @@ class Box final : public BoxBase {
   ~Box() override {
     free_beam();
     free_adjoint();
+    clear_beam_currents();
     release();
   }
 
@@ -278,6 +279,47 @@ class Box final : public BoxBase {
   }
 
   int64_t beam_count() const override { return beam_n_; }
+
+  void set_beam_current(int k, const double* jz) override {
+    QSP_HIP(hipSetDevice(device_));
+    rec_valid_ = false;
+    if (cur_.empty()) cur_.assign(cfg_.nzeta, nullptr);
+    if (!jz) {
+      if (cur_[k]) {
+        QSP_HIP(hipStreamSynchronize(st_));
+        QSP_HIP(hipFree(cur_[k]));
+        cur_[k] = nullptr;
+        const int64_t b = static_cast<int64_t>(std::max<size_t>(plane() * sizeof(double), 256));
+        bytes_ -= b;
+      }
+      return;
+    }
+    if (!cur_[k]) {
+      const size_t bytes = std::max<size_t>(plane() * sizeof(double), 256);
+      if (cfg_.mem_cap_bytes > 0 && bytes_ + static_cast<int64_t>(bytes) > cfg_.mem_cap_bytes)
+        throw std::bad_alloc();
+      void* p = nullptr;
+      const hipError_t e = hipMalloc(&p, bytes);
+      if (e == hipErrorOutOfMemory) throw std::bad_alloc();
+      QSP_HIP(e);
+      cur_[k] = static_cast<double*>(p);
+      bytes_ += static_cast<int64_t>(bytes);
+    }
+    launch_from_nodes<double, double>(geom_, jz, cur_[k], st_);
+  }
+
+  void clear_beam_currents() override {
+    if (cur_.empty()) return;
+    (void)hipStreamSynchronize(st_);
+    const int64_t b = static_cast<int64_t>(std::max<size_t>(plane() * sizeof(double), 256));
+    for (double*& p : cur_)
+      if (p) {
+        (void)hipFree(p);
+        p = nullptr;
+        bytes_ -= b;
+      }
+    rec_valid_ = false;
+  }
 
   void get_stats(qsp_stats* s) override {
     DevCounters c{};
@@ -1074,6 +1116,9 @@ class Box final : public BoxBase {
         launch_beam_deposit(geom_, beam_soa_, beam_n_, b0, bcount, cfg_.dzeta, dc[0], dc[3], dc[4],
                             st_);
       });
+    // explicit beam current of slice k
+    if (!cur_.empty() && cur_[k])
+      timed(QSP_K_OTHER, [&] { launch_add_current(pl, cur_[k], dc[3], dc[4], st_); });
     // psi, Ez, Bz (Sec. II steps 4-6)
     {
       SrcPEZ<T> s{dc[0], dc[1], dc[2], cfg_.n0, t1_};
@@ -1222,6 +1267,7 @@ class Box final : public BoxBase {
   bool beam_dirty_ = false;
   BeamScratch bs_{};
   std::vector<int64_t> beam_off_;
+  std::vector<double*> cur_;          // explicit beam current per slice (or null)
   std::vector<void*> allocs_;
   int64_t bytes_ = 0;
   T *psi_ = nullptr, *exmby_ = nullptr, *eypbx_ = nullptr, *ez_ = nullptr, *bz_ = nullptr;

@@ -32,6 +32,9 @@ class BoxBase {
   virtual void set_state(const qsp_slice_state* src) = 0;
   virtual void set_deposit_tiled(bool on) = 0;
   virtual void set_beam_particles(int64_t n, const float* soa, double dt) = 0;
+  // explicit Jz (= rho) of slice k, node layout FP64 on the device; NULL removes it
+  virtual void set_beam_current(int k, const double* jz) = 0;
+  virtual void clear_beam_currents() = 0;
   virtual void get_beam_particles(float* soa) = 0;
   virtual int64_t beam_count() const = 0;
   virtual void solve_poisson(int nbatch, const void* src, void* dst, double shift) = 0;

@@ -116,6 +116,7 @@ def lib() -> C.CDLL:
             "qsp_init_plasma": [vp],
             "qsp_set_beam_gaussian": [vp, _DP, d, d, d, d],
             "qsp_set_beam_particles": [vp, i64, vp, d],
+            "qsp_set_beam_current": [vp, i32, vp],
             "qsp_get_beam_particles": [vp, i64, vp],
             "qsp_get_beam_count": [vp, C.POINTER(i64)],
             "qsp_advance_slice": [vp, C.POINTER(SliceOut)],
@@ -275,6 +276,16 @@ class Box:
         if soa.dtype != self.torch.float32 or soa.dim() != 2 or soa.shape[0] != 7:
             raise ValueError("soa must be float32 [7, n]")
         self._call("qsp_set_beam_particles", int(soa.shape[1]), C.c_void_p(_ptr(soa)), float(dt))
+
+    def set_beam_current(self, k: int, jz=None):
+        """Explicit Jz (= rho) of slice k: float64 device tensor [ny+1, nx+1]
+        (None removes it; k = -1 with None removes all)."""
+        if jz is not None:
+            if jz.dtype != self.torch.float64 or tuple(jz.shape) != self.node_shape():
+                raise ValueError("jz must be float64 [ny+1, nx+1]")
+            if jz.device != self.device:
+                raise ValueError("jz must be on the box device")
+        self._call("qsp_set_beam_current", int(k), C.c_void_p(_ptr(jz)))
 
     def beam_count(self) -> int:
         n = C.c_int64()

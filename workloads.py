@@ -140,6 +140,24 @@ C3_GAMMA = 2000.0
 BEAM_DT = 6.0     # beam time step, omega_p^-1 (Appendix)
 
 
+def explicit_currents(cfg: BoxConfig, peak: float = 0.8, seed: int = SEED) -> np.ndarray:
+    """Per-slice beam current planes Jz (node layout, zero on the boundary)
+    that no Gaussian describes: an off-axis elliptical driver plus a weaker
+    displaced satellite, with a seeded per-slice amplitude jitter.  Shape
+    [nzeta, ny+1, nx+1]; Jz < 0 (electrons moving along +z)."""
+    x = cfg.x_lo + cfg.hx * np.arange(cfg.nx + 1)
+    y = cfg.y_lo + cfg.hy * np.arange(cfg.ny + 1)
+    X, Y = np.meshgrid(x, y)
+    main = np.exp(-(X - 0.4) ** 2 / 0.5 - Y ** 2 / 0.9)
+    sat = 0.3 * np.exp(-((X + 1.0) ** 2 + (Y - 0.7) ** 2) / 0.3)
+    rng = np.random.default_rng(seed + 1)
+    env = gaussian_envelope(cfg, peak, -1.0, 0.7) * (1.0 + 0.1 * rng.uniform(-1, 1, cfg.nzeta))
+    J = -env[:, None, None] * (main + sat)[None]
+    J[:, 0, :] = J[:, -1, :] = 0.0
+    J[:, :, 0] = J[:, :, -1] = 0.0
+    return J
+
+
 def witness_factors(cfg: BoxConfig, rel_cut: float = 1e-10):
     """Separable factors of ``witness_profile`` restricted to the slices
     where the longitudinal factor exceeds rel_cut * peak: returns
