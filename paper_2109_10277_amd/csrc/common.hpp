@@ -53,6 +53,7 @@ struct Geom {
   int nx, ny;            // cells = nodes per stored row/column
   int lx, ly;            // log2(nx), log2(ny)
   double x_lo, y_lo, hx, hy;
+  int rr;                // rows per workgroup of the transform row passes
 };
 
 // Plasma lattice: (nx*ppc_x) x (ny*ppc_y) sites, particle p = I + J*nX.

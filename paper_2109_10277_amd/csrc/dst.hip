@@ -23,6 +23,7 @@
 //   eigenvalue division of P2.
 #include <cstdlib>
 #include <stdexcept>
+#include <type_traits>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -57,254 +58,337 @@ struct Pad {
   }
 };
 
-// In-place Stockham FFT (forward, e^{-2 pi i jk/n}) of `nfft` sequences of
-// length n = 2^logn; sequence f starts at buf + f*pitch (complex units).
-// tw[m] = e^{-2 pi i m / n}.  MAXB bounds the radix-4 butterflies per thread.
-template <typename T, int MAXB>
-__device__ void block_fft(Cplx<T>* buf, int logn, int nfft, int pitch,
-                          const Cplx<T>* __restrict__ tw) {
-  using P = Pad<T>;
-  const int n = 1 << logn;
-  const int tid = threadIdx.x;
-  int ns = 1;
-  int lns = 0;
-  while (lns + 2 <= logn) {
-    const int q = n >> 2;             // butterflies per sequence
-    const int nbf = q * nfft;
-    Cplx<T> v[MAXB][4];
+// ---------------------------------------------------------------------------
+// Wave-level transforms.  Each wavefront owns a group of P row pairs
+// (P * n >= 512 complex points, P = max(1, 512 / n)) and transforms them in
+// its own part of LDS: no workgroup barrier inside a transform.  LDS
+// operations of one wavefront execute in order, so a wave-local exchange
+// only needs the compiler kept from reordering across the sync point.
+// ---------------------------------------------------------------------------
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T>
+__device__ inline Cplx<T> cadd(Cplx<T> a, Cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ inline Cplx<T> csub(Cplx<T> a, Cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ inline Cplx<T> cmul_mi(Cplx<T> a) { return {a.im, -a.re}; }   // -i a
+
+// in-place DFT of length 4 (forward)
+template <typename T>
+__device__ __forceinline__ void dft4(Cplx<T>& y0, Cplx<T>& y1, Cplx<T>& y2, Cplx<T>& y3) {
+  const Cplx<T> c0 = cadd(y0, y2), c1 = csub(y0, y2), c2 = cadd(y1, y3);
+  const Cplx<T> c3 = cmul_mi(csub(y1, y3));
+  y0 = cadd(c0, c2);
+  y2 = csub(c0, c2);
+  y1 = cadd(c1, c3);
+  y3 = csub(c1, c3);
+}
+
+// in-place DFT of length 8 (forward), natural order in and out
+template <typename T>
+__device__ __forceinline__ void dft8(Cplx<T>* v) {
+  const T h = T(0.70710678118654752440);
+  Cplx<T> a[4], b[4];
 #pragma unroll
-    for (int it = 0; it < MAXB; ++it) {
-      const int b = tid + it * kBlock;
-      if (b < nbf) {
-        const int f = b >> (logn - 2);
-        const int j = b & (q - 1);
-        const int k = j & (ns - 1);
-        Cplx<T>* s = buf + f * pitch;
-        const int step = k << (logn - 2 - lns);   // k * n / (4 ns)
-        v[it][0] = s[P::cidx(j)];
-        v[it][1] = cmul(s[P::cidx(j + q)], tw[step]);
-        v[it][2] = cmul(s[P::cidx(j + 2 * q)], tw[2 * step]);
-        v[it][3] = cmul(s[P::cidx(j + 3 * q)], tw[3 * step]);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < MAXB; ++it) {
-      const int b = tid + it * kBlock;
-      if (b < nbf) {
-        const Cplx<T> a0 = v[it][0], a1 = v[it][1], a2 = v[it][2], a3 = v[it][3];
-        const Cplx<T> s02 = {a0.re + a2.re, a0.im + a2.im};
-        const Cplx<T> d02 = {a0.re - a2.re, a0.im - a2.im};
-        const Cplx<T> s13 = {a1.re + a3.re, a1.im + a3.im};
-        const Cplx<T> d13 = {a1.re - a3.re, a1.im - a3.im};
-        const int f = b >> (logn - 2);
-        const int j = b & (q - 1);
-        const int d0 = ((j >> lns) << (lns + 2)) + (j & (ns - 1));
-        Cplx<T>* o = buf + f * pitch;
-        o[P::cidx(d0)] = {s02.re + s13.re, s02.im + s13.im};
-        o[P::cidx(d0 + ns)] = {d02.re + d13.im, d02.im - d13.re};       // a0 - i a1 - a2 + i a3
-        o[P::cidx(d0 + 2 * ns)] = {s02.re - s13.re, s02.im - s13.im};
-        o[P::cidx(d0 + 3 * ns)] = {d02.re - d13.im, d02.im + d13.re};   // a0 + i a1 - a2 - i a3
-      }
-    }
-    __syncthreads();
-    ns <<= 2;
-    lns += 2;
+  for (int m = 0; m < 4; ++m) {
+    a[m] = cadd(v[m], v[m + 4]);
+    b[m] = csub(v[m], v[m + 4]);
   }
-  if (lns < logn) {  // one radix-2 stage (ns = n/2)
-    const int h = n >> 1;
-    const int nbf = h * nfft;
-    Cplx<T> v[2 * MAXB][2];
+  // b_m *= e^{-2 pi i m / 8}
+  b[1] = {h * (b[1].re + b[1].im), h * (b[1].im - b[1].re)};
+  b[2] = cmul_mi(b[2]);
+  b[3] = {h * (b[3].im - b[3].re), -h * (b[3].re + b[3].im)};
+  dft4(a[0], a[1], a[2], a[3]);
+  dft4(b[0], b[1], b[2], b[3]);
 #pragma unroll
-    for (int it = 0; it < 2 * MAXB; ++it) {
-      const int b = tid + it * kBlock;
-      if (b < nbf) {
-        const int f = b >> (logn - 1);
-        const int j = b & (h - 1);
-        Cplx<T>* s = buf + f * pitch;
-        v[it][0] = s[P::cidx(j)];
-        v[it][1] = cmul(s[P::cidx(j + h)], tw[j]);    // k = j, step n/(2 ns) = 1
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < 2 * MAXB; ++it) {
-      const int b = tid + it * kBlock;
-      if (b < nbf) {
-        const int f = b >> (logn - 1);
-        const int j = b & (h - 1);
-        Cplx<T>* o = buf + f * pitch;
-        o[P::cidx(j)] = {v[it][0].re + v[it][1].re, v[it][0].im + v[it][1].im};
-        o[P::cidx(j + h)] = {v[it][0].re - v[it][1].re, v[it][0].im - v[it][1].im};
-      }
-    }
-    __syncthreads();
+  for (int r = 0; r < 4; ++r) {
+    v[2 * r] = a[r];
+    v[2 * r + 1] = b[r];
   }
 }
 
-// Inclusive prefix sum over the odd entries (1, 3, ..., n-1) of each of the
-// nrow rows (row r at buf + (r/2)*ppitch + (r&1)*n, real units).
-template <typename T, int MAXC>
-__device__ void block_odd_scan(T* buf, int logn, int nrow, int ppitch, T* wsum) {
+// One Stockham pass of radix R (8, 4 or 2) over the npg sequences of a
+// group (sequence f at z + f*cp, complex units), stride ns = 8^.. so far:
+// butterfly j reads s[j + m n/R] * w^(m k n/(R ns)) (k = j mod ns) and
+// writes its DFT_R outputs to s[(j/ns) R ns + k + r ns].  NB bounds the
+// butterflies per lane.
+template <typename T, int R, int NB, int logn, int lns>
+__device__ __forceinline__ void wave_pass(Cplx<T>* z, int cp, int npg, const Cplx<T>* __restrict__ tw) {
   using P = Pad<T>;
-  const int n = 1 << logn;
-  const int half = n >> 1;
-  const int total = nrow * half;
-  const int tid = threadIdx.x;
-  // chunk of c consecutive odd entries of one row per thread
-  const int c = total >= kBlock ? total / kBlock : 1;
-  const int active = total / c;                // threads holding a chunk
-  const int tpr = half / c;                    // threads per row (power of 2)
-  T loc[MAXC];
-  T run = 0;
-  int row = 0, q0 = 0;
-  if (tid < active) {
-    row = (tid * c) / half;
-    q0 = (tid * c) % half;
-    T* r = buf + (row >> 1) * ppitch + (row & 1) * P::rlen(n);
+  constexpr int LR = R == 8 ? 3 : (R == 4 ? 2 : 1);
+  const int lane = threadIdx.x & 63;
+  constexpr int n = 1 << logn;
+  constexpr int q = n >> LR;
+  constexpr int ns = 1 << lns;
+  const int nbf = q * npg;
+  Cplx<T> v[NB][R];
 #pragma unroll
-    for (int t = 0; t < MAXC; ++t) {
-      if (t < c) {
-        run += r[P::ridx(2 * (q0 + t) + 1)];
-        loc[t] = run;
-      }
+  for (int it = 0; it < NB; ++it) {
+    const int b = lane + it * 64;
+    if (b < nbf) {
+      const int f = b >> (logn - LR);
+      const int j = b & (q - 1);
+      const int k = j & (ns - 1);
+      const int step = k << (logn - LR - lns);
+      const Cplx<T>* s = z + f * cp;
+      v[it][0] = s[P::cidx(j)];
+#pragma unroll
+      for (int m = 1; m < R; ++m) v[it][m] = cmul(s[P::cidx(j + m * q)], tw[m * step]);
     }
   }
-  // inclusive scan of the chunk totals across the threads of each row
-  const int lane = tid & 63;
-  const int width = tpr < 64 ? tpr : 64;
-  T incl = run;
-  for (int off = 1; off < width; off <<= 1) {
-    const T o = __shfl_up(incl, off, 64);
-    if ((lane & (width - 1)) >= off) incl += o;
-  }
-  if (tpr > 64) {
-    const int wave = tid >> 6;
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    const int first = (wave / (tpr >> 6)) * (tpr >> 6);
-    T add = 0;
-    for (int w = first; w < wave; ++w) add += wsum[w];
-    incl += add;
-  }
-  const T excl = incl - run;
-  __syncthreads();   // every thread has read its inputs
-  if (tid < active) {
-    T* r = buf + (row >> 1) * ppitch + (row & 1) * P::rlen(n);
+  wave_sync();
 #pragma unroll
-    for (int t = 0; t < MAXC; ++t)
-      if (t < c) r[P::ridx(2 * (q0 + t) + 1)] = loc[t] + excl;
+  for (int it = 0; it < NB; ++it) {
+    const int b = lane + it * 64;
+    if (b < nbf) {
+      if (R == 8) dft8(v[it]);
+      if (R == 4) dft4(v[it][0], v[it][1], v[it][2], v[it][3]);
+      if (R == 2) {
+        const Cplx<T> t0 = v[it][0];
+        v[it][0] = cadd(t0, v[it][1]);
+        v[it][1] = csub(t0, v[it][1]);
+      }
+      const int f = b >> (logn - LR);
+      const int j = b & (q - 1);
+      const int k = j & (ns - 1);
+      const int d0 = ((j >> lns) << (lns + LR)) + k;
+      Cplx<T>* o = z + f * cp;
+#pragma unroll
+      for (int r = 0; r < R; ++r) o[P::cidx(d0 + r * ns)] = v[it][r];
+    }
   }
-  __syncthreads();
+  wave_sync();
+}
+
+// Stockham passes after the first: radix 8 while three or more factors of
+// 2 are left, then one radix-4 or radix-2 pass (schedule fixed at compile
+// time, so every index is a constant shift)
+template <typename T, int E, int logn, int lns>
+__device__ __forceinline__ void wave_passes(Cplx<T>* z, int cp, int npg, const Cplx<T>* __restrict__ tw) {
+  if constexpr (lns + 3 <= logn) {
+    wave_pass<T, 8, E / 8, logn, lns>(z, cp, npg, tw);
+    wave_passes<T, E, logn, lns + 3>(z, cp, npg, tw);
+  } else if constexpr (lns + 2 == logn) {
+    wave_pass<T, 4, E / 4, logn, lns>(z, cp, npg, tw);
+  } else if constexpr (lns + 1 == logn) {
+    wave_pass<T, 2, E / 2, logn, lns>(z, cp, npg, tw);
+  }
+}
+
+// Type-I sine transform of the npg row pairs of one group, by one wave.
+// Pair f holds rows a (at g + f*ppitch) and b (at + rlen(n)), entry 0 = 0;
+// on return entry p of each row holds S_p.  E = complex points per lane.
+template <typename T, int E, int logn>
+__device__ __forceinline__ void wave_dst(T* g, int npg, int ppitch, const Cplx<T>* __restrict__ tw,
+                         const T* __restrict__ pre) {
+  using P = Pad<T>;
+  const int lane = threadIdx.x & 63;
+  constexpr int n = 1 << logn;
+  const int cp = ppitch / 2;
+  Cplx<T>* z = reinterpret_cast<Cplx<T>*>(g);
+  // A + first radix-8 pass: pre-twiddle straight into the butterfly inputs
+  // (the first pass has no twiddles: k = 0)
+  {
+    constexpr int NB = E / 8;
+    constexpr int q = n >> 3;
+    const int nbf = q * npg;
+    Cplx<T> v[NB][8];
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int b = lane + it * 64;
+      if (b < nbf) {
+        const int f = b >> (logn - 3);
+        const int j = b & (q - 1);
+        const T* ra = g + f * ppitch;
+        const T* rb = ra + P::rlen(n);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int p = j + m * q;
+          const T s = pre[p];
+          const T a0 = ra[P::ridx(p)], b0 = rb[P::ridx(p)];
+          const T a1 = p ? ra[P::ridx(n - p)] : T(0);
+          const T b1 = p ? rb[P::ridx(n - p)] : T(0);
+          v[it][m] = {s * (a0 + a1) + T(0.5) * (a0 - a1), s * (b0 + b1) + T(0.5) * (b0 - b1)};
+        }
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int it = 0; it < NB; ++it) {
+      const int b = lane + it * 64;
+      if (b < nbf) {
+        dft8(v[it]);
+        const int f = b >> (logn - 3);
+        const int j = b & (q - 1);
+        Cplx<T>* o = z + f * cp;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) o[P::cidx(8 * j + r)] = v[it][r];
+      }
+    }
+    wave_sync();
+  }
+  wave_passes<T, E, logn, 3>(z, cp, npg, tw);
+  // C: unpack the two real spectra; even outputs directly, odd ones as the
+  //    increments of the prefix sum
+  {
+    constexpr int NQ = E / 2;
+    constexpr int h = n >> 1;
+    const int nq = h * npg;
+    T sa[NQ], ra_[NQ], sb[NQ], rb_[NQ];
+#pragma unroll
+    for (int it = 0; it < NQ; ++it) {
+      const int e = lane + it * 64;
+      if (e < nq) {
+        const int f = e >> (logn - 1);
+        const int q = e & (h - 1);
+        const Cplx<T>* zz = z + f * cp;
+        const Cplx<T> zq = zz[P::cidx(q)];
+        const Cplx<T> zm = zz[P::cidx((n - q) & (n - 1))];
+        sa[it] = q ? T(0.5) * (zm.im - zq.im) : T(0);
+        sb[it] = q ? T(0.5) * (zq.re - zm.re) : T(0);
+        ra_[it] = q ? T(0.5) * (zq.re + zm.re) : T(0.5) * zq.re;
+        rb_[it] = q ? T(0.5) * (zq.im + zm.im) : T(0.5) * zq.im;
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int it = 0; it < NQ; ++it) {
+      const int e = lane + it * 64;
+      if (e < nq) {
+        const int f = e >> (logn - 1);
+        const int q = e & (h - 1);
+        T* a = g + f * ppitch;
+        T* b = a + P::rlen(n);
+        a[P::ridx(2 * q)] = sa[it];
+        a[P::ridx(2 * q + 1)] = ra_[it];
+        b[P::ridx(2 * q)] = sb[it];
+        b[P::ridx(2 * q + 1)] = rb_[it];
+      }
+    }
+    wave_sync();
+  }
+  // D: odd outputs = inclusive prefix sums of the odd entries, per row.
+  //    The 2*npg rows of the group hold n/2 odd entries each; a lane takes
+  //    c = E/... consecutive entries of one row, the lanes of a row scan
+  //    their chunk totals with shuffles.
+  {
+    constexpr int h = n >> 1;
+    const int total = 2 * npg * h;              // odd entries in the group
+    const int c = total >= 64 ? total / 64 : 1; // entries per lane
+    const int active = total / c;
+    const int tpr = h / c;                      // lanes per row (power of 2, <= 64)
+    T loc[E];
+    T run = T(0);
+    int row = 0, q0 = 0;
+    if (lane < active) {
+      row = (lane * c) / h;
+      q0 = (lane * c) % h;
+      T* r = g + (row >> 1) * ppitch + (row & 1) * P::rlen(n);
+#pragma unroll
+      for (int t = 0; t < E; ++t) {
+        if (t < c) {
+          run += r[P::ridx(2 * (q0 + t) + 1)];
+          loc[t] = run;
+        }
+      }
+    }
+    T incl = run;
+    for (int off = 1; off < tpr; off <<= 1) {
+      const T o = __shfl_up(incl, off, 64);
+      if ((lane & (tpr - 1)) >= off) incl += o;
+    }
+    const T excl = incl - run;
+    wave_sync();
+    if (lane < active) {
+      T* r = g + (row >> 1) * ppitch + (row & 1) * P::rlen(n);
+#pragma unroll
+      for (int t = 0; t < E; ++t)
+        if (t < c) r[P::ridx(2 * (q0 + t) + 1)] = loc[t] + excl;
+    }
+    wave_sync();
+  }
 }
 
 // Type-I sine transform of nrow rows (nrow even) of length n = 2^logn held
 // in LDS; pair f = rows (2f, 2f+1) occupies buf[f*ppitch .. f*ppitch + 2n)
 // (row 2f first).  Entry 0 of every input row must be 0; on output entry p
-// holds S_p (entry 0 = 0).  MAXC bounds the complex elements per thread.
-template <typename T, int MAXC>
-__device__ void block_dst(T* buf, int logn, int nrow, int ppitch,
-                          const Cplx<T>* __restrict__ tw, const T* __restrict__ pre,
-                          T* wsum) {
-  using P = Pad<T>;
-  const int n = 1 << logn;
-  const int tid = threadIdx.x;
+// holds S_p (entry 0 = 0).  Groups of max(1, 512/n) pairs are handed to the
+// workgroup's waves in turn; ends with a workgroup barrier.
+template <typename T, int LOGN>
+__device__ __forceinline__ void block_dst(T* buf, int logn, int nrow, int ppitch,
+                                          const Cplx<T>* __restrict__ tw,
+                                          const T* __restrict__ pre) {
+  constexpr int n = 1 << LOGN;
+  constexpr int per = n >= 512 ? 1 : 512 / n;
+  constexpr int E = n <= 512 ? 8 : n / 64;
+  (void)logn;
   const int npair = nrow >> 1;
-  const int ncplx = npair * n;
-  // A: pre-twiddle into packed complex rows
-  {
-    T ya[MAXC], yb[MAXC];
-#pragma unroll
-    for (int it = 0; it < MAXC; ++it) {
-      const int e = tid + it * kBlock;
-      if (e < ncplx) {
-        const int f = e >> logn;
-        const int j = e & (n - 1);
-        const T* ra = buf + f * ppitch;
-        const T* rb = ra + P::rlen(n);
-        const T s = pre[j];
-        const T a0 = ra[P::ridx(j)], b0 = rb[P::ridx(j)];
-        const T a1 = j ? ra[P::ridx(n - j)] : T(0);
-        const T b1 = j ? rb[P::ridx(n - j)] : T(0);
-        ya[it] = s * (a0 + a1) + T(0.5) * (a0 - a1);
-        yb[it] = s * (b0 + b1) + T(0.5) * (b0 - b1);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < MAXC; ++it) {
-      const int e = tid + it * kBlock;
-      if (e < ncplx) {
-        const int f = e >> logn;
-        const int j = e & (n - 1);
-        Cplx<T>* z = reinterpret_cast<Cplx<T>*>(buf + f * ppitch);
-        z[P::cidx(j)] = {ya[it], yb[it]};
-      }
-    }
-    __syncthreads();
+  const int ngroup = (npair + per - 1) / per;
+  const int wave = threadIdx.x >> 6;
+  const int nwave = blockDim.x >> 6;
+  for (int gi = wave; gi < ngroup; gi += nwave) {
+    const int npg = min(per, npair - gi * per);
+    wave_dst<T, E, LOGN>(buf + static_cast<size_t>(gi) * per * ppitch, npg, ppitch, tw, pre);
   }
-  // B: complex FFTs of the packed pairs
-  block_fft<T, (MAXC + 3) / 4>(reinterpret_cast<Cplx<T>*>(buf), logn, npair,
-                               ppitch / 2, tw);
-  // C: unpack the two real spectra; even outputs directly, odd ones as the
-  //    increments of the prefix sum
-  {
-    constexpr int MQ = (MAXC + 1) / 2;
-    T sa[MQ], ra[MQ], sb[MQ], rb[MQ];
-    const int nq = npair * (n >> 1);
-#pragma unroll
-    for (int it = 0; it < MQ; ++it) {
-      const int e = tid + it * kBlock;
-      if (e < nq) {
-        const int f = e >> (logn - 1);
-        const int q = e & ((n >> 1) - 1);
-        const Cplx<T>* z = reinterpret_cast<const Cplx<T>*>(buf + f * ppitch);
-        const Cplx<T> zq = z[P::cidx(q)];
-        const Cplx<T> zm = z[P::cidx((n - q) & (n - 1))];
-        sa[it] = q ? T(0.5) * (zm.im - zq.im) : T(0);
-        sb[it] = q ? T(0.5) * (zq.re - zm.re) : T(0);
-        ra[it] = q ? T(0.5) * (zq.re + zm.re) : T(0.5) * zq.re;
-        rb[it] = q ? T(0.5) * (zq.im + zm.im) : T(0.5) * zq.im;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int it = 0; it < MQ; ++it) {
-      const int e = tid + it * kBlock;
-      if (e < nq) {
-        const int f = e >> (logn - 1);
-        const int q = e & ((n >> 1) - 1);
-        T* a = buf + f * ppitch;
-        T* b = a + P::rlen(n);
-        a[P::ridx(2 * q)] = sa[it];
-        a[P::ridx(2 * q + 1)] = ra[it];
-        b[P::ridx(2 * q)] = sb[it];
-        b[P::ridx(2 * q + 1)] = rb[it];
-      }
-    }
-    __syncthreads();
-  }
-  // D: odd outputs
-  block_odd_scan<T, MAXC>(buf, logn, nrow, ppitch, wsum);
+  __syncthreads();
 }
 
-// rows per row-pass workgroup: 2048 elements (at least two rows), at most ny
-__host__ __device__ inline int row_block_rows(int nx, int ny) {
-  const int r = nx >= 1024 ? 2 : 2048 / nx;
-  return r < ny ? r : ny;
+// Runs f(std::integral_constant<int, log2 n>) for the transform length n
+// (a power of two in [16, 2048]); every kernel is instantiated per length.
+template <typename F>
+void with_logn(int n, F&& f) {
+  switch (n) {
+    case 16: f(std::integral_constant<int, 4>{}); break;
+    case 32: f(std::integral_constant<int, 5>{}); break;
+    case 64: f(std::integral_constant<int, 6>{}); break;
+    case 128: f(std::integral_constant<int, 7>{}); break;
+    case 256: f(std::integral_constant<int, 8>{}); break;
+    case 512: f(std::integral_constant<int, 9>{}); break;
+    case 1024: f(std::integral_constant<int, 10>{}); break;
+    case 2048: f(std::integral_constant<int, 11>{}); break;
+    default: throw std::invalid_argument("transform length must be a power of two in [16, 2048]");
+  }
 }
 
-// columns per column-pass workgroup: at most a 32 KiB LDS strip and at most
-// 16 columns, and narrow enough that the pass has >= 512 workgroups
+template <typename T>
+__host__ __device__ inline size_t table_bytes(int n) {
+  return static_cast<size_t>(n) * (sizeof(Cplx<T>) + sizeof(T));
+}
+
+// Busy waves per workgroup of a transform pass: each wave transforms a group
+// of max(1, 512/n) row pairs.  The QSP_ROW_WAVES / QSP_COL_WAVES environment
+// variables (1, 2 or 4) override the defaults for tuning.
+inline int pass_waves(const char* env, int dflt) {
+  if (const char* e = std::getenv(env)) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) return v;
+  }
+  return dflt;
+}
+
+template <typename T>
+inline size_t pass_lds(int rows, int n) {
+  return static_cast<size_t>(rows / 2) * Pad<T>::pitch(n) * sizeof(T) + table_bytes<T>(n) +
+         static_cast<size_t>(n) * sizeof(double);
+}
+
+// columns per column-pass workgroup (even, at most nx, within 64 KiB of LDS)
 template <typename T>
 inline int col_strip(int nx, int ny, int nfield) {
-  const int lim = 32768 / static_cast<int>(sizeof(T));
-  int w = 16;
-  while (w > 2 && (w * ny > lim || (nx / w) * nfield < 512)) w >>= 1;
+  (void)nfield;
+  const int per = ny >= 512 ? 1 : 512 / ny;
+  int w = 2 * per * pass_waves("QSP_COL_WAVES", 1);
   if (const char* e = std::getenv("QSP_COL_W")) {   // tuning override
     const int v = std::atoi(e);
-    if (v >= 2 && v <= 16 && (v & (v - 1)) == 0 && v * ny <= lim) w = v;
+    if (v >= 2 && (v & (v - 1)) == 0) w = v;
   }
+  if (w > nx) w = nx;
+  while (w > 2 && pass_lds<T>(w, ny) > 65536) w >>= 1;
   return w;
 }
 
@@ -321,11 +405,6 @@ __device__ inline void stage_tables(const AxisTables<T>& t, int n, unsigned char
   }
   tw = stw;
   pre = spre;
-}
-
-template <typename T>
-__host__ __device__ inline size_t table_bytes(int n) {
-  return static_cast<size_t>(n) * (sizeof(Cplx<T>) + sizeof(T));
 }
 
 __device__ inline void zero_job(const ZeroJob& z) {
@@ -369,26 +448,60 @@ __device__ inline int xcd_strip(int b, int nstrip) {
   return (b & 7) * per + (b >> 3);
 }
 
-constexpr int kRowMaxC = 8;    // n <= 2048: 2 rows x 2048 / 512 complex per thread
-constexpr int kColMaxC = 16;
-constexpr int kRowMaxE = 16;   // row-pass elements per thread (2 rows of 2048)
-constexpr int kColMaxE = 32;   // column-pass elements per thread (32 KiB strip)
+// Workgroups per CU the transform kernels are compiled for: four (<= 128
+// VGPRs) while a lane holds at most 8 FP32 complex points, fewer for the
+// long FP64 transforms whose register arrays would otherwise spill.
+constexpr int dst_blocks_per_cu(int logn, int tsize) {
+  const int u = (logn <= 9 ? 8 : (1 << logn) / 64) * tsize / 4;
+  return u <= 8 ? 4 : (u <= 16 ? 2 : 1);
+}
+
+// Calls f(e) for the workgroup's elements e = threadIdx.x + it*kBlock,
+// e < total.  The whole multiples of kBlock run as unrolled straight-line
+// chunks of up to 8, so with a branch-free f the global loads of a chunk are
+// in flight together instead of one load latency per element.
+template <int CH, typename F>
+__device__ __forceinline__ void elem_chunk(int& it, F& f) {
+#pragma unroll
+  for (int u = 0; u < CH; ++u) f(static_cast<int>(threadIdx.x) + (it + u) * kBlock);
+  it += CH;
+}
+
+template <typename F>
+__device__ __forceinline__ void for_elems(int total, F&& f) {
+  const int nit = total / kBlock;   // uniform across the workgroup
+  int it = 0;
+  while (it + 8 <= nit) elem_chunk<8>(it, f);
+  if (nit & 4) elem_chunk<4>(it, f);
+  if (nit & 2) elem_chunk<2>(it, f);
+  if (nit & 1) elem_chunk<1>(it, f);
+  for (int e = nit * kBlock + static_cast<int>(threadIdx.x); e < total; e += kBlock) f(e);
+}
 
 }  // namespace
+
+// rows per row-pass workgroup (even, at most ny, within 144 KiB of LDS)
+template <typename T>
+int row_rows(int nx, int ny) {
+  const int per = nx >= 512 ? 1 : 512 / nx;
+  int r = 2 * per * pass_waves("QSP_ROW_WAVES", 2);
+  if (r > ny) r = ny;
+  while (r > 2 && pass_lds<T>(r, nx) > 147456) r >>= 1;
+  return r;
+}
 
 // ---------------------------------------------------------------------------
 // P1: sources + forward DST along x
 // ---------------------------------------------------------------------------
 
 // field ids of the psi / Ez / Bz batch
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  __shared__ T wsum[4];
   const int n = g.nx;
-  const int R = row_block_rows(n, g.ny);
+  const int R = g.rr;
   const int ppitch = Pad<T>::pitch(n);
   const Cplx<T>* tw;
   const T* pre;
@@ -396,51 +509,44 @@ k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
   const int j0 = blockIdx.x * R;
   const int fld = blockIdx.y;   // 0 psi, 1 Ez, 2 Bz
   const double ihx = 0.5 / g.hx, ihy = 0.5 / g.hy;
-#pragma unroll
-  for (int it = 0; it < kRowMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= R * n) break;
-    const int r = e / n, i = e % n;
+  const int lx = g.lx;
+  // neighbour indices are clamped so that every load is in bounds; values
+  // outside the interior are replaced by selects
+  for_elems(R * n, [&](int e) {
+    const int r = e >> lx, i = e & (n - 1);
     const int j = j0 + r;
-    double s = 0.0;
-    if (i > 0 && j > 0) {
-      const int o = j * n + i;
-      if (fld == 0) {
-        s = -(a.rho_mjz[o] + a.n0);
-      } else {
-        const double jx_e = i + 1 < n ? a.jx[o + 1] : 0.0, jx_w = a.jx[o - 1];
-        const double jy_e = i + 1 < n ? a.jy[o + 1] : 0.0, jy_w = a.jy[o - 1];
-        const double jx_n = j + 1 < g.ny ? a.jx[o + n] : 0.0, jx_s = a.jx[o - n];
-        const double jy_n = j + 1 < g.ny ? a.jy[o + n] : 0.0, jy_s = a.jy[o - n];
-        if (fld == 1)
-          s = (jx_e - jx_w) * ihx + (jy_n - jy_s) * ihy;
-        else
-          s = (jx_n - jx_s) * ihy - (jy_e - jy_w) * ihx;
-      }
+    const int o = j * n + i;
+    double s;
+    if (fld == 0) {
+      s = -(a.rho_mjz[o] + a.n0);
+    } else {
+      const int ow = i > 0 ? o - 1 : o, oe = i + 1 < n ? o + 1 : o;
+      const int os = j > 0 ? o - n : o, on = j + 1 < g.ny ? o + n : o;
+      const double xe = a.jx[oe], xw = a.jx[ow], xn = a.jx[on], xs = a.jx[os];
+      const double ye = a.jy[oe], yw = a.jy[ow], yn = a.jy[on], ys = a.jy[os];
+      const double jx_e = i + 1 < n ? xe : 0.0, jy_e = i + 1 < n ? ye : 0.0;
+      const double jx_n = j + 1 < g.ny ? xn : 0.0, jy_n = j + 1 < g.ny ? yn : 0.0;
+      s = fld == 1 ? (jx_e - xw) * ihx + (jy_n - ys) * ihy : (jx_n - xs) * ihy - (jy_e - yw) * ihx;
     }
-    buf[Pad<T>::rpos(n, ppitch, r, i)] = static_cast<T>(s);
-  }
+    buf[Pad<T>::rpos(n, ppitch, r, i)] = static_cast<T>((i > 0 && j > 0) ? s : 0.0);
+  });
   __syncthreads();
-  block_dst<T, kRowMaxC>(buf, g.lx, R, ppitch, tw, pre, wsum);
+  block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.out + static_cast<size_t>(fld) * g.nx * g.ny;
-#pragma unroll
-  for (int it = 0; it < kRowMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= R * n) break;
-    const int r = e / n, i = e % n;
+  for_elems(R * n, [&](int e) {
+    const int r = e >> lx, i = e & (n - 1);
     out[(j0 + r) * n + i] = buf[Pad<T>::rpos(n, ppitch, r, i)];
-  }
+  });
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_src_fwd_bxby(Geom g, SrcBxBy<T> a, AxisTables<T> tx, const DevCounters* ctr) {
   if (ctr->pc_done) return;
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  __shared__ T wsum[4];
   const int n = g.nx;
-  const int R = row_block_rows(n, g.ny);
+  const int R = g.rr;
   const int ppitch = Pad<T>::pitch(n);
   const Cplx<T>* tw;
   const T* pre;
@@ -449,62 +555,56 @@ k_src_fwd_bxby(Geom g, SrcBxBy<T> a, AxisTables<T> tx, const DevCounters* ctr) {
   const int fld = blockIdx.y;   // 0 Bx, 1 By
   const double ihx = 0.5 / g.hx, ihy = 0.5 / g.hy;
   const double idz = 0.5 / a.dzeta;
-#pragma unroll
-  for (int it = 0; it < kRowMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= R * n) break;
-    const int r = e / n, i = e % n;
+  const int lx = g.lx;
+  const double amp = a.beam_amp;
+  for_elems(R * n, [&](int e) {
+    const int r = e >> lx, i = e & (n - 1);
     const int j = j0 + r;
-    double s = 0.0;
-    if (i > 0 && j > 0) {
-      const int o = j * n + i;
-      if (fld == 0) {
-        // -d_y Jz + (Jy_{k-1} - Jy_{k+1}) / (2 dzeta) - shift * Bx_old
-        double jz_n = 0.0, jz_s = a.jz[o - n];
-        if (j + 1 < g.ny) jz_n = a.jz[o + n];
-        if (a.beam_amp != 0.0) {
-          jz_s -= a.beam_amp * a.bgx[i] * a.bgy[j - 1];
-          if (j + 1 < g.ny) jz_n -= a.beam_amp * a.bgx[i] * a.bgy[j + 1];
-        }
-        s = -(jz_n - jz_s) * ihy + (a.jy_prev[o] - a.jy_next[o]) * idz -
-            a.shift * static_cast<double>(a.bx[o]);
-      } else {
-        double jz_e = 0.0, jz_w = a.jz[o - 1];
-        if (i + 1 < n) jz_e = a.jz[o + 1];
-        if (a.beam_amp != 0.0) {
-          jz_w -= a.beam_amp * a.bgx[i - 1] * a.bgy[j];
-          if (i + 1 < n) jz_e -= a.beam_amp * a.bgx[i + 1] * a.bgy[j];
-        }
-        s = (jz_e - jz_w) * ihx - (a.jx_prev[o] - a.jx_next[o]) * idz -
-            a.shift * static_cast<double>(a.by[o]);
-      }
+    const int o = j * n + i;
+    double s;
+    if (fld == 0) {
+      // -d_y Jz + (Jy_{k-1} - Jy_{k+1}) / (2 dzeta) - shift * Bx_old
+      const int js = j > 0 ? j - 1 : 0;
+      const double zs = a.jz[js * n + i], zn = a.jz[(j + 1 < g.ny ? j + 1 : j) * n + i];
+      const double yp = a.jy_prev[o], yt = a.jy_next[o];
+      const double bo = static_cast<double>(a.bx[o]);
+      const double gx = a.bgx[i], gs = a.bgy[js], gn = a.bgy[j + 1];
+      const double jz_s = zs - amp * gx * gs;
+      const double jz_n = j + 1 < g.ny ? zn - amp * gx * gn : 0.0;
+      s = -(jz_n - jz_s) * ihy + (yp - yt) * idz - a.shift * bo;
+    } else {
+      // d_x Jz - (Jx_{k-1} - Jx_{k+1}) / (2 dzeta) - shift * By_old
+      const int iw = i > 0 ? i - 1 : 0;
+      const double zw = a.jz[j * n + iw], ze = a.jz[j * n + (i + 1 < n ? i + 1 : i)];
+      const double xp = a.jx_prev[o], xt = a.jx_next[o];
+      const double bo = static_cast<double>(a.by[o]);
+      const double gy = a.bgy[j], gw = a.bgx[iw], ge = a.bgx[i + 1];
+      const double jz_w = zw - amp * gw * gy;
+      const double jz_e = i + 1 < n ? ze - amp * ge * gy : 0.0;
+      s = (jz_e - jz_w) * ihx - (xp - xt) * idz - a.shift * bo;
     }
-    buf[Pad<T>::rpos(n, ppitch, r, i)] = static_cast<T>(s);
-  }
+    buf[Pad<T>::rpos(n, ppitch, r, i)] = static_cast<T>((i > 0 && j > 0) ? s : 0.0);
+  });
   __syncthreads();
-  block_dst<T, kRowMaxC>(buf, g.lx, R, ppitch, tw, pre, wsum);
+  block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.out + static_cast<size_t>(fld) * g.nx * g.ny;
-#pragma unroll
-  for (int it = 0; it < kRowMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= R * n) break;
-    const int r = e / n, i = e % n;
+  for_elems(R * n, [&](int e) {
+    const int r = e >> lx, i = e & (n - 1);
     out[(j0 + r) * n + i] = buf[Pad<T>::rpos(n, ppitch, r, i)];
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
 // P2: column strip solve
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_col_solve(Geom g, ColArgs<T> a, AxisTables<T> ty, const double* __restrict__ lamx,
             const DevCounters* ctr) {
   if (a.honor_done && ctr->pc_done) return;
   zero_job(a.zero);
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  __shared__ T wsum[4];
   const int ny = g.ny, nx = g.nx;
   const int W = a.w;
   const int ppitch = Pad<T>::pitch(ny);
@@ -518,60 +618,51 @@ k_col_solve(Geom g, ColArgs<T> a, AxisTables<T> ty, const double* __restrict__ l
   const int fld = blockIdx.y;
   const size_t plane = static_cast<size_t>(nx) * ny;
   const T* in = a.in + fld * plane;
-#pragma unroll
-  for (int it = 0; it < kColMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= W * ny) break;
-    const int c = e % W, j = e / W;
+  const int lw = 31 - __clz(W), ly = g.ly;
+  for_elems(W * ny, [&](int e) {
+    const int c = e & (W - 1), j = e >> lw;
     buf[Pad<T>::rpos(ny, ppitch, c, j)] = in[j * nx + p0 + c];
-  }
+  });
   __syncthreads();
-  block_dst<T, kColMaxC>(buf, g.ly, W, ppitch, tw, pre, wsum);
+  block_dst<T, LOGN>(buf, g.ly, W, ppitch, tw, pre);
   const double shift = a.shift[fld];
   const double norm = 4.0 / (static_cast<double>(nx) * ny);
-#pragma unroll
-  for (int it = 0; it < kColMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= W * ny) break;
-    const int c = e / ny, q = e % ny;
+  for_elems(W * ny, [&](int e) {
+    const int c = e >> ly, q = e & (ny - 1);
     const int p = p0 + c;
     T* r = buf + Pad<T>::rpos(ny, ppitch, c, 0);
     const double den = lamx[p] + slam[q] - shift;
     const int iq = Pad<T>::ridx(q);
-    r[iq] = (p > 0 && q > 0) ? static_cast<T>(static_cast<double>(r[iq]) * norm / den) : T(0);
-  }
+    const double v = static_cast<double>(r[iq]) * norm / den;
+    r[iq] = (p > 0 && q > 0) ? static_cast<T>(v) : T(0);
+  });
   __syncthreads();
-  block_dst<T, kColMaxC>(buf, g.ly, W, ppitch, tw, pre, wsum);
+  block_dst<T, LOGN>(buf, g.ly, W, ppitch, tw, pre);
   T* out = a.out + fld * plane;
-  const bool dy = (fld == 0) && a.out_dy != nullptr;
+  T* out_dy = (fld == 0) ? a.out_dy : nullptr;
   const T mihy = static_cast<T>(-0.5 / g.hy);
-#pragma unroll
-  for (int it = 0; it < kColMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= W * ny) break;
-    const int c = e % W, j = e / W;
+  for_elems(W * ny, [&](int e) {
+    const int c = e & (W - 1), j = e >> lw;
     const T* r = buf + Pad<T>::rpos(ny, ppitch, c, 0);
     out[j * nx + p0 + c] = r[Pad<T>::ridx(j)];
-    if (dy) {
-      T d = T(0);
-      if (j > 0)
-        d = mihy * ((j + 1 < ny ? r[Pad<T>::ridx(j + 1)] : T(0)) - r[Pad<T>::ridx(j - 1)]);
-      a.out_dy[j * nx + p0 + c] = d;
+    if (out_dy) {
+      const T up = r[Pad<T>::ridx(j + 1 < ny ? j + 1 : j)], dn = r[Pad<T>::ridx(j > 0 ? j - 1 : 0)];
+      const T d = mihy * ((j + 1 < ny ? up : T(0)) - dn);
+      out_dy[j * nx + p0 + c] = j > 0 ? d : T(0);
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
 // P3: inverse DST along x with epilogues
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  __shared__ T wsum[4];
   const int n = g.nx;
-  const int R = row_block_rows(n, g.ny);
+  const int R = g.rr;
   const int ppitch = Pad<T>::pitch(n);
   const Cplx<T>* tw;
   const T* pre;
@@ -579,52 +670,45 @@ k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   const int j0 = blockIdx.x * R;
   const int fld = blockIdx.y;
   const T* in = a.in[fld];
-#pragma unroll
-  for (int it = 0; it < kRowMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= R * n) break;
-    const int r = e / n, i = e % n;
+  const int lx = g.lx;
+  for_elems(R * n, [&](int e) {
+    const int r = e >> lx, i = e & (n - 1);
     buf[Pad<T>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
-  }
+  });
   __syncthreads();
-  block_dst<T, kRowMaxC>(buf, g.lx, R, ppitch, tw, pre, wsum);
+  block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   guess_job(a.guess, static_cast<size_t>(g.nx) * g.ny);
   T* out = a.out[fld];
   T* out_dx = a.out_dx[fld];
   const T mihx = static_cast<T>(-0.5 / g.hx);
-#pragma unroll
-  for (int it = 0; it < kRowMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= R * n) break;
-    const int r = e / n, i = e % n;
+  for_elems(R * n, [&](int e) {
+    const int r = e >> lx, i = e & (n - 1);
     const int j = j0 + r;
     const T* row = buf + Pad<T>::rpos(n, ppitch, r, 0);
-    const T u = j > 0 ? row[Pad<T>::ridx(i)] : T(0);
-    out[j * n + i] = u;
+    const T u = row[Pad<T>::ridx(i)];
+    out[j * n + i] = j > 0 ? u : T(0);
     if (out_dx) {
-      T d = T(0);
-      if (i > 0 && j > 0)
-        d = mihx * ((i + 1 < n ? row[Pad<T>::ridx(i + 1)] : T(0)) - row[Pad<T>::ridx(i - 1)]);
-      out_dx[j * n + i] = d;
+      const T ue = row[Pad<T>::ridx(i + 1 < n ? i + 1 : i)], uw = row[Pad<T>::ridx(i > 0 ? i - 1 : 0)];
+      const T d = mihx * ((i + 1 < n ? ue : T(0)) - uw);
+      out_dx[j * n + i] = (i > 0 && j > 0) ? d : T(0);
     }
-  }
+  });
 }
 
 // Predictor-corrector epilogue: B_new from the inverse transform, FP64 sums
 // of |B_new - B_old|^2 and |B_new|^2, B_old overwritten by B_new in place.
 // The last workgroup to finish forms the relative change and decides
 // convergence for the whole slice.
-template <typename T>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int LOGN>
+__global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_row_inv_pc(Geom g, PCArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   if (ctr->pc_done) return;
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  __shared__ T wsum[4];
   __shared__ double red[2][kBlock / 64];
   __shared__ bool last;
   const int n = g.nx;
-  const int R = row_block_rows(n, g.ny);
+  const int R = g.rr;
   const int ppitch = Pad<T>::pitch(n);
   const Cplx<T>* tw;
   const T* pre;
@@ -632,32 +716,28 @@ k_row_inv_pc(Geom g, PCArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   const int j0 = blockIdx.x * R;
   const int fld = blockIdx.y;   // 0 Bx, 1 By
   const T* in = a.in + static_cast<size_t>(fld) * g.nx * g.ny;
-#pragma unroll
-  for (int it = 0; it < kRowMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= R * n) break;
-    const int r = e / n, i = e % n;
+  const int lx = g.lx;
+  for_elems(R * n, [&](int e) {
+    const int r = e >> lx, i = e & (n - 1);
     buf[Pad<T>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
-  }
+  });
   __syncthreads();
-  block_dst<T, kRowMaxC>(buf, g.lx, R, ppitch, tw, pre, wsum);
+  block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* b = fld == 0 ? a.bx : a.by;
+  T* tp = fld == 0 ? a.tape_bx : a.tape_by;
   double dsum = 0.0, nsum = 0.0;
-#pragma unroll
-  for (int it = 0; it < kRowMaxE; ++it) {
-    const int e = threadIdx.x + it * kBlock;
-    if (e >= R * n) break;
-    const int r = e / n, i = e % n;
+  for_elems(R * n, [&](int e) {
+    const int r = e >> lx, i = e & (n - 1);
     const int j = j0 + r;
-    const T u = (j > 0) ? buf[Pad<T>::rpos(n, ppitch, r, i)] : T(0);
+    const T v = buf[Pad<T>::rpos(n, ppitch, r, i)];
+    const T u = j > 0 ? v : T(0);
     const double old = static_cast<double>(b[j * n + i]);
     const double d = static_cast<double>(u) - old;
     dsum += d * d;
     nsum += static_cast<double>(u) * static_cast<double>(u);
     b[j * n + i] = u;
-    T* tp = fld == 0 ? a.tape_bx : a.tape_by;
     if (tp) tp[j * n + i] = u;
-  }
+  });
   // workgroup reduction
   for (int off = 32; off > 0; off >>= 1) {
     dsum += __shfl_down(dsum, off, 64);
@@ -731,21 +811,27 @@ static void allow_lds(const void* fn, size_t lds) {
 template <typename T>
 void launch_src_fwd_pez(const Geom& g, const SrcPEZ<T>& a, const AxisTables<T>& tx,
                         hipStream_t st) {
-  const int R = row_block_rows(g.nx, g.ny);
+  const int R = g.rr;
   const size_t lds = static_cast<size_t>(R / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
-  allow_lds(reinterpret_cast<const void*>(&k_src_fwd_pez<T>), lds);
-  hipLaunchKernelGGL(k_src_fwd_pez<T>, dim3(g.ny / R, 3), dim3(kBlock), lds, st, g, a, tx);
+  with_logn(g.nx, [&](auto e) {
+    constexpr int E = decltype(e)::value;
+    allow_lds(reinterpret_cast<const void*>(&k_src_fwd_pez<T, E>), lds);
+    hipLaunchKernelGGL((k_src_fwd_pez<T, E>), dim3(g.ny / R, 3), dim3(kBlock), lds, st, g, a, tx);
+  });
   QSP_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_src_fwd_bxby(const Geom& g, const SrcBxBy<T>& a, const AxisTables<T>& tx,
                          const DevCounters* ctr, hipStream_t st) {
-  const int R = row_block_rows(g.nx, g.ny);
+  const int R = g.rr;
   const size_t lds = static_cast<size_t>(R / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
-  allow_lds(reinterpret_cast<const void*>(&k_src_fwd_bxby<T>), lds);
-  hipLaunchKernelGGL(k_src_fwd_bxby<T>, dim3(g.ny / R, 2), dim3(kBlock), lds, st, g, a, tx,
-                     ctr);
+  with_logn(g.nx, [&](auto e) {
+    constexpr int E = decltype(e)::value;
+    allow_lds(reinterpret_cast<const void*>(&k_src_fwd_bxby<T, E>), lds);
+    hipLaunchKernelGGL((k_src_fwd_bxby<T, E>), dim3(g.ny / R, 2), dim3(kBlock), lds, st, g, a, tx,
+                       ctr);
+  });
   QSP_LAUNCH_CHECK();
 }
 
@@ -757,33 +843,43 @@ void launch_col_solve(const Geom& g, const ColArgs<T>& a, int nfield, const Axis
     throw std::invalid_argument("column pass: bad strip width or field count");
   const size_t lds = static_cast<size_t>(W / 2) * Pad<T>::pitch(g.ny) * sizeof(T) + table_bytes<T>(g.ny) +
                      static_cast<size_t>(g.ny) * sizeof(double);
-  allow_lds(reinterpret_cast<const void*>(&k_col_solve<T>), lds);
-  hipLaunchKernelGGL(k_col_solve<T>, dim3(g.nx / W, nfield), dim3(kBlock), lds, st, g, a, ty,
-                     lamx, ctr);
+  with_logn(g.ny, [&](auto e) {
+    constexpr int E = decltype(e)::value;
+    allow_lds(reinterpret_cast<const void*>(&k_col_solve<T, E>), lds);
+    hipLaunchKernelGGL((k_col_solve<T, E>), dim3(g.nx / W, nfield), dim3(kBlock), lds, st, g, a,
+                       ty, lamx, ctr);
+  });
   QSP_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_row_inv(const Geom& g, const RowInvArgs<T>& a, int nfield, const AxisTables<T>& tx,
                     hipStream_t st) {
-  const int R = row_block_rows(g.nx, g.ny);
+  const int R = g.rr;
   const size_t lds = static_cast<size_t>(R / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
-  allow_lds(reinterpret_cast<const void*>(&k_row_inv<T>), lds);
-  hipLaunchKernelGGL(k_row_inv<T>, dim3(g.ny / R, nfield), dim3(kBlock), lds, st, g, a, tx);
+  with_logn(g.nx, [&](auto e) {
+    constexpr int E = decltype(e)::value;
+    allow_lds(reinterpret_cast<const void*>(&k_row_inv<T, E>), lds);
+    hipLaunchKernelGGL((k_row_inv<T, E>), dim3(g.ny / R, nfield), dim3(kBlock), lds, st, g, a, tx);
+  });
   QSP_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_row_inv_pc(const Geom& g, const PCArgs<T>& a, const AxisTables<T>& tx,
                        DevCounters* ctr, hipStream_t st) {
-  const int R = row_block_rows(g.nx, g.ny);
+  const int R = g.rr;
   const size_t lds = static_cast<size_t>(R / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
-  allow_lds(reinterpret_cast<const void*>(&k_row_inv_pc<T>), lds);
-  hipLaunchKernelGGL(k_row_inv_pc<T>, dim3(g.ny / R, 2), dim3(kBlock), lds, st, g, a, tx, ctr);
+  with_logn(g.nx, [&](auto e) {
+    constexpr int E = decltype(e)::value;
+    allow_lds(reinterpret_cast<const void*>(&k_row_inv_pc<T, E>), lds);
+    hipLaunchKernelGGL((k_row_inv_pc<T, E>), dim3(g.ny / R, 2), dim3(kBlock), lds, st, g, a, tx,
+                       ctr);
+  });
   QSP_LAUNCH_CHECK();
 }
 
-int pc_partial_count(const Geom& g) { return 2 * (g.ny / row_block_rows(g.nx, g.ny)); }
+int pc_partial_count(const Geom& g) { return 2 * (g.ny / g.rr); }
 
 template <typename T>
 int col_width(const Geom& g, int nfield) {
@@ -791,6 +887,8 @@ int col_width(const Geom& g, int nfield) {
 }
 template int col_width<float>(const Geom&, int);
 template int col_width<double>(const Geom&, int);
+template int row_rows<float>(int, int);
+template int row_rows<double>(int, int);
 
 #define QSP_INST(T)                                                                       \
   template void launch_src_fwd_pez<T>(const Geom&, const SrcPEZ<T>&, const AxisTables<T>&, \

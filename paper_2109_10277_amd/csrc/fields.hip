@@ -39,13 +39,14 @@ __global__ void k_guess(size_t n, T* bx, T* by, const T* bx1, const T* by1, cons
 }
 
 // explicit beam current of a slice: an ultra-relativistic beam has
-// rho_b = Jz_b, so the plane is added to both channels
+// rho_b = Jz_b and rho_b - Jz_b = 0, so the plane is added to Jz (and to a
+// separate rho channel if one is kept)
 __global__ void k_add_current(size_t n, const double* src, double* jz, double* rho) {
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
     const double v = src[i];
     jz[i] += v;
-    rho[i] += v;
+    if (rho) rho[i] += v;
   }
 }
 
@@ -86,6 +87,7 @@ __global__ void k_out_copy(Geom g, OutCopy c) {
       const size_t o = static_cast<size_t>(j) * nx + i;
       v = c.is_double[id] ? static_cast<const double*>(c.src[id])[o]
                           : static_cast<double>(static_cast<const float*>(c.src[id])[o]);
+      if (c.src2[id]) v += c.src2[id][o];
     }
     if (interior) {
       if (c.add_beam[id]) v -= c.beam_amp * c.bgx[i] * c.bgy[j];

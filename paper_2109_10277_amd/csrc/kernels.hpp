@@ -104,6 +104,9 @@ int pc_partial_count(const Geom&);
 // column-strip width of a column pass over nfield planes
 template <typename T>
 int col_width(const Geom&, int nfield);
+// rows per workgroup of the transform row passes (Geom::rr)
+template <typename T>
+int row_rows(int nx, int ny);
 
 // ---------------------------------------------------------------- particles
 template <typename T>
@@ -128,7 +131,7 @@ struct SliceFields {        // the six fields a particle sees
 };
 
 struct DepOut {
-  double* ch[5];            // rho-Jz, Jx, Jy, Jz, rho (rho may be null)
+  double* ch[4];            // rho-Jz, Jx, Jy, Jz (rho is formed as (rho - Jz) + Jz)
 };
 
 enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2 };
@@ -152,8 +155,8 @@ struct PushArgs {
 template <typename T>
 void launch_init_plasma(const Lattice&, const Particles<T>&, double w0, hipStream_t);
 template <typename T>
-void launch_push(const Geom&, const Lattice&, const PushArgs<T>&, PushMode, bool with_rho,
-                 DevCounters*, hipStream_t);
+void launch_push(const Geom&, const Lattice&, const PushArgs<T>&, PushMode, DevCounters*,
+                 hipStream_t);
 template <typename T>
 void launch_import_state(const Geom&, const Lattice&, const Particles<T>&, const double* x,
                          const double* y, const double* ux, const double* uy,
@@ -177,6 +180,7 @@ void launch_slice_end(DevCounters*, int32_t* iters_out, double* resid_out, doubl
 // copy a stored [ny][nx] grid into an [ny+1][nx+1] node array
 struct OutCopy {
   const void* src[kMaxOut];
+  const double* src2[kMaxOut];  // FP64 plane added to an FP64 source, may be null
   void* dst[kMaxOut];
   int is_double[kMaxOut];   // source precision (the destination matches it)
   int add_beam[kMaxOut];    // add -n_b (Jz, rho outputs of a Gaussian beam)

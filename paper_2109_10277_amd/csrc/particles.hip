@@ -100,7 +100,9 @@ __device__ inline unsigned long long block_sum(unsigned int v, unsigned int* red
 
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock)
-k_push(Geom g, Lattice L, PushArgs<T> a, int nch, DevCounters* ctr) {
+k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
+  // channels: trial push Jx, Jy; otherwise rho - Jz, Jx, Jy, Jz
+  constexpr int nch = MODE == kPushTrial ? 2 : 4;
   if (MODE == kPushTrial && ctr->pc_done) return;
   if (MODE == kPushReal && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
     // close the slice's predictor-corrector bookkeeping
@@ -206,7 +208,7 @@ k_push(Geom g, Lattice L, PushArgs<T> a, int nch, DevCounters* ctr) {
     const T d = clamped ? floor_d : draw;
     const T id = T(1) / d;
     const T omd = clamped ? T(1) - d : -psi;     // 1 - D
-    double v[5];
+    double v[4];
     if (MODE == kPushTrial) {
       v[0] = static_cast<double>(-w * ux * id);
       v[1] = static_cast<double>(-w * uy * id);
@@ -217,7 +219,6 @@ k_push(Geom g, Lattice L, PushArgs<T> a, int nch, DevCounters* ctr) {
       v[1] = static_cast<double>(-w * ux * id);
       v[2] = static_cast<double>(-w * uy * id);
       v[3] = static_cast<double>(-w * uz * id);
-      v[4] = v[0] + v[3];   // rho = (rho - Jz) + Jz: gamma/D = 1 + uz/D without rounding 1 + small
     }
     int ci, cj;
     T fx, fy;
@@ -230,6 +231,7 @@ k_push(Geom g, Lattice L, PushArgs<T> a, int nch, DevCounters* ctr) {
     if (tiled && li >= 0 && li + 1 < ts.nw && lj >= 0 && lj + 1 < ts.nh) {
       const int base = lj * ts.nw + li;
       const int off[4] = {0, 1, ts.nw, ts.nw + 1};
+#pragma unroll
       for (int c = 0; c < nch; ++c) {
         double* t = tile + c * ntile + base;
 #pragma unroll
@@ -243,6 +245,7 @@ k_push(Geom g, Lattice L, PushArgs<T> a, int nch, DevCounters* ctr) {
       for (int q = 0; q < 4; ++q) {
         if (gi[q] < 1 || gi[q] >= nx || gj[q] < 1 || gj[q] >= ny) continue;
         const size_t o = static_cast<size_t>(gj[q]) * nx + gi[q];
+#pragma unroll
         for (int c = 0; c < nch; ++c) global_add(a.dep.ch[c] + o, v[c] * s[q]);
       }
     }
@@ -356,21 +359,20 @@ void launch_init_plasma(const Lattice& L, const Particles<T>& p, double w0, hipS
 
 template <typename T>
 void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode mode,
-                 bool with_rho, DevCounters* ctr, hipStream_t st) {
+                 DevCounters* ctr, hipStream_t st) {
   const TileShape ts = tile_shape(L, a.tile_rows);
-  const int nch = mode == kPushTrial ? 2 : (with_rho ? 5 : 4);
+  const int nch = mode == kPushTrial ? 2 : 4;
   const size_t lds = a.tiled ? static_cast<size_t>(nch) * ts.nw * ts.nh * sizeof(double) : 0;
   const dim3 grid(L.nX / ts.tx, L.nY / ts.ty);
   switch (mode) {
     case kPushReal:
-      hipLaunchKernelGGL((k_push<T, kPushReal>), grid, dim3(kBlock), lds, st, g, L, a, nch, ctr);
+      hipLaunchKernelGGL((k_push<T, kPushReal>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
       break;
     case kPushTrial:
-      hipLaunchKernelGGL((k_push<T, kPushTrial>), grid, dim3(kBlock), lds, st, g, L, a, nch, ctr);
+      hipLaunchKernelGGL((k_push<T, kPushTrial>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
       break;
     default:
-      hipLaunchKernelGGL((k_push<T, kDepositOnly>), grid, dim3(kBlock), lds, st, g, L, a, nch,
-                         ctr);
+      hipLaunchKernelGGL((k_push<T, kDepositOnly>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
       break;
   }
   QSP_LAUNCH_CHECK();
@@ -399,7 +401,7 @@ void launch_export_state(const Geom& g, const Lattice& L, const Particles<T>& p,
   template void launch_init_plasma<T>(const Lattice&, const Particles<T>&, double,          \
                                       hipStream_t);                                         \
   template void launch_push<T>(const Geom&, const Lattice&, const PushArgs<T>&, PushMode,   \
-                               bool, DevCounters*, hipStream_t);                            \
+                               DevCounters*, hipStream_t);                                  \
   template void launch_import_state<T>(const Geom&, const Lattice&, const Particles<T>&,    \
                                        const double*, const double*, const double*,         \
                                        const double*, const double*, const double*,         \

@@ -157,6 +157,7 @@ class Box final : public BoxBase {
     geom_.y_lo = cfg.y_lo;
     geom_.hx = (cfg.x_hi - cfg.x_lo) / cfg.nx;
     geom_.hy = (cfg.y_hi - cfg.y_lo) / cfg.ny;
+    geom_.rr = row_rows<T>(cfg.nx, cfg.ny);
     lat_.ppc_x = cfg.ppc_x;
     lat_.ppc_y = cfg.ppc_y;
     lat_.nX = cfg.nx * cfg.ppc_x;
@@ -1068,6 +1069,7 @@ class Box final : public BoxBase {
     oc.is_double[i] = (q >= QSP_RHO_MJZ) || sizeof(T) == 8;
     oc.add_beam[i] = 0;
     oc.add_ion[i] = 0;
+    oc.src2[i] = nullptr;
     double* const* dc = dep_[ic_];
     switch (q) {
       case QSP_PSI: oc.src[i] = psi_; break;
@@ -1081,7 +1083,8 @@ class Box final : public BoxBase {
       case QSP_JX: oc.src[i] = dc[1]; break;
       case QSP_JY: oc.src[i] = dc[2]; break;
       case QSP_JZ: oc.src[i] = dc[3]; oc.add_beam[i] = 1; break;
-      case QSP_RHO: oc.src[i] = dc[4]; oc.add_beam[i] = 1; oc.add_ion[i] = 1; break;
+      case QSP_RHO:   // rho = (rho - Jz) + Jz, both FP64 sums
+        oc.src[i] = dc[0]; oc.src2[i] = dc[3]; oc.add_beam[i] = 1; oc.add_ion[i] = 1; break;
       default: throw std::runtime_error("bad output id");
     }
   }
@@ -1103,7 +1106,7 @@ class Box final : public BoxBase {
         for (int c = 0; c < 5; ++c) launch_zero(dc[c], pl, st_);
       });
       PushArgs<T> a = push_args(fields(b_[ik_][0], b_[ik_][1]), dc, k);
-      timed(QSP_K_OTHER, [&] { launch_push<T>(geom_, lat_, a, kDepositOnly, true, ctr_, st_); });
+      timed(QSP_K_OTHER, [&] { launch_push<T>(geom_, lat_, a, kDepositOnly, ctr_, st_); });
       dep_valid_ = true;
     }
     T* bxk = b_[ik_][0];
@@ -1113,12 +1116,12 @@ class Box final : public BoxBase {
     // beam deposit of slice k (Sec. II step 3)
     if (bcount > 0)
       timed(QSP_K_OTHER, [&] {
-        launch_beam_deposit(geom_, beam_soa_, beam_n_, b0, bcount, cfg_.dzeta, dc[0], dc[3], dc[4],
+        launch_beam_deposit(geom_, beam_soa_, beam_n_, b0, bcount, cfg_.dzeta, dc[0], dc[3], nullptr,
                             st_);
       });
     // explicit beam current of slice k
     if (!cur_.empty() && cur_[k])
-      timed(QSP_K_OTHER, [&] { launch_add_current(pl, cur_[k], dc[3], dc[4], st_); });
+      timed(QSP_K_OTHER, [&] { launch_add_current(pl, cur_[k], dc[3], nullptr, st_); });
     // psi, Ez, Bz (Sec. II steps 4-6)
     {
       SrcPEZ<T> s{dc[0], dc[1], dc[2], cfg_.n0, t1_};
@@ -1131,8 +1134,8 @@ class Box final : public BoxBase {
       c.honor_done = 0;
       c.w = col_width<T>(geom_, 3);
       // the deposit planes of slice k+1 are free: clear them for the real push
-      for (int q = 0; q < 5; ++q) c.zero.p[q] = dn[q];
-      c.zero.count = 5;
+      for (int q = 0; q < 4; ++q) c.zero.p[q] = dn[q];
+      c.zero.count = 4;
       c.zero.n = pl;
       timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 3, ty(), lamx_, ctr_, st_); });
       RowInvArgs<T> r{};
@@ -1154,8 +1157,8 @@ class Box final : public BoxBase {
     }
     // Bx/By predictor-corrector (Sec. II step 7, Sec. III.B)
     for (int m = 0; m < cfg_.pc_max_iter; ++m) {
-      PushArgs<T> a = push_args(fields(bxk, byk), trial_, k);
-      timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, false, ctr_, st_); });
+      PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
+      timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, ctr_, st_); });
       SrcBxBy<T> s{};
       s.jz = dc[3];
       s.jx_prev = dp[1];
@@ -1208,7 +1211,7 @@ class Box final : public BoxBase {
       PushArgs<T> a = push_args(fields(bxk, byk), dn, k);
       a.iters_out = iters_out;
       a.resid_out = resid_out;
-      timed(QSP_K_PUSH, [&] { launch_push<T>(geom_, lat_, a, kPushReal, true, ctr_, st_); });
+      timed(QSP_K_PUSH, [&] { launch_push<T>(geom_, lat_, a, kPushReal, ctr_, st_); });
       pushes_ += lat_.np;
     } else {
       timed(QSP_K_OTHER, [&] {
@@ -1228,11 +1231,11 @@ class Box final : public BoxBase {
     ++slices_done_;
   }
 
-  PushArgs<T> push_args(const SliceFields<T>& f, double* const* ch, int k) {
+  PushArgs<T> push_args(const SliceFields<T>& f, double* const* ch, int k, int nch = 4) {
     PushArgs<T> a{};
     a.p = p_;
     a.f = f;
-    for (int c = 0; c < 5; ++c) a.dep.ch[c] = ch[c];
+    for (int c = 0; c < nch; ++c) a.dep.ch[c] = ch[c];
     a.k = k;
     a.dzeta = cfg_.dzeta;
     a.hx = geom_.hx;
