@@ -145,6 +145,7 @@ struct PushArgs {
   double dzeta, hx, hy, psi_floor;
   int tiled;                // 1: LDS tile histograms, 0: direct global atomics
   int tile_rows;            // lattice rows per workgroup tile
+  int tile_halo;            // cells of LDS histogram around the tile's own cells
   // end-of-slice bookkeeping of the predictor-corrector (real push only)
   int32_t* iters_out;
   double* resid_out;

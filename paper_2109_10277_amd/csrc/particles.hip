@@ -17,12 +17,12 @@ namespace qsp {
 
 namespace {
 
-constexpr int kHalo = 2;
 
 struct TileShape {
   int tx, ty;      // lattice sites per tile
   int lpx, lpy;    // log2 ppc
   int nw, nh;      // LDS node tile (cells + 1 + 2 halo)
+  int halo;        // cells around the tile's own cells covered in LDS
 };
 
 __host__ __device__ inline int ilog2(int v) {
@@ -31,14 +31,15 @@ __host__ __device__ inline int ilog2(int v) {
   return l;
 }
 
-__host__ __device__ inline TileShape tile_shape(const Lattice& L, int rows) {
+__host__ __device__ inline TileShape tile_shape(const Lattice& L, int rows, int halo) {
   TileShape t;
+  t.halo = halo;
   t.tx = L.nX < 64 ? L.nX : 64;
   t.ty = L.nY < rows ? L.nY : rows;
   t.lpx = ilog2(L.ppc_x);
   t.lpy = ilog2(L.ppc_y);
-  t.nw = (t.tx >> t.lpx) + 1 + 2 * kHalo;
-  t.nh = (t.ty >> t.lpy) + 1 + 2 * kHalo;
+  t.nw = (t.tx >> t.lpx) + 1 + 2 * halo;
+  t.nh = (t.ty >> t.lpy) + 1 + 2 * halo;
   return t;
 }
 
@@ -66,16 +67,17 @@ __device__ inline bool inside(int c0, T t, int n) {
   return c >= 0 && (c < n || (c == n && t == fl));
 }
 
-template <typename T>
-__device__ inline T node(const T* __restrict__ F, int i, int j, int nx, int ny) {
-  return (i < nx && j < ny) ? F[j * nx + i] : T(0);
-}
-
+// CIC interpolation in cell (i, j), 0 <= i < nx, 0 <= j < ny; the upper
+// Dirichlet nodes (index n, not stored) are zero.  All four loads are
+// unconditional (clamped indices) so that they issue together.
 template <typename T>
 __device__ inline T gather(const T* __restrict__ F, int i, int j, T w00, T w10, T w01, T w11,
                            int nx, int ny) {
-  return w00 * node(F, i, j, nx, ny) + w10 * node(F, i + 1, j, nx, ny) +
-         w01 * node(F, i, j + 1, nx, ny) + w11 * node(F, i + 1, j + 1, nx, ny);
+  const bool ie = i + 1 < nx, jn = j + 1 < ny;
+  const int i1 = ie ? i + 1 : i, j1 = jn ? j + 1 : j;
+  const T f00 = F[j * nx + i], f10 = F[j * nx + i1], f01 = F[j1 * nx + i], f11 = F[j1 * nx + i1];
+  return w00 * f00 + w10 * (ie ? f10 : T(0)) + w01 * (jn ? f01 : T(0)) +
+         w11 * ((ie && jn) ? f11 : T(0));
 }
 
 __device__ inline void lds_add(double* p, double v) {
@@ -116,7 +118,7 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
   extern __shared__ unsigned char smem_raw[];
   double* tile = reinterpret_cast<double*>(smem_raw);
   __shared__ unsigned int red[kBlock / 64];
-  const TileShape ts = tile_shape(L, a.tile_rows);
+  const TileShape ts = tile_shape(L, a.tile_rows, a.tile_halo);
   const int ntile = ts.nw * ts.nh;
   const bool tiled = a.tiled != 0;
   if (tiled) {
@@ -124,7 +126,7 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
     __syncthreads();
   }
   const int I0 = blockIdx.x * ts.tx, J0 = blockIdx.y * ts.ty;
-  const int ox = (I0 >> ts.lpx) - kHalo, oy = (J0 >> ts.lpy) - kHalo;
+  const int ox = (I0 >> ts.lpx) - ts.halo, oy = (J0 >> ts.lpy) - ts.halo;
   const int nx = g.nx, ny = g.ny;
   const T inv_hx = static_cast<T>(1.0 / a.hx), inv_hy = static_cast<T>(1.0 / a.hy);
   const T floor_d = static_cast<T>(a.psi_floor);
@@ -139,15 +141,24 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
   for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock) {
     const int I = I0 + e % ts.tx, J = J0 + e / ts.tx;
     const size_t p = static_cast<size_t>(J) * L.nX + I;
+    // every load of the particle is issued before any decision on it
     const T w = a.p.w[p];
-    if (w == T(0)) continue;
+    T xi = a.p.xi_x[p], eta = a.p.xi_y[p];
+    T ux = a.p.ux[p], uy = a.p.uy[p], psi = a.p.psi[p];
     const int ci0 = I >> ts.lpx, cj0 = J >> ts.lpy;
     const T fx0 = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
     const T fy0 = (T(2 * (J & (L.ppc_y - 1)) + 1)) / T(2 * L.ppc_y);
-    T xi = a.p.xi_x[p], eta = a.p.xi_y[p];
-    T ux = a.p.ux[p], uy = a.p.uy[p], psi = a.p.psi[p];
+    bool alive = w != T(0);
 
     if (MODE != kDepositOnly) {
+      T h[4][5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        h[0][c] = hist[(s1 * 5 + c) * np + p];
+        h[1][c] = hist[(s2 * 5 + c) * np + p];
+        h[2][c] = hist[(s3 * 5 + c) * np + p];
+        h[3][c] = hist[(s4 * 5 + c) * np + p];
+      }
       int ci, cj;
       T fx, fy;
       locate(ci0, fx0 + xi, nx, ci, fx);
@@ -163,7 +174,7 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
       // right-hand side of the pusher equations for an electron (q = -1)
       const T draw = T(1) + psi;
       const T d = draw < floor_d ? floor_d : draw;
-      if (MODE == kPushReal && draw < floor_d) ++nclamp;
+      if (MODE == kPushReal && alive && draw < floor_d) ++nclamp;
       const T id = T(1) / d;
       const T gam = (T(1) + ux * ux + uy * uy + d * d) * T(0.5) * id;
       T f[5];
@@ -174,13 +185,9 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
       f[4] = (ux * e1 + uy * e2) * id - ez;
       T y[5] = {xi, eta, ux, uy, psi};
 #pragma unroll
-      for (int c = 0; c < 5; ++c) {
-        const T h1 = hist[(s1 * 5 + c) * np + p];
-        const T h2 = hist[(s2 * 5 + c) * np + p];
-        const T h3 = hist[(s3 * 5 + c) * np + p];
-        const T h4 = hist[(s4 * 5 + c) * np + p];
-        y[c] = y[c] - dz * (b0 * f[c] + b1 * h1 + b2 * h2 + b3 * h3 + b4 * h4);
-      }
+      for (int c = 0; c < 5; ++c)
+        y[c] = y[c] - dz * (b0 * f[c] + b1 * h[0][c] + b2 * h[1][c] + b3 * h[2][c] + b4 * h[3][c]);
+      if (!alive) continue;
       if (!inside(ci0, fx0 + y[0], nx) || !inside(cj0, fy0 + y[1], ny)) {
         ++nabs;
         if (MODE == kPushReal) a.p.w[p] = T(0);
@@ -200,6 +207,8 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) hist[(s_new * 5 + c) * np + p] = f[c];
       }
+    } else if (!alive) {
+      continue;
     }
 
     // deposit at the (new) position: rho - Jz = q w exactly, J = q w u / D
@@ -360,10 +369,17 @@ void launch_init_plasma(const Lattice& L, const Particles<T>& p, double w0, hipS
 template <typename T>
 void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode mode,
                  DevCounters* ctr, hipStream_t st) {
-  const TileShape ts = tile_shape(L, a.tile_rows);
+  const TileShape ts = tile_shape(L, a.tile_rows, a.tile_halo);
   const int nch = mode == kPushTrial ? 2 : 4;
   const size_t lds = a.tiled ? static_cast<size_t>(nch) * ts.nw * ts.nh * sizeof(double) : 0;
+  if (lds > 160 * 1024) throw std::invalid_argument("push tile histogram exceeds the LDS");
   const dim3 grid(L.nX / ts.tx, L.nY / ts.ty);
+  if (lds > 65536) {   // opt in above 64 KiB (gfx950 offers 160 KiB per workgroup)
+    const void* fn = mode == kPushReal    ? reinterpret_cast<const void*>(&k_push<T, kPushReal>)
+                     : mode == kPushTrial ? reinterpret_cast<const void*>(&k_push<T, kPushTrial>)
+                                          : reinterpret_cast<const void*>(&k_push<T, kDepositOnly>);
+    QSP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+  }
   switch (mode) {
     case kPushReal:
       hipLaunchKernelGGL((k_push<T, kPushReal>), grid, dim3(kBlock), lds, st, g, L, a, ctr);

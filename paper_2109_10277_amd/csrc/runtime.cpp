@@ -166,6 +166,7 @@ class Box final : public BoxBase {
     shift_ = cfg.pc_shift < 0 ? default_pc_shift(cfg.n0) : cfg.pc_shift;
     tiled_ = cfg.deposit_mode == 0;
     tile_rows_ = default_tile_rows();
+    tile_halo_ = default_tile_halo();
     QSP_HIP(hipSetDevice(device_));
     try {
       allocate();
@@ -929,6 +930,17 @@ class Box final : public BoxBase {
 
   // Lattice rows per push workgroup (64 sites wide): as many rows as keep
   // >= 1024 workgroups per launch, between 4 and 16.
+  // Cells of LDS deposit histogram around a push tile: particles displaced
+  // further than this from their tile go to global atomics.
+  int default_tile_halo() const {
+    int h = 2;
+    if (const char* e = std::getenv("QSP_HALO")) {   // tuning override
+      const int v = std::atoi(e);
+      if (v >= 1 && v <= 16) h = v;
+    }
+    return h;
+  }
+
   int default_tile_rows() const {
     const int tx = lat_.nX < 64 ? lat_.nX : 64;
     int r = 16;
@@ -1243,6 +1255,7 @@ class Box final : public BoxBase {
     a.psi_floor = cfg_.psi_floor;
     a.tiled = tiled_ ? 1 : 0;
     a.tile_rows = tile_rows_;
+    a.tile_halo = tile_halo_;
     a.pc_tol = cfg_.pc_tol;
     a.pc_max_iter = cfg_.pc_max_iter;
     return a;
@@ -1311,6 +1324,7 @@ class Box final : public BoxBase {
   bool dep_valid_ = false;
   bool tiled_ = true;
   int tile_rows_ = 16;
+  int tile_halo_ = 2;
   bool nonfinite_ = false;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
   double last_ms_ = 0.0;
