@@ -1,0 +1,275 @@
+// Device-side body of the fused plasma gather + Adams-Bashforth push +
+// deposit, shared by the per-launch kernels and the persistent
+// predictor-corrector kernel (HiPACE++, arXiv:2109.10277, Sec. III.B: plasma
+// pusher equations, CIC deposition zeroth order in zeta).
+//
+// Particles are stored SoA in lattice order and keep their lattice site for
+// life; positions are stored as displacements from that site (in cells) so
+// that small displacements keep full precision.  A workgroup owns a tile of
+// lattice sites; its particles deposit into FP64 histograms in LDS covering
+// the tile's cells plus a halo, which are then added to the global FP64
+// deposit arrays with one atomic per non-zero node.  Particles that have
+// left the tile+halo fall back to global FP64 atomics.
+#pragma once
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace qsp {
+namespace push_detail {
+
+struct TileShape {
+  int tx, ty;      // lattice sites per tile
+  int lpx, lpy;    // log2 ppc
+  int nw, nh;      // LDS node tile (cells + 1 + 2 halo)
+  int halo;        // cells around the tile's own cells covered in LDS
+};
+
+__host__ __device__ inline int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+__host__ __device__ inline TileShape tile_shape(const Lattice& L, int rows, int halo) {
+  TileShape t;
+  t.halo = halo;
+  t.tx = L.nX < 64 ? L.nX : 64;
+  t.ty = L.nY < rows ? L.nY : rows;
+  t.lpx = ilog2(L.ppc_x);
+  t.lpy = ilog2(L.ppc_y);
+  t.nw = (t.tx >> t.lpx) + 1 + 2 * halo;
+  t.nh = (t.ty >> t.lpy) + 1 + 2 * halo;
+  return t;
+}
+
+// cell index and offset inside the cell of a particle; clamps the upper
+// edge like the node range 0..n allows
+template <typename T>
+__device__ inline void locate(int c0, T t, int n, int& c, T& f) {
+  const T fl = floor(t);
+  c = c0 + static_cast<int>(fl);
+  f = t - fl;
+  if (c >= n) {
+    c = n - 1;
+    f = T(1);
+  }
+  if (c < 0) {
+    c = 0;
+    f = T(0);
+  }
+}
+
+template <typename T>
+__device__ inline bool inside(int c0, T t, int n) {
+  const T fl = floor(t);
+  const int c = c0 + static_cast<int>(fl);
+  return c >= 0 && (c < n || (c == n && t == fl));
+}
+
+// CIC interpolation in cell (i, j), 0 <= i < nx, 0 <= j < ny; the upper
+// Dirichlet nodes (index n, not stored) are zero.  All four loads are
+// unconditional (clamped indices) so that they issue together.
+template <typename T>
+__device__ inline T gather(const T* __restrict__ F, int i, int j, T w00, T w10, T w01, T w11,
+                           int nx, int ny) {
+  const bool ie = i + 1 < nx, jn = j + 1 < ny;
+  const int i1 = ie ? i + 1 : i, j1 = jn ? j + 1 : j;
+  const T f00 = F[j * nx + i], f10 = F[j * nx + i1], f01 = F[j1 * nx + i], f11 = F[j1 * nx + i1];
+  return w00 * f00 + w10 * (ie ? f10 : T(0)) + w01 * (jn ? f01 : T(0)) +
+         w11 * ((ie && jn) ? f11 : T(0));
+}
+
+__device__ inline void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline void global_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+__device__ inline unsigned long long block_sum(unsigned int v, unsigned int* red) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  unsigned long long s = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kBlock / 64; ++w) s += red[w];
+  return s;
+}
+
+// Gather, push and deposit of the particles of lattice tile (tbx, tby) by
+// one workgroup; `tile` is the workgroup's LDS histogram (nch channels of
+// tile_shape's nw x nh nodes).  Safe to call repeatedly from one workgroup.
+template <typename T, int MODE>
+__device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const PushArgs<T>& a,
+                                          DevCounters* ctr, int tbx, int tby, double* tile) {
+  // channels: trial push Jx, Jy; otherwise rho - Jz, Jx, Jy, Jz
+  constexpr int nch = MODE == kPushTrial ? 2 : 4;
+  __shared__ unsigned int red[kBlock / 64];
+  const TileShape ts = tile_shape(L, a.tile_rows, a.tile_halo);
+  const int ntile = ts.nw * ts.nh;
+  const bool tiled = a.tiled != 0;
+  if (tiled) {
+    __syncthreads();   // a previous tile's flush has read the histogram
+    for (int e = threadIdx.x; e < nch * ntile; e += kBlock) tile[e] = 0.0;
+    __syncthreads();
+  }
+  const int I0 = tbx * ts.tx, J0 = tby * ts.ty;
+  const int ox = (I0 >> ts.lpx) - ts.halo, oy = (J0 >> ts.lpy) - ts.halo;
+  const int nx = g.nx, ny = g.ny;
+  const T inv_hx = static_cast<T>(1.0 / a.hx), inv_hy = static_cast<T>(1.0 / a.hy);
+  const T floor_d = static_cast<T>(a.psi_floor);
+  const T dz = static_cast<T>(a.dzeta);
+  const T b0 = T(kAB5[0]), b1 = T(kAB5[1]), b2 = T(kAB5[2]), b3 = T(kAB5[3]), b4 = T(kAB5[4]);
+  const size_t np = static_cast<size_t>(L.np);
+  T* hist = a.p.hist;
+  const int s_new = a.k & 3;
+  const int s1 = (a.k + 3) & 3, s2 = (a.k + 2) & 3, s3 = (a.k + 1) & 3, s4 = s_new;
+  unsigned int nclamp = 0, nabs = 0, nglob = 0;
+
+  for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock) {
+    const int I = I0 + e % ts.tx, J = J0 + e / ts.tx;
+    const size_t p = static_cast<size_t>(J) * L.nX + I;
+    // every load of the particle is issued before any decision on it
+    const T w = a.p.w[p];
+    T xi = a.p.xi_x[p], eta = a.p.xi_y[p];
+    T ux = a.p.ux[p], uy = a.p.uy[p], psi = a.p.psi[p];
+    const int ci0 = I >> ts.lpx, cj0 = J >> ts.lpy;
+    const T fx0 = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
+    const T fy0 = (T(2 * (J & (L.ppc_y - 1)) + 1)) / T(2 * L.ppc_y);
+    bool alive = w != T(0);
+
+    if (MODE != kDepositOnly) {
+      T h[4][5];
+#pragma unroll
+      for (int c = 0; c < 5; ++c) {
+        h[0][c] = hist[(s1 * 5 + c) * np + p];
+        h[1][c] = hist[(s2 * 5 + c) * np + p];
+        h[2][c] = hist[(s3 * 5 + c) * np + p];
+        h[3][c] = hist[(s4 * 5 + c) * np + p];
+      }
+      int ci, cj;
+      T fx, fy;
+      locate(ci0, fx0 + xi, nx, ci, fx);
+      locate(cj0, fy0 + eta, ny, cj, fy);
+      const T w00 = (T(1) - fx) * (T(1) - fy), w10 = fx * (T(1) - fy);
+      const T w01 = (T(1) - fx) * fy, w11 = fx * fy;
+      const T e1 = gather(a.f.exmby, ci, cj, w00, w10, w01, w11, nx, ny);
+      const T e2 = gather(a.f.eypbx, ci, cj, w00, w10, w01, w11, nx, ny);
+      const T ez = gather(a.f.ez, ci, cj, w00, w10, w01, w11, nx, ny);
+      const T bx = gather(a.f.bx, ci, cj, w00, w10, w01, w11, nx, ny);
+      const T by = gather(a.f.by, ci, cj, w00, w10, w01, w11, nx, ny);
+      const T bz = gather(a.f.bz, ci, cj, w00, w10, w01, w11, nx, ny);
+      // right-hand side of the pusher equations for an electron (q = -1)
+      const T draw = T(1) + psi;
+      const T d = draw < floor_d ? floor_d : draw;
+      if (MODE == kPushReal && alive && draw < floor_d) ++nclamp;
+      const T id = T(1) / d;
+      const T gam = (T(1) + ux * ux + uy * uy + d * d) * T(0.5) * id;
+      T f[5];
+      f[0] = -ux * id * inv_hx;
+      f[1] = -uy * id * inv_hy;
+      f[2] = gam * id * e1 + by + bz * uy * id;
+      f[3] = gam * id * e2 - bx - bz * ux * id;
+      f[4] = (ux * e1 + uy * e2) * id - ez;
+      T y[5] = {xi, eta, ux, uy, psi};
+#pragma unroll
+      for (int c = 0; c < 5; ++c)
+        y[c] = y[c] - dz * (b0 * f[c] + b1 * h[0][c] + b2 * h[1][c] + b3 * h[2][c] + b4 * h[3][c]);
+      if (!alive) continue;
+      if (!inside(ci0, fx0 + y[0], nx) || !inside(cj0, fy0 + y[1], ny)) {
+        ++nabs;
+        if (MODE == kPushReal) a.p.w[p] = T(0);
+        continue;
+      }
+      xi = y[0];
+      eta = y[1];
+      ux = y[2];
+      uy = y[3];
+      psi = y[4];
+      if (MODE == kPushReal) {
+        a.p.xi_x[p] = xi;
+        a.p.xi_y[p] = eta;
+        a.p.ux[p] = ux;
+        a.p.uy[p] = uy;
+        a.p.psi[p] = psi;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) hist[(s_new * 5 + c) * np + p] = f[c];
+      }
+    } else if (!alive) {
+      continue;
+    }
+
+    // deposit at the (new) position: rho - Jz = q w exactly, J = q w u / D
+    const T draw = T(1) + psi;
+    const bool clamped = draw < floor_d;
+    const T d = clamped ? floor_d : draw;
+    const T id = T(1) / d;
+    const T omd = clamped ? T(1) - d : -psi;     // 1 - D
+    double v[4];
+    if (MODE == kPushTrial) {
+      v[0] = static_cast<double>(-w * ux * id);
+      v[1] = static_cast<double>(-w * uy * id);
+    } else {
+      const T u2 = ux * ux + uy * uy;
+      const T uz = (u2 + omd * (T(1) + d)) * T(0.5) * id;
+      v[0] = static_cast<double>(-w);
+      v[1] = static_cast<double>(-w * ux * id);
+      v[2] = static_cast<double>(-w * uy * id);
+      v[3] = static_cast<double>(-w * uz * id);
+    }
+    int ci, cj;
+    T fx, fy;
+    locate(ci0, fx0 + xi, nx, ci, fx);
+    locate(cj0, fy0 + eta, ny, cj, fy);
+    const double dfx = static_cast<double>(fx), dfy = static_cast<double>(fy);
+    const double s[4] = {(1.0 - dfx) * (1.0 - dfy), dfx * (1.0 - dfy), (1.0 - dfx) * dfy,
+                         dfx * dfy};
+    const int li = ci - ox, lj = cj - oy;
+    if (tiled && li >= 0 && li + 1 < ts.nw && lj >= 0 && lj + 1 < ts.nh) {
+      const int base = lj * ts.nw + li;
+      const int off[4] = {0, 1, ts.nw, ts.nw + 1};
+#pragma unroll
+      for (int c = 0; c < nch; ++c) {
+        double* t = tile + c * ntile + base;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lds_add(t + off[q], v[c] * s[q]);
+      }
+    } else {
+      if (tiled) ++nglob;
+      const int gi[4] = {ci, ci + 1, ci, ci + 1};
+      const int gj[4] = {cj, cj, cj + 1, cj + 1};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (gi[q] < 1 || gi[q] >= nx || gj[q] < 1 || gj[q] >= ny) continue;
+        const size_t o = static_cast<size_t>(gj[q]) * nx + gi[q];
+#pragma unroll
+        for (int c = 0; c < nch; ++c) global_add(a.dep.ch[c] + o, v[c] * s[q]);
+      }
+    }
+  }
+
+  if (tiled) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < nch * ntile; e += kBlock) {
+      const int c = e / ntile, l = e % ntile;
+      const int gi = ox + l % ts.nw, gj = oy + l / ts.nw;
+      if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
+      const double val = tile[e];
+      if (val != 0.0) global_add(a.dep.ch[c] + static_cast<size_t>(gj) * nx + gi, val);
+    }
+  }
+  // counters
+  const unsigned long long tc = block_sum(nclamp, red);
+  const unsigned long long ta = block_sum(nabs, red);
+  const unsigned long long tg = block_sum(nglob, red);
+  if (threadIdx.x == 0) {
+    if (tc) atomicAdd(&ctr->n_clamped, tc);
+    if (MODE == kPushReal && ta) atomicAdd(&ctr->n_absorbed, ta);
+    if (MODE != kPushTrial && tg) atomicAdd(&ctr->n_dep_global, tg);
+  }
+}
+
+}  // namespace push_detail
+}  // namespace qsp

@@ -1168,9 +1168,8 @@ class Box final : public BoxBase {
       dst_solves_ += 3;
     }
     // Bx/By predictor-corrector (Sec. II step 7, Sec. III.B)
-    for (int m = 0; m < cfg_.pc_max_iter; ++m) {
-      PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
-      timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, ctr_, st_); });
+    {
+      const PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
       SrcBxBy<T> s{};
       s.jz = dc[3];
       s.jx_prev = dp[1];
@@ -1185,7 +1184,6 @@ class Box final : public BoxBase {
       s.bgx = bgx_;
       s.bgy = bgy_;
       s.out = t1_;
-      timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_bxby<T>(geom_, s, tx(), ctr_, st_); });
       ColArgs<T> c{};
       c.in = t1_;
       c.out = t2_;
@@ -1198,11 +1196,15 @@ class Box final : public BoxBase {
       c.zero.p[1] = trial_[1];
       c.zero.count = 2;
       c.zero.n = pl;
-      timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
-      PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol,
-                   tape_slot_ ? tape_b(*tape_slot_, m + 1, 0) : nullptr,
-                   tape_slot_ ? tape_b(*tape_slot_, m + 1, 1) : nullptr};
-      timed(QSP_K_ROW_INV, [&] { launch_row_inv_pc<T>(geom_, pc, tx(), ctr_, st_); });
+      for (int m = 0; m < cfg_.pc_max_iter; ++m) {
+        timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, ctr_, st_); });
+        timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_bxby<T>(geom_, s, tx(), ctr_, st_); });
+        timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
+        PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol,
+                     tape_slot_ ? tape_b(*tape_slot_, m + 1, 0) : nullptr,
+                     tape_slot_ ? tape_b(*tape_slot_, m + 1, 1) : nullptr};
+        timed(QSP_K_ROW_INV, [&] { launch_row_inv_pc<T>(geom_, pc, tx(), ctr_, st_); });
+      }
     }
     // beam particles of slice k take their time step in the final fields
     if (bcount > 0 && beam_dt_ != 0.0) {
