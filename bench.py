@@ -28,24 +28,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+METRIC = "plasma particle-slice updates/s + DST solves/s; FP32 vs FP64; fwd+bwd/fwd ratio"
 
 # HBM bytes per real-push launch at c2 FP32 from the FETCH_SIZE / WRITE_SIZE
-# counter runs (scaled by a 256 MiB copy), valid for the push kernel source
-# with this sha256 prefix
-PUSH_TRAFFIC = {"source": "paper_2109_10277_amd/csrc/particles.hip",
-                "sha256_prefix": "8a04a4635963ef38", "workload": "c2", "bytes": 68.53e6,
+# counter runs (scaled by a 256 MiB copy), valid while the push kernel's
+# sources hash to this value
+PUSH_TRAFFIC = {"sources": ["paper_2109_10277_amd/csrc/particles.hip",
+                            "paper_2109_10277_amd/csrc/push_tile.hpp"],
+                "sha256_prefix": "1667717135d8a419", "workload": "c2", "bytes": 64.24e6,
                 "summary": "profiles/hbm_traffic_c2_blowout_512x512x1024_fp32.md"}
+
+
+def push_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in PUSH_TRAFFIC["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def push_traffic(workload_name: str):
     """Counter-measured bytes per launch, or None once the kernel changed."""
-    import hashlib
+    if PUSH_TRAFFIC["bytes"] is None or not PUSH_TRAFFIC["sha256_prefix"]:
+        return None
     if not workload_name.startswith(PUSH_TRAFFIC["workload"] + "_"):
         return None
-    with open(os.path.join(ROOT, PUSH_TRAFFIC["source"]), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    return PUSH_TRAFFIC["bytes"] if sha.startswith(PUSH_TRAFFIC["sha256_prefix"]) else None
-METRIC = "plasma particle-slice updates/s + DST solves/s; FP32 vs FP64; fwd+bwd/fwd ratio"
+    return PUSH_TRAFFIC["bytes"] if push_source_hash().startswith(PUSH_TRAFFIC["sha256_prefix"]) else None
 
 
 def workload(name: str):
@@ -66,10 +75,10 @@ def push_bytes(cfg, fsize: int) -> int:
     """Algorithmic HBM bytes of one real push launch: every particle reads
     its state (x, y, ux, uy, Psi, w) and 4 history slots x 5 quantities and
     writes 5 state + 5 history values; the six field planes are read once
-    and the five FP64 deposit planes written once."""
+    and the four FP64 deposit planes (rho - Jz, Jx, Jy, Jz) written once."""
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     plane = cfg.nx * cfg.ny
-    return n_p * (26 + 10) * fsize + 6 * plane * fsize + 5 * plane * 8
+    return n_p * (26 + 10) * fsize + 6 * plane * fsize + 4 * plane * 8
 
 
 def run_gpu(cfg, beam, precision: str, steps: int, warmup: int, timing_every: int):
@@ -205,7 +214,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--timing-every", type=int, default=4,
                     help="time the kernels of every n-th slice with HIP events")
-    ap.add_argument("--cpu-slices", type=int, default=12)
+    ap.add_argument("--cpu-slices", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
