@@ -357,12 +357,23 @@ def beam_slice_index(cfg, zeta: np.ndarray) -> np.ndarray:
     return np.rint((cfg.zeta_hi - zeta) / cfg.dzeta).astype(np.int64)
 
 
+def beam_slices(cfg, b) -> np.ndarray:
+    """Slice of each beam particle for the current time step.  The beam is
+    sorted per slice once per time step, before the loop over slices
+    (Sec. III.A), so a particle keeps the slice it had at the start of the
+    box for its deposit and its push even if the push moves it across a
+    slice boundary; ``run_box`` fixes this assignment.  Outside a box the
+    assignment is taken from the current positions."""
+    frozen = getattr(b, "_slice_of_step", None)
+    return frozen if frozen is not None else beam_slice_index(cfg, b.zeta)
+
+
 def particle_beam_source(cfg, b, k: int) -> dict:
     """Deposit of the macro-particles of slice k (NGP in zeta, CIC
     transversely): rho = q w S / (hx hy dzeta), Jz = rho v_z, with
     rho - Jz = rho (1 + u_perp^2) / (gamma (gamma + u_z)) written so it does
     not cancel; the transverse beam current is neglected."""
-    sel = (beam_slice_index(cfg, b.zeta) == k)
+    sel = (beam_slices(cfg, b) == k)
     x, y = b.x[sel].astype(np.float64), b.y[sel].astype(np.float64)
     ux, uy, uz = (b.ux[sel].astype(np.float64), b.uy[sel].astype(np.float64),
                   b.uz[sel].astype(np.float64))
@@ -393,7 +404,7 @@ def beam_push_slice(cfg, b, k: int, flds: dict, dt: float) -> None:
       x_new = x_h + dt/2 u_perp_new/gamma_new,  zeta likewise.
 
     The particle keeps its slice for the gather.  Mutates ``b`` in place."""
-    sel = np.nonzero(beam_slice_index(cfg, b.zeta) == k)[0]
+    sel = np.nonzero(beam_slices(cfg, b) == k)[0]
     if sel.size == 0:
         return
     x, y, z = b.x[sel].astype(np.float64), b.y[sel].astype(np.float64), b.zeta[sel].astype(np.float64)
@@ -537,11 +548,32 @@ def run_box(cfg, beam, keep: Optional[Callable[[int, dict], dict]] = None,
     st = initial_state(cfg) if state is None else state
     k_end = cfg.nzeta if k_end is None else k_end
     out = []
-    while st.k < k_end:
-        k = st.k
-        st, rec = advance_slice(cfg, st, beam)
-        out.append(rec if keep is None else keep(k, rec))
+    particle_beam = beam is not None and hasattr(beam, "zeta")
+    if particle_beam:
+        beam._slice_of_step = beam_slice_index(cfg, beam.zeta)
+    try:
+        while st.k < k_end:
+            k = st.k
+            st, rec = advance_slice(cfg, st, beam)
+            out.append(rec if keep is None else keep(k, rec))
+    finally:
+        if particle_beam:
+            beam._slice_of_step = None
     return out, st
+
+
+def run_steps(cfg, beam, nsteps: int, state_fn: Optional[Callable[[], "SliceState"]] = None,
+              after_step: Optional[Callable[[int, list], None]] = None):
+    """Multi-time-step loop (Sec. II): each time step runs the whole box
+    from the head with a fresh plasma (``state_fn()``, default the
+    unperturbed plasma) while the beam macro-particles advance by their
+    time step dt in every slice; ``after_step(step, records)`` sees each
+    box.  Mutates ``beam``."""
+    for step in range(nsteps):
+        st = state_fn() if state_fn is not None else None
+        recs, _ = run_box(cfg, beam, keep=lambda k, r: {}, state=st)
+        if after_step is not None:
+            after_step(step, recs)
 
 
 def stack(records: Sequence[dict], name: str) -> np.ndarray:

@@ -158,6 +158,26 @@ def explicit_currents(cfg: BoxConfig, peak: float = 0.8, seed: int = SEED) -> np
     return J
 
 
+def ion_column(n: int = 64, nzeta: int = 4, extent: float = 4.0, x0: float = 0.2,
+               gamma: float = 2000.0, dt: float = BEAM_DT, w: float = 1e-8):
+    """Beam test particles in a pure ion column: the box holds ions of
+    density n0 = 1 and no plasma electrons (their weights are zeroed by the
+    caller), so Ex - By = x/2 and Ey + Bx = y/2 inside.  One test electron
+    per slice at (x0, 0), (0, x0), (x0, x0/2) and (-x0/2, x0) in turn, at
+    rest transversally, u_z = gamma, negligible charge w.  Returns
+    (BoxConfig, ParticleBeam)."""
+    cfg = BoxConfig(nx=n, ny=n, x_lo=-extent, x_hi=extent, y_lo=-extent, y_hi=extent,
+                    nzeta=nzeta, zeta_hi=0.0, dzeta=1.0 / nzeta, pc_max_iter=2, pc_tol=0.0)
+    pts = [(x0, 0.0), (0.0, x0), (x0, 0.5 * x0), (-0.5 * x0, x0)]
+    x = np.array([pts[k % 4][0] for k in range(nzeta)], dtype=np.float32)
+    y = np.array([pts[k % 4][1] for k in range(nzeta)], dtype=np.float32)
+    zeta = np.asarray(cfg.zeta(), dtype=np.float32)
+    uz = np.full(nzeta, np.sqrt(gamma * gamma - 1.0), dtype=np.float32)
+    zero = np.zeros(nzeta, dtype=np.float32)
+    beam = ParticleBeam(x, y, zeta, zero.copy(), zero.copy(), uz, np.full(nzeta, w, np.float32), dt)
+    return cfg, beam
+
+
 def witness_factors(cfg: BoxConfig, rel_cut: float = 1e-10):
     """Separable factors of ``witness_profile`` restricted to the slices
     where the longitudinal factor exceeds rel_cut * peak: returns
