@@ -188,6 +188,53 @@ def adjoint_leg(name: str, precision: str, ckpt_every: int, reps: int = 2) -> di
             "grad_sigma": gs.cpu().tolist()}
 
 
+def emittance_study(nsteps: int) -> dict:
+    """FP32 versus FP64 drift of the witness emittance over nsteps time steps
+    on a reduced reference setup (256^2 x 256 slices, driver + witness
+    macro-particle beams, witness with zero initial emittance and a
+    transverse centroid offset of one sigma_x).  Each time step runs the box
+    with a fresh plasma while the beams advance by dt = 6 in every slice."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2109_10277_amd import qsp
+    cfg, beam = W.emittance_study()
+    w_wit = float(beam.w[-1])
+    every = max(1, nsteps // 20)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        box = qsp.Box(cfg, prec)
+        box.set_beam_particles(torch.tensor(beam.soa(), device="cuda"), beam.dt)
+        series = []
+        t0 = time.perf_counter()
+        for step in range(nsteps + 1):
+            if step % every == 0 or step == nsteps:
+                b = box.get_beam_particles().double()
+                m = torch.isclose(b[6], torch.tensor(w_wit, dtype=torch.float64, device=b.device))
+                x, ux = b[0][m], b[3][m]
+                x, ux = x - x.mean(), ux - ux.mean()
+                emit = torch.sqrt(torch.clamp((x * x).mean() * (ux * ux).mean() - (x * ux).mean() ** 2,
+                                              min=0.0))
+                series.append((step, float(emit), float(b[0][m].mean())))
+            if step < nsteps:
+                box.init_plasma()
+                box.run_box()
+        torch.cuda.synchronize()
+        out[prec] = {"seconds": time.perf_counter() - t0, "series": series}
+        box.close()
+    e32 = np.array([s[1] for s in out["fp32"]["series"]])
+    e64 = np.array([s[1] for s in out["fp64"]["series"]])
+    rel = np.abs(e32 - e64) / np.maximum(e64, 1e-300)
+    return {"study": "witness emittance, FP32 vs FP64", "steps": nsteps, "dt": beam.dt,
+            "config": {"nx": cfg.nx, "ny": cfg.ny, "slices": cfg.nzeta,
+                       "beam_particles": int(beam.x.size)},
+            "steps_sampled": [s[0] for s in out["fp64"]["series"]],
+            "emittance_fp64": e64.tolist(), "emittance_fp32": e32.tolist(),
+            "rel_error_fp32_final": float(rel[-1]), "rel_error_fp32_max_after_first": float(rel[1:].max()),
+            "centroid_x_fp64": [s[2] for s in out["fp64"]["series"]],
+            "seconds": {p: out[p]["seconds"] for p in out}}
+
+
 def cpu_baseline(cfg, beam, n_slices: int) -> dict:
     """The FP64 oracle on the host cores: the first n_slices slices of the
     same box, from the unperturbed plasma."""
@@ -221,6 +268,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--emittance-study", type=int, default=0, metavar="STEPS",
+                    help="only run the FP32-vs-FP64 witness emittance study for STEPS time steps")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint legs and print their JSON")
     ap.add_argument("--adjoint-c5", default="",
@@ -242,6 +291,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
+    if args.emittance_study:
+        print(json.dumps(emittance_study(args.emittance_study)))
         return
     if args.adjoint_only:
         legs = [] if args.no_adjoint else [adjoint_leg("c4", "fp32", 32)]

@@ -254,7 +254,8 @@ qsp_status qsp_get_slice_state(qsp_ctx ctx, qsp_slice_state* dst);
 
 /* Replaces the state at the start of slice src->k (0 <= k < nzeta) and moves
  * the cursor there (synchronises).  Positions must lie inside the box for
- * particles with w > 0. */
+ * particles with w > 0.  Like qsp_init_plasma it sorts a pushed
+ * macro-particle beam by slice again. */
 qsp_status qsp_set_slice_state(qsp_ctx ctx, const qsp_slice_state* src);
 
 /* Batched 2D Dirichlet solve with the context's transforms (Sec. III.B fast

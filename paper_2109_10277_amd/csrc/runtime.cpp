@@ -197,14 +197,7 @@ class Box final : public BoxBase {
   void init_plasma() override {
     QSP_HIP(hipSetDevice(device_));
     rec_valid_ = false;
-    if (beam_n_ > 0 && beam_dirty_) {
-      // a pushed beam is re-sorted by slice before the next box
-      QSP_HIP(hipMemcpyAsync(beam_tmp_, beam_soa_, 7 * beam_n_ * sizeof(float),
-                             hipMemcpyDeviceToDevice, st_));
-      beam_sort(beam_tmp_, beam_soa_, beam_n_, cfg_.zeta_hi, cfg_.dzeta, cfg_.nzeta, bs_,
-                beam_off_, st_);
-      beam_dirty_ = false;
-    }
+    resort_beam();
     launch_init_plasma<T>(lat_, p_, cfg_.n0 / (cfg_.ppc_x * cfg_.ppc_y), st_);
     for (int b = 0; b < 3; ++b)
       for (int c = 0; c < 2; ++c) launch_zero_t<T>(b_[b][c], plane(), st_);
@@ -223,6 +216,17 @@ class Box final : public BoxBase {
     slices_done_ = 0;
     dst_solves_ = 0;
     pushes_ = 0;
+  }
+
+  // A beam pushed during a box is sorted by slice again before the next box
+  // (its particles keep their slice for the whole of a box).
+  void resort_beam() {
+    if (beam_n_ == 0 || !beam_dirty_) return;
+    QSP_HIP(hipMemcpyAsync(beam_tmp_, beam_soa_, 7 * beam_n_ * sizeof(float),
+                           hipMemcpyDeviceToDevice, st_));
+    beam_sort(beam_tmp_, beam_soa_, beam_n_, cfg_.zeta_hi, cfg_.dzeta, cfg_.nzeta, bs_, beam_off_,
+              st_);
+    beam_dirty_ = false;
   }
 
   void set_beam_gaussian(const double* amp, double sx, double sy, double x0,
@@ -393,6 +397,7 @@ class Box final : public BoxBase {
   }
 
   void set_state(const qsp_slice_state* s) override {
+    resort_beam();
     const size_t np = static_cast<size_t>(lat_.np);
     const size_t nn = nodes();
     double* tmp = nullptr;

@@ -158,6 +158,29 @@ def explicit_currents(cfg: BoxConfig, peak: float = 0.8, seed: int = SEED) -> np
     return J
 
 
+def emittance_study(n: int = 256, nzeta: int = 256, n_per_beam: int = 2 ** 15,
+                    witness_zeta: float = -4.0,
+                    seed: int = SEED) -> tuple[BoxConfig, ParticleBeam]:
+    """Reduced reference setup for a precision study: the C3 geometry at
+    n x n x nzeta, driver and witness macro-particle beams (gamma = 2000),
+    the witness with zero initial emittance (u_perp = 0) and its centroid
+    offset transversely by one sigma_x.  The witness sits inside the first
+    bubble (zeta = -4: focusing Ex - By = x/2 and accelerating); at the C3
+    position zeta = -5 it would straddle the back of the bubble, where the
+    field defocuses.  Driver and witness carry different macro weights,
+    which identify them after the beam has been re-sorted."""
+    cfg = c3_config(n, nzeta)
+    rng = np.random.default_rng(seed + 7)
+    d = gaussian_particle_beam(n_per_beam, C3_DRIVER["peak"], C3_DRIVER["sigma_r"],
+                               C3_DRIVER["sigma_z"], C3_DRIVER["zeta_c"], C3_GAMMA, rng)
+    w = gaussian_particle_beam(n_per_beam, C3_WITNESS["peak"], C3_WITNESS["sigma_r"],
+                               C3_WITNESS["sigma_z"], witness_zeta, C3_GAMMA, rng)
+    w.x = w.x + C3_WITNESS["sigma_r"]
+    beam = ParticleBeam(*(np.concatenate([getattr(d, f.name), getattr(w, f.name)])
+                          for f in dataclasses.fields(ParticleBeam)[:7]), dt=BEAM_DT)
+    return cfg, beam
+
+
 def ion_column(n: int = 64, nzeta: int = 4, extent: float = 4.0, x0: float = 0.2,
                gamma: float = 2000.0, dt: float = BEAM_DT, w: float = 1e-8):
     """Beam test particles in a pure ion column: the box holds ions of
