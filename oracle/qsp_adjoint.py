@@ -89,26 +89,55 @@ def forward_with_tape(cfg, beam):
 # Transposed building blocks
 # --------------------------------------------------------------------------
 
+def shape_1d_grad(s, n: int, order: int):
+    """Derivatives d w / d s of the ``shape_1d`` weights (orders 1-3; the
+    order-0 shape is discontinuous and has no adjoint)."""
+    s = np.asarray(s, dtype=np.float64)
+    if order == 1:
+        b = np.clip(np.floor(s).astype(np.int64), 0, n - 1)
+        return [-np.ones_like(s), np.ones_like(s)]
+    if order == 2:
+        b = np.floor(s + 0.5).astype(np.int64)
+        d = s - b
+        return [-(0.5 - d), -2.0 * d, 0.5 + d]
+    if order == 3:
+        b = np.floor(s).astype(np.int64)
+        d = s - b
+        return [-0.5 * (1.0 - d) ** 2, (-12.0 * d + 9.0 * d * d) / 6.0,
+                (3.0 + 6.0 * d - 9.0 * d * d) / 6.0, 0.5 * d * d]
+    raise ValueError("the adjoint needs a shape of order 1, 2 or 3")
+
+
 def cic_grad(cfg, x, y):
-    """Nodes, weights S and their derivatives dS/dx, dS/dy (CIC)."""
-    nodes, wts = O.cic_weights(cfg, x, y)
+    """Nodes, weights S and their derivatives dS/dx, dS/dy for the
+    configured shape (tensor products of ``shape_1d`` and its derivative)."""
+    o = O.shape_order(cfg)
     sx = (x - cfg.x_lo) / cfg.hx
     sy = (y - cfg.y_lo) / cfg.hy
-    i = np.clip(np.floor(sx).astype(np.int64), 0, cfg.nx - 1)
-    j = np.clip(np.floor(sy).astype(np.int64), 0, cfg.ny - 1)
-    fx, fy = sx - i, sy - j
-    ihx, ihy = 1.0 / cfg.hx, 1.0 / cfg.hy
-    dx = [-(1 - fy) * ihx, (1 - fy) * ihx, -fy * ihx, fy * ihx]
-    dy = [-(1 - fx) * ihy, -fx * ihy, (1 - fx) * ihy, fx * ihy]
+    ni, wi = O.shape_1d(sx, cfg.nx, o)
+    nj, wj = O.shape_1d(sy, cfg.ny, o)
+    di = shape_1d_grad(sx, cfg.nx, o)
+    dj = shape_1d_grad(sy, cfg.ny, o)
+    nodes, wts, dx, dy = [], [], [], []
+    for j, wy, dwy in zip(nj, wj, dj):
+        for i, wx, dwx in zip(ni, wi, di):
+            nodes.append((i, j))
+            wts.append(wx * wy)
+            dx.append(dwx * wy / cfg.hx)
+            dy.append(wx * dwy / cfg.hy)
     return nodes, wts, dx, dy
 
 
 def gather_grad(cfg, F, x, y):
-    """Value of the CIC interpolant of F at the particles and its gradient."""
+    """Value of the shape interpolant of F at the particles and its gradient."""
     nodes, wts, dx, dy = cic_grad(cfg, x, y)
-    v = sum(F[j, i] * s for (i, j), s in zip(nodes, wts))
-    gx = sum(F[j, i] * d for (i, j), d in zip(nodes, dx))
-    gy = sum(F[j, i] * d for (i, j), d in zip(nodes, dy))
+    v = gx = gy = 0.0
+    for (i, j), s, ddx, ddy in zip(nodes, wts, dx, dy):
+        ok = O._valid(cfg, i, j)
+        f = np.where(ok, F[np.clip(j, 0, cfg.ny), np.clip(i, 0, cfg.nx)], 0.0)
+        v = v + f * s
+        gx = gx + f * ddx
+        gy = gy + f * ddy
     return v, gx, gy
 
 

@@ -112,6 +112,61 @@ def init_plasma(cfg) -> Plasma:
                   hist=np.zeros((4, 5, n)))
 
 
+def shape_1d(s, n: int, order: int):
+    """Transverse particle shape of order 0-3 (Sec. III.B: orders 0-3 are
+    available transversely) along one axis: the centred B-spline of degree
+    ``order`` (the box function convolved with itself ``order`` times)
+    evaluated at the node offsets, for positions s in node units
+    (0 <= s <= n).  Returns (node index arrays, weight arrays); nodes may fall
+    outside 0..n, where the field is zero and deposits are dropped.
+
+      order 0 (NGP): nearest node b = floor(s + 1/2)
+      order 1 (CIC): b = floor(s) (b = n - 1 at s = n), d = s - b:
+                     (1 - d, d) on (b, b + 1)
+      order 2:       b = floor(s + 1/2), d = s - b in [-1/2, 1/2):
+                     ((1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2) on b-1 .. b+1
+      order 3:       b = floor(s), d = s - b in [0, 1):
+                     ((1-d)^3, 4 - 6d^2 + 3d^3, 1 + 3d + 3d^2 - 3d^3, d^3) / 6 on b-1 .. b+2
+    """
+    s = np.asarray(s, dtype=np.float64)
+    if order == 0:
+        b = np.floor(s + 0.5).astype(np.int64)
+        return [b], [np.ones_like(s)]
+    if order == 1:
+        b = np.clip(np.floor(s).astype(np.int64), 0, n - 1)
+        d = s - b
+        return [b, b + 1], [1.0 - d, d]
+    if order == 2:
+        b = np.floor(s + 0.5).astype(np.int64)
+        d = s - b
+        return [b - 1, b, b + 1], [0.5 * (0.5 - d) ** 2, 0.75 - d * d, 0.5 * (0.5 + d) ** 2]
+    if order == 3:
+        b = np.floor(s).astype(np.int64)
+        d = s - b
+        return ([b - 1, b, b + 1, b + 2],
+                [(1.0 - d) ** 3 / 6.0, (4.0 - 6.0 * d * d + 3.0 * d ** 3) / 6.0,
+                 (1.0 + 3.0 * d + 3.0 * d * d - 3.0 * d ** 3) / 6.0, d ** 3 / 6.0])
+    raise ValueError("shape order must be 0, 1, 2 or 3")
+
+
+def shape_order(cfg) -> int:
+    return int(getattr(cfg, "shape_order", 1))
+
+
+def shape_weights(cfg, x, y):
+    """2D tensor-product shape of the configured order: lists of node index
+    pairs and weights (one entry per stencil node)."""
+    o = shape_order(cfg)
+    ni, wi = shape_1d((x - cfg.x_lo) / cfg.hx, cfg.nx, o)
+    nj, wj = shape_1d((y - cfg.y_lo) / cfg.hy, cfg.ny, o)
+    nodes, wts = [], []
+    for j, wy in zip(nj, wj):
+        for i, wx in zip(ni, wi):
+            nodes.append((i, j))
+            wts.append(wx * wy)
+    return nodes, wts
+
+
 def cic_weights(cfg, x, y):
     """Linear (CIC) shape: the particle in cell (i, j) with fractional
     offsets (fx, fy) gives weights (1-fx)(1-fy), fx(1-fy), (1-fx)fy, fx*fy
@@ -127,23 +182,33 @@ def cic_weights(cfg, x, y):
     return nodes, wts
 
 
+def _valid(cfg, i, j):
+    return (i >= 0) & (i <= cfg.nx) & (j >= 0) & (j <= cfg.ny)
+
+
 def deposit_values(cfg, x, y, values: np.ndarray) -> np.ndarray:
-    """Scatter-add per-particle density ``values`` to the nodes with the CIC
-    shape (zeroth order in zeta); deposits on boundary nodes are dropped."""
+    """Scatter-add per-particle density ``values`` to the nodes with the
+    configured transverse shape (zeroth order in zeta); deposits on or
+    beyond the boundary nodes are dropped."""
     out = np.zeros((cfg.ny + 1) * (cfg.nx + 1))
-    nodes, wts = cic_weights(cfg, x, y)
+    nodes, wts = shape_weights(cfg, x, y)
     for (i, j), s in zip(nodes, wts):
-        out += np.bincount(j * (cfg.nx + 1) + i, weights=values * s,
+        ok = _valid(cfg, i, j)
+        out += np.bincount((j * (cfg.nx + 1) + i)[ok], weights=(values * s)[ok],
                            minlength=out.size)
     return zero_boundary(out.reshape(cfg.ny + 1, cfg.nx + 1))
 
 
 def gather(cfg, field: np.ndarray, x, y) -> np.ndarray:
-    """Interpolate a node field to the particles with the same CIC shape
-    (the transpose of ``deposit_values`` up to the 1/(hx hy) density
-    normalisation)."""
-    nodes, wts = cic_weights(cfg, x, y)
-    return sum(field[j, i] * s for (i, j), s in zip(nodes, wts))
+    """Interpolate a node field to the particles with the same shape (the
+    transpose of ``deposit_values`` up to the 1/(hx hy) density
+    normalisation); nodes beyond the box read zero."""
+    nodes, wts = shape_weights(cfg, x, y)
+    total = 0.0
+    for (i, j), s in zip(nodes, wts):
+        ok = _valid(cfg, i, j)
+        total = total + np.where(ok, field[np.clip(j, 0, cfg.ny), np.clip(i, 0, cfg.nx)], 0.0) * s
+    return total
 
 
 def clamp_d(cfg, psi):
@@ -179,10 +244,30 @@ def plasma_deposit(cfg, p: Plasma, channels: Sequence[str] = DEPOSITS):
     return {c: deposit_values(cfg, p.x, p.y, per[c]) for c in channels}
 
 
+def ion_density(cfg) -> np.ndarray:
+    """Density of the immobile ions (Sec. II: ions remain practically
+    immobile).  They are taken as a neutralising species sitting on the
+    electrons' rest lattice and deposited with the same transverse shape, so
+    the unperturbed plasma is neutral node by node for every shape order,
+    also next to the box edge where a stencil of order >= 2 reaches past it.
+    For order 1 this is n0 at every interior node."""
+    key = (cfg.nx, cfg.ny, cfg.ppc_x, cfg.ppc_y, cfg.x_lo, cfg.y_lo, cfg.hx,
+           cfg.hy, cfg.n0, shape_order(cfg))
+    ion = _ION_CACHE.get(key)
+    if ion is None:
+        p = init_plasma(cfg)
+        ion = deposit_values(cfg, p.x, p.y, p.w / (cfg.hx * cfg.hy))
+        _ION_CACHE[key] = ion
+    return ion
+
+
+_ION_CACHE: dict = {}
+
+
 def add_ion_background(cfg, dep: dict) -> dict:
-    """Immobile ions of density n0: +n0 to rho (and rho - Jz) everywhere
-    inside the box (Sec. II: the ions remain practically immobile)."""
-    ion = zero_boundary(np.full((cfg.ny + 1, cfg.nx + 1), cfg.n0))
+    """Add the ion charge density to rho and rho - Jz (the ions carry no
+    current)."""
+    ion = ion_density(cfg)
     for c in ("rho_mjz", "rho"):
         if c in dep:
             dep[c] = dep[c] + ion

@@ -28,10 +28,11 @@ def loss(cfg, beam, cot):
     return A.loss_value(recs, cot)
 
 
-@pytest.mark.parametrize("ppc,nb", [(1, 0.8), (2, 1.5)])
-def test_adjoint_matches_central_differences(ppc, nb):
+@pytest.mark.parametrize("ppc,nb,order", [(1, 0.8, 1), (2, 1.5, 1), (1, 0.8, 2), (1, 0.8, 3)])
+def test_adjoint_matches_central_differences(ppc, nb, order):
     cfg, beam = W.small(n=16, nzeta=14, ppc=ppc, nb=nb, sigma=0.9, pc_max_iter=2,
                         pc_tol=0.0, extent=4.0)
+    cfg.shape_order = order
     cot = cot_all_fields(cfg, 7, 11)
     recs, tape = A.forward_with_tape(cfg, beam)
     ga, gsx, gsy = A.adjoint_box(cfg, beam, tape, cot)

@@ -59,6 +59,7 @@ class BoxConfig:
     pc_tol: float = 0.0          # <= 0: always pc_max_iter iterations
     pc_shift: Optional[float] = None   # None: the method's default screening
     psi_floor: float = ONE_PLUS_PSI_FLOOR
+    shape_order: int = 1         # transverse particle shape: 0 NGP, 1 CIC, 2 and 3 B-splines
 
     @property
     def hx(self) -> float:
