@@ -34,7 +34,8 @@ METRIC = "plasma particle-slice updates/s + DST solves/s; FP32 vs FP64; fwd+bwd/
 # counter runs (scaled by a 256 MiB copy), valid while the push kernel's
 # sources hash to this value
 PUSH_TRAFFIC = {"sources": ["paper_2109_10277_amd/csrc/particles.hip",
-                            "paper_2109_10277_amd/csrc/push_tile.hpp"],
+                            "paper_2109_10277_amd/csrc/push_tile.hpp",
+                            "paper_2109_10277_amd/csrc/shape.hpp"],
                 "sha256_prefix": "1667717135d8a419", "workload": "c2", "bytes": 64.24e6,
                 "summary": "profiles/hbm_traffic_c2_blowout_512x512x1024_fp32.md"}
 

@@ -91,7 +91,15 @@ enum {
  *            particle contribution straight to global FP64 atomics (same
  *            result up to summation order; kept for differential testing).
  *   mem_cap_bytes: 0 = no cap, else creation fails with
- *            QSP_ERR_OUT_OF_MEMORY if the context would hold more. */
+ *            QSP_ERR_OUT_OF_MEMORY if the context would hold more.
+ *   shape_order: transverse particle shape of plasma and beam deposit and
+ *            gather (Sec. III.B: orders 0-3 transversely, zeroth order in
+ *            zeta), the centred B-spline of that degree: 0 nearest node,
+ *            1 linear (CIC, the usual choice), 2 quadratic, 3 cubic.  A
+ *            zero-initialised config selects 0.  The ions are the
+ *            electrons' rest lattice deposited with the same shape, so the
+ *            unperturbed plasma is neutral at every node.
+ *   reserved1: set to 0. */
 typedef struct {
   int32_t nx, ny;
   double x_lo, x_hi, y_lo, y_hi;
@@ -106,6 +114,8 @@ typedef struct {
   double pc_shift;
   double psi_floor;
   int64_t mem_cap_bytes;
+  int32_t shape_order; /* 0..3 */
+  int32_t reserved1;
 } qsp_config;
 
 /* Per-slice outputs of qsp_advance_slice: one device pointer per quantity
@@ -290,8 +300,10 @@ typedef struct {
  * the per-slice record of the last chunk of slices.  Device memory grows by
  * about ceil(n_slices/ckpt_every) slice states plus ckpt_every records;
  * mem_cap_bytes applies.  Requires the cursor at 0, a Gaussian beam, and no
- * macro-particle beam that moves (dt != 0); 1 <= n_slices <= nzeta,
- * ckpt_every >= 1.  Synchronises. */
+ * macro-particle beam that moves (dt != 0) -> else QSP_ERR_BAD_STATE;
+ * 1 <= n_slices <= nzeta, ckpt_every >= 1 and shape_order >= 1 (the
+ * nearest-node shape has no derivative) -> else QSP_ERR_INVALID_ARG.
+ * Synchronises. */
 qsp_status qsp_run_box_record(qsp_ctx ctx, int32_t n_slices, int32_t ckpt_every,
                               const qsp_box_out* out, qsp_stats* stats);
 

@@ -1,9 +1,10 @@
 // Adjoint (reverse-mode) kernels of the slice loop.  Every kernel is the
 // transpose of a forward step of the HiPACE++ slice routine (arXiv:2109.10277
 // Sec. II, III.B) as the forward kernels discretise it:
-//   * field gather (CIC)            -> FP64 scatter of the gathered adjoints
+//   * field gather (shape S of order 1-3)
+//                                   -> FP64 scatter of the gathered adjoints
 //                                      plus grad-S position terms;
-//   * deposit (CIC)                 -> gather of the adjoint planes with S and
+//   * deposit (shape S)             -> gather of the adjoint planes with S and
 //                                      grad S;
 //   * pusher right-hand side        -> its Jacobian, transposed;
 //   * Adams-Bashforth step          -> adjoint history ring (slot s holds the
@@ -14,6 +15,7 @@
 // particles and floored 1+Psi are locally constant.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "shape.hpp"
 
 namespace qsp {
 
@@ -21,52 +23,88 @@ namespace {
 
 __device__ inline void gadd(double* p, double v) { unsafeAtomicAdd(p, v); }
 
-template <typename T>
-__device__ inline T at(const T* __restrict__ F, int i, int j, int nx, int ny) {
-  return (i < nx && j < ny) ? F[static_cast<size_t>(j) * nx + i] : T(0);
-}
-
 // node value with the Dirichlet nodes (index 0 and n) read as zero
 template <typename T>
 __device__ inline T inner(const T* __restrict__ F, int i, int j, int nx, int ny) {
   return (i >= 1 && j >= 1 && i < nx && j < ny) ? F[static_cast<size_t>(j) * nx + i] : T(0);
 }
 
-// value and xi-gradient of the CIC interpolant of F in cell (i, j)
-template <typename T, typename R>
-__device__ inline void interp(const T* __restrict__ F, int i, int j, R fx, R fy, int nx, int ny,
-                              R& v, R& gx, R& gy) {
-  const R f00 = static_cast<R>(at(F, i, j, nx, ny)), f10 = static_cast<R>(at(F, i + 1, j, nx, ny));
-  const R f01 = static_cast<R>(at(F, i, j + 1, nx, ny)), f11 = static_cast<R>(at(F, i + 1, j + 1, nx, ny));
-  v = (R(1) - fx) * (R(1) - fy) * f00 + fx * (R(1) - fy) * f10 + (R(1) - fx) * fy * f01 + fx * fy * f11;
-  gx = (f10 - f00) * (R(1) - fy) + (f11 - f01) * fy;
-  gy = (f01 - f00) * (R(1) - fx) + (f11 - f10) * fx;
-}
+// One axis of a particle's stencil: lowest node b, fraction d, clamped node
+// indices, and the shape weights and their slopes (per cell) in precision R,
+// zero on the nodes that are not stored.
+template <int O, typename R>
+struct Axis {
+  int b;
+  R d;
+  int idx[O + 1];
+  R w[O + 1], g[O + 1];
+};
 
-__device__ inline void scatter4(double* P, int i, int j, double fx, double fy, int nx, int ny,
-                                double v) {
-  if (v == 0.0) return;
-  const double s[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
-  const int di[4] = {0, 1, 0, 1}, dj[4] = {0, 0, 1, 1};
+template <int O, typename R>
+__device__ inline Axis<O, R> make_axis(int b, R d, int n) {
+  Axis<O, R> A;
+  A.b = b;
+  A.d = d;
+  bool ok[O + 1];
+  shape::weights<O>(d, A.w);
+  shape::weight_slopes<O>(d, A.g);
+  shape::axis_nodes<O>(b, n, A.idx, ok);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int a = i + di[q], b = j + dj[q];
-    if (a >= 1 && a < nx && b >= 1 && b < ny) gadd(P + static_cast<size_t>(b) * nx + a, v * s[q]);
+  for (int q = 0; q <= O; ++q) {
+    A.w[q] = ok[q] ? A.w[q] : R(0);
+    A.g[q] = ok[q] ? A.g[q] : R(0);
+  }
+  return A;
+}
+
+template <int O, typename T>
+__device__ inline Axis<O, T> locate_axis(int c0, T t, int n) {
+  int b;
+  const T d = shape::locate<O>(c0, t, n, b);
+  return make_axis<O, T>(b, d, n);
+}
+
+// value and position gradient (per cell) of the shape interpolant of F
+template <int O, typename T, typename R>
+__device__ inline void interp(const T* __restrict__ F, const Axis<O, R>& X, const Axis<O, R>& Y,
+                              int nx, R& v, R& gx, R& gy) {
+  v = R(0);
+  gx = R(0);
+  gy = R(0);
+#pragma unroll
+  for (int b = 0; b <= O; ++b) {
+    const T* row = F + static_cast<size_t>(Y.idx[b]) * nx;
+    R rv = R(0), rg = R(0);
+#pragma unroll
+    for (int a = 0; a <= O; ++a) {
+      const R f = static_cast<R>(row[X.idx[a]]);
+      rv += X.w[a] * f;
+      rg += X.g[a] * f;
+    }
+    v += Y.w[b] * rv;
+    gx += Y.w[b] * rg;
+    gy += Y.g[b] * rv;
   }
 }
 
-template <typename T>
-__device__ inline void locate_c(int c0, T t, int n, int& c, T& f) {
-  const T fl = floor(t);
-  c = c0 + static_cast<int>(fl);
-  f = t - fl;
-  if (c >= n) {
-    c = n - 1;
-    f = T(1);
-  }
-  if (c < 0) {
-    c = 0;
-    f = T(0);
+// FP64 scatter of v S (weights in FP64 from the fraction) onto the interior
+// nodes: the transpose of the gather
+template <int O, typename R>
+__device__ inline void scatter(double* P, const Axis<O, R>& X, const Axis<O, R>& Y, int nx, int ny,
+                               double v) {
+  if (v == 0.0) return;
+  double sx[O + 1], sy[O + 1];
+  shape::weights<O>(static_cast<double>(X.d), sx);
+  shape::weights<O>(static_cast<double>(Y.d), sy);
+#pragma unroll
+  for (int b = 0; b <= O; ++b) {
+    const int j = Y.b + b;
+#pragma unroll
+    for (int a = 0; a <= O; ++a) {
+      const int i = X.b + a;
+      if (i >= 1 && i < nx && j >= 1 && j < ny)
+        gadd(P + static_cast<size_t>(j) * nx + i, v * (sx[a] * sy[b]));
+    }
   }
 }
 
@@ -85,7 +123,7 @@ __device__ inline bool inside_c(int c0, T t, int n) {
 // f_k is consumed.  Trial: the adjoint of the trial state comes from the
 // trial-current adjoints (Jx~ = +lsb_y/2dz, Jy~ = -lsb_x/2dz) gathered at the
 // trial position and is added to lam_y.
-template <typename T, int MODE>
+template <typename T, int MODE, int O>
 __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushArgs<T> a) {
   const int64_t np = L.np;
   const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -113,14 +151,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushA
 #pragma unroll
     for (int c = 0; c < 5; ++c) h[m][c] = a.p.hist[(static_cast<size_t>(slot[m]) * 5 + c) * np + p];
   // gather with gradients at the current position
-  int ci, cj;
-  T fx, fy;
-  locate_c(ci0, fx0 + y[0], nx, ci, fx);
-  locate_c(cj0, fy0 + y[1], ny, cj, fy);
+  const Axis<O, T> X = locate_axis<O>(ci0, fx0 + y[0], nx);
+  const Axis<O, T> Y = locate_axis<O>(cj0, fy0 + y[1], ny);
   T v[6], gx[6], gy[6];
   const T* F[6] = {a.f.exmby, a.f.eypbx, a.f.ez, a.f.bx, a.f.by, a.f.bz};
 #pragma unroll
-  for (int c = 0; c < 6; ++c) interp(F[c], ci, cj, fx, fy, nx, ny, v[c], gx[c], gy[c]);
+  for (int c = 0; c < 6; ++c) interp(F[c], X, Y, nx, v[c], gx[c], gy[c]);
   const T e1 = v[0], e2 = v[1], ez = v[2], bx = v[3], by = v[4], bz = v[5];
   const T ux = y[2], uy = y[3];
   const T draw = T(1) + y[4];
@@ -158,13 +194,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushA
   } else {
     if (moved) {
       // deposit transpose of Jx~, Jy~ at the trial state
-      int ti, tj;
-      T tfx, tfy;
-      locate_c(ci0, fx0 + yn[0], nx, ti, tfx);
-      locate_c(cj0, fy0 + yn[1], ny, tj, tfy);
+      const Axis<O, T> TX = locate_axis<O>(ci0, fx0 + yn[0], nx);
+      const Axis<O, T> TY = locate_axis<O>(cj0, fy0 + yn[1], ny);
       T gjx, gjx_x, gjx_y, gjy, gjy_x, gjy_y;
-      interp(a.lsb_y, ti, tj, tfx, tfy, nx, ny, gjx, gjx_x, gjx_y);
-      interp(a.lsb_x, ti, tj, tfx, tfy, nx, ny, gjy, gjy_x, gjy_y);
+      interp(a.lsb_y, TX, TY, nx, gjx, gjx_x, gjx_y);
+      interp(a.lsb_x, TX, TY, nx, gjy, gjy_x, gjy_y);
       const T s2 = static_cast<T>(a.inv2dz);
       gjx *= s2; gjx_x *= s2; gjx_y *= s2;
       gjy *= -s2; gjy_x *= -s2; gjy_y *= -s2;
@@ -214,8 +248,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushA
   for (int c = 0; c < 6; ++c) {
     lam[0] += lg[c] * gx[c];
     lam[1] += lg[c] * gy[c];
-    scatter4(a.lam_F[c], ci, cj, static_cast<double>(fx), static_cast<double>(fy), nx, ny,
-             static_cast<double>(lg[c]));
+    scatter(a.lam_F[c], X, Y, nx, ny, static_cast<double>(lg[c]));
   }
   if (MODE == 0) {
 #pragma unroll
@@ -228,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushA
 
 // Transpose of the deposit at the slice-k state: gathers the adjoints of
 // rho-Jz, Jx, Jy, Jz (FP64 planes) with S and grad S.
-template <typename T>
+template <typename T, int O>
 __global__ void __launch_bounds__(kBlock) k_adj_deposit(Geom g, Lattice L, AdjDepArgs<T> a) {
   const int64_t np = L.np;
   const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -241,10 +274,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_deposit(Geom g, Lattice L, AdjDe
   const T fx0 = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
   const T fy0 = (T(2 * (J & (L.ppc_y - 1)) + 1)) / T(2 * L.ppc_y);
   const T xi = a.p.xi_x[p], eta = a.p.xi_y[p], ux = a.p.ux[p], uy = a.p.uy[p], psi = a.p.psi[p];
-  int ci, cj;
-  T fx, fy;
-  locate_c(I >> lpx, fx0 + xi, nx, ci, fx);
-  locate_c(J >> lpy, fy0 + eta, ny, cj, fy);
+  int bi, bj;
+  const T dx = shape::locate<O>(I >> lpx, fx0 + xi, nx, bi);
+  const T dy = shape::locate<O>(J >> lpy, fy0 + eta, ny, bj);
+  const Axis<O, double> X = make_axis<O, double>(bi, static_cast<double>(dx), nx);
+  const Axis<O, double> Y = make_axis<O, double>(bj, static_cast<double>(dy), ny);
   const T floor_d = static_cast<T>(a.psi_floor);
   const T draw = T(1) + psi;
   const bool un = !(draw < floor_d);
@@ -260,8 +294,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_deposit(Geom g, Lattice L, AdjDe
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     double v, gxv, gyv;
-    interp(a.lam_dep[c], ci, cj, static_cast<double>(fx), static_cast<double>(fy), nx, ny, v, gxv,
-           gyv);
+    interp(a.lam_dep[c], X, Y, nx, v, gxv, gyv);
     l[0] += val[c] * static_cast<T>(gxv);
     l[1] += val[c] * static_cast<T>(gyv);
     l[2] += dux[c] * static_cast<T>(v);
@@ -484,21 +517,41 @@ dim3 gp(int64_t n) {
   if (b < 1) b = 1;
   return dim3(static_cast<unsigned>(b));
 }
+
+// the adjoint needs a shape with a derivative: orders 1-3
+template <typename F>
+void with_adj_order(int order, F&& f) {
+  switch (order) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    default: throw std::invalid_argument("the adjoint needs a shape order of 1, 2 or 3");
+  }
+}
 }  // namespace
 
 template <typename T>
 void launch_adj_push(const Geom& g, const Lattice& L, const AdjPushArgs<T>& a, bool trial,
                      hipStream_t st) {
   if (trial)
-    hipLaunchKernelGGL((k_adj_push<T, 1>), gp(L.np), dim3(kBlock), 0, st, g, L, a);
+    with_adj_order(g.order, [&](auto order) {
+      hipLaunchKernelGGL((k_adj_push<T, 1, decltype(order)::value>), gp(L.np), dim3(kBlock), 0,
+                         st, g, L, a);
+    });
   else
-    hipLaunchKernelGGL((k_adj_push<T, 0>), gp(L.np), dim3(kBlock), 0, st, g, L, a);
+    with_adj_order(g.order, [&](auto order) {
+      hipLaunchKernelGGL((k_adj_push<T, 0, decltype(order)::value>), gp(L.np), dim3(kBlock), 0,
+                         st, g, L, a);
+    });
   QSP_LAUNCH_CHECK();
 }
 
 template <typename T>
 void launch_adj_deposit(const Geom& g, const Lattice& L, const AdjDepArgs<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_deposit<T>, gp(L.np), dim3(kBlock), 0, st, g, L, a);
+  with_adj_order(g.order, [&](auto order) {
+    hipLaunchKernelGGL((k_adj_deposit<T, decltype(order)::value>), gp(L.np), dim3(kBlock), 0, st,
+                       g, L, a);
+  });
   QSP_LAUNCH_CHECK();
 }
 

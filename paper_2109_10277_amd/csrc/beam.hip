@@ -1,11 +1,12 @@
 // Macro-particle beams (HiPACE++, arXiv:2109.10277, Sec. III.A): the beam is
 // sorted by slice once per box, and inside the slice loop the particles of
 // slice k deposit their charge and longitudinal current (zeroth order in
-// zeta, CIC transversely) before the field solves, then take one time step
+// zeta, transverse shape of order 0-3) before the field solves, then take one time step
 // (second-order drift-kick-drift with a Boris kick) in the fields of slice k
 // once those are final.  The slice sort is rocPRIM's stable radix sort.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "shape.hpp"
 
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -49,39 +50,33 @@ __global__ void k_beam_permute(const float* __restrict__ in, int64_t n,
   }
 }
 
-// CIC cell and offset of an absolute position; false outside [lo, lo + n h]
-__device__ inline bool cic(double x, double lo, double h, int n, int& i, double& f) {
-  const double s = (x - lo) / h;
-  if (!(s >= 0.0 && s <= static_cast<double>(n))) return false;
-  double fl = floor(s);
-  i = static_cast<int>(fl);
-  f = s - fl;
-  if (i >= n) {
-    i = n - 1;
-    f = 1.0;
-  }
-  return true;
+// node coordinate of an absolute position; false outside [lo, lo + n h]
+__device__ inline bool node_coord(double x, double lo, double h, int n, double& s) {
+  s = (x - lo) / h;
+  return s >= 0.0 && s <= static_cast<double>(n);
 }
 
 __device__ inline void add_node(double* p, int i, int j, int nx, int ny, double v) {
   if (i >= 1 && i < nx && j >= 1 && j < ny) unsafeAtomicAdd(p + static_cast<size_t>(j) * nx + i, v);
 }
 
-template <typename T>
-__device__ inline double node_val(const T* F, int i, int j, int nx, int ny) {
-  return (i < nx && j < ny) ? static_cast<double>(F[static_cast<size_t>(j) * nx + i]) : 0.0;
-}
-
-template <typename T>
-__device__ inline double gather_d(const T* F, int i, int j, double fx, double fy, int nx, int ny) {
-  return (1 - fx) * (1 - fy) * node_val(F, i, j, nx, ny) + fx * (1 - fy) * node_val(F, i + 1, j, nx, ny) +
-         (1 - fx) * fy * node_val(F, i, j + 1, nx, ny) + fx * fy * node_val(F, i + 1, j + 1, nx, ny);
+// shape weights of one axis, zero on the nodes that are not stored
+template <int O>
+__device__ inline void axis(double s, int n, int (&idx)[O + 1], double (&w)[O + 1]) {
+  int b;
+  const double d = shape::locate<O>(0, s, n, b);
+  bool ok[O + 1];
+  shape::weights<O>(d, w);
+  shape::axis_nodes<O>(b, n, idx, ok);
+#pragma unroll
+  for (int a = 0; a <= O; ++a) w[a] = ok[a] ? w[a] : 0.0;
 }
 
 }  // namespace
 
 // rho = q w / (hx hy dzeta), Jz = rho u_z / gamma, rho - Jz written as
 // rho (1 + u_perp^2) / (gamma (gamma + u_z)) so that it does not cancel
+template <int O>
 __global__ void k_beam_deposit(Geom g, const float* __restrict__ soa, int64_t n, int64_t start,
                                int64_t count, double dzeta, double* rho_mjz, double* jz,
                                double* rho) {
@@ -90,24 +85,28 @@ __global__ void k_beam_deposit(Geom g, const float* __restrict__ soa, int64_t n,
   const int64_t p = start + t;
   const double x = soa[p], y = soa[n + p];
   const double ux = soa[3 * n + p], uy = soa[4 * n + p], uz = soa[5 * n + p], w = soa[6 * n + p];
-  int i, j;
-  double fx, fy;
-  if (!cic(x, g.x_lo, g.hx, g.nx, i, fx) || !cic(y, g.y_lo, g.hy, g.ny, j, fy)) return;
+  double sx, sy;
+  if (!node_coord(x, g.x_lo, g.hx, g.nx, sx) || !node_coord(y, g.y_lo, g.hy, g.ny, sy)) return;
+  int bi, bj;
+  double wx[O + 1], wy[O + 1];
+  shape::weights<O>(shape::locate<O>(0, sx, g.nx, bi), wx);
+  shape::weights<O>(shape::locate<O>(0, sy, g.ny, bj), wy);
   const double gam = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
   const double r = -w / (g.hx * g.hy * dzeta);
   const double v[3] = {r * (1.0 + ux * ux + uy * uy) / (gam * (gam + uz)), r * uz / gam, r};
   double* ch[3] = {rho_mjz, jz, rho};
-  const double s[4] = {(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy};
-  const int di[4] = {0, 1, 0, 1}, dj[4] = {0, 0, 1, 1};
   for (int c = 0; c < 3; ++c) {
     if (!ch[c]) continue;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) add_node(ch[c], i + di[q], j + dj[q], g.nx, g.ny, v[c] * s[q]);
+    for (int qb = 0; qb <= O; ++qb)
+#pragma unroll
+      for (int qa = 0; qa <= O; ++qa)
+        add_node(ch[c], bi + qa, bj + qb, g.nx, g.ny, v[c] * (wx[qa] * wy[qb]));
   }
 }
 
 // one time step of the particles of a slice in that slice's fields
-template <typename T>
+template <typename T, int O>
 __global__ void k_beam_push(Geom g, float* soa, int64_t n, int64_t start, int64_t count,
                             SliceFields<T> f, double dt) {
   const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -119,17 +118,20 @@ __global__ void k_beam_push(Geom g, float* soa, int64_t n, int64_t start, int64_
   const double yh = soa[n + p] + 0.5 * dt * u[1] / g0;
   const double zh = soa[2 * n + p] + 0.5 * dt * (u[2] / g0 - 1.0);
   double E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
-  int i, j;
-  double fx, fy;
-  if (cic(xh, g.x_lo, g.hx, g.nx, i, fx) && cic(yh, g.y_lo, g.hy, g.ny, j, fy)) {
-    const double e1 = gather_d(f.exmby, i, j, fx, fy, g.nx, g.ny);
-    const double e2 = gather_d(f.eypbx, i, j, fx, fy, g.nx, g.ny);
-    B[0] = gather_d(f.bx, i, j, fx, fy, g.nx, g.ny);
-    B[1] = gather_d(f.by, i, j, fx, fy, g.nx, g.ny);
-    B[2] = gather_d(f.bz, i, j, fx, fy, g.nx, g.ny);
+  double sx, sy;
+  if (node_coord(xh, g.x_lo, g.hx, g.nx, sx) && node_coord(yh, g.y_lo, g.hy, g.ny, sy)) {
+    int ix[O + 1], iy[O + 1];
+    double wx[O + 1], wy[O + 1];
+    axis<O>(sx, g.nx, ix, wx);
+    axis<O>(sy, g.ny, iy, wy);
+    const double e1 = shape::interp<O>(f.exmby, ix, iy, wx, wy, g.nx);
+    const double e2 = shape::interp<O>(f.eypbx, ix, iy, wx, wy, g.nx);
+    B[0] = shape::interp<O>(f.bx, ix, iy, wx, wy, g.nx);
+    B[1] = shape::interp<O>(f.by, ix, iy, wx, wy, g.nx);
+    B[2] = shape::interp<O>(f.bz, ix, iy, wx, wy, g.nx);
     E[0] = e1 + B[1];
     E[1] = e2 - B[0];
-    E[2] = gather_d(f.ez, i, j, fx, fy, g.nx, g.ny);
+    E[2] = shape::interp<O>(f.ez, ix, iy, wx, wy, g.nx);
   }
   const double h = -0.5 * dt;   // q dt / 2 with q = -1
   double um[3], tv[3], sv[3], up[3], un[3];
@@ -193,8 +195,10 @@ size_t beam_sort_temp_bytes(int64_t n, int nzeta) {
 void launch_beam_deposit(const Geom& g, const float* soa, int64_t n, int64_t start, int64_t count,
                          double dzeta, double* rho_mjz, double* jz, double* rho, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_beam_deposit, grid_of(count), dim3(kBlock), 0, st, g, soa, n, start, count,
-                     dzeta, rho_mjz, jz, rho);
+  with_order(g.order, [&](auto order) {
+    hipLaunchKernelGGL((k_beam_deposit<decltype(order)::value>), grid_of(count), dim3(kBlock), 0,
+                       st, g, soa, n, start, count, dzeta, rho_mjz, jz, rho);
+  });
   QSP_LAUNCH_CHECK();
 }
 
@@ -202,8 +206,10 @@ template <typename T>
 void launch_beam_push(const Geom& g, float* soa, int64_t n, int64_t start, int64_t count,
                       const SliceFields<T>& f, double dt, hipStream_t st) {
   if (count <= 0) return;
-  hipLaunchKernelGGL(k_beam_push<T>, grid_of(count), dim3(kBlock), 0, st, g, soa, n, start, count,
-                     f, dt);
+  with_order(g.order, [&](auto order) {
+    hipLaunchKernelGGL((k_beam_push<T, decltype(order)::value>), grid_of(count), dim3(kBlock), 0,
+                       st, g, soa, n, start, count, f, dt);
+  });
   QSP_LAUNCH_CHECK();
 }
 

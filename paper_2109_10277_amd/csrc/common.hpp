@@ -54,6 +54,7 @@ struct Geom {
   int lx, ly;            // log2(nx), log2(ny)
   double x_lo, y_lo, hx, hy;
   int rr;                // rows per workgroup of the transform row passes
+  int order;             // transverse particle shape order, 0..3
 };
 
 // Plasma lattice: (nx*ppc_x) x (ny*ppc_y) sites, particle p = I + J*nX.

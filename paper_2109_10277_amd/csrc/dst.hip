@@ -35,7 +35,7 @@ k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
     const int o = j * n + i;
     double s;
     if (fld == 0) {
-      s = -(a.rho_mjz[o] + a.n0);
+      s = -(a.rho_mjz[o] + (a.ionx ? a.n0 * a.ionx[i] * a.iony[j] : a.n0));
     } else {
       const int ow = i > 0 ? o - 1 : o, oe = i + 1 < n ? o + 1 : o;
       const int os = j > 0 ? o - n : o, on = j + 1 < g.ny ? o + n : o;

@@ -91,7 +91,7 @@ __global__ void k_out_copy(Geom g, OutCopy c) {
     }
     if (interior) {
       if (c.add_beam[id]) v -= c.beam_amp * c.bgx[i] * c.bgy[j];
-      if (c.add_ion[id]) v += c.n0;
+      if (c.add_ion[id]) v += c.ionx ? c.n0 * c.ionx[i] * c.iony[j] : c.n0;
     }
     if (c.is_double[id])
       static_cast<double*>(c.dst[id])[e] = v;

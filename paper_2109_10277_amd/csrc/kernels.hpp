@@ -4,6 +4,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "shape.hpp"
 
 namespace qsp {
 
@@ -14,6 +15,8 @@ struct SrcPEZ {             // psi, Ez, Bz sources of slice k
   const double* jx;
   const double* jy;
   double n0;
+  const double* ionx;       // ion density n0 ionx[i] iony[j]; null: uniform n0
+  const double* iony;
   T* out;                   // 3 planes [ny][nx]: psi, Ez, Bz (x-transformed)
 };
 
@@ -185,10 +188,12 @@ struct OutCopy {
   void* dst[kMaxOut];
   int is_double[kMaxOut];   // source precision (the destination matches it)
   int add_beam[kMaxOut];    // add -n_b (Jz, rho outputs of a Gaussian beam)
-  int add_ion[kMaxOut];     // add +n0 (rho-Jz, rho outputs)
+  int add_ion[kMaxOut];     // add the ion density (rho-Jz, rho outputs)
   int kind[kMaxOut];        // 0 full plane, 1 row ny/2, 2 axis node
   int count;
   double beam_amp, n0;
+  const double* ionx;       // ion profile factors (null: uniform n0)
+  const double* iony;
   const double* bgx;
   const double* bgy;
 };

@@ -13,7 +13,7 @@ using push_detail::push_tile;
 using push_detail::tile_shape;
 using push_detail::TileShape;
 
-template <typename T, int MODE>
+template <typename T, int MODE, int O>
 __global__ void __launch_bounds__(kBlock)
 k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
   if (MODE == kPushTrial && ctr->pc_done) return;
@@ -27,7 +27,7 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
       ctr->pc_not_converged += 1ull;
   }
   extern __shared__ unsigned char smem_raw[];
-  push_tile<T, MODE>(g, L, a, ctr, blockIdx.x, blockIdx.y, reinterpret_cast<double*>(smem_raw));
+  push_tile<T, MODE, O>(g, L, a, ctr, blockIdx.x, blockIdx.y, reinterpret_cast<double*>(smem_raw));
 }
 
 template <typename T>
@@ -123,23 +123,26 @@ void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode
   const size_t lds = a.tiled ? static_cast<size_t>(nch) * ts.nw * ts.nh * sizeof(double) : 0;
   if (lds > 160 * 1024) throw std::invalid_argument("push tile histogram exceeds the LDS");
   const dim3 grid(L.nX / ts.tx, L.nY / ts.ty);
-  if (lds > 65536) {   // opt in above 64 KiB (gfx950 offers 160 KiB per workgroup)
-    const void* fn = mode == kPushReal    ? reinterpret_cast<const void*>(&k_push<T, kPushReal>)
-                     : mode == kPushTrial ? reinterpret_cast<const void*>(&k_push<T, kPushTrial>)
-                                          : reinterpret_cast<const void*>(&k_push<T, kDepositOnly>);
-    QSP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-  }
-  switch (mode) {
-    case kPushReal:
-      hipLaunchKernelGGL((k_push<T, kPushReal>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
-      break;
-    case kPushTrial:
-      hipLaunchKernelGGL((k_push<T, kPushTrial>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
-      break;
-    default:
-      hipLaunchKernelGGL((k_push<T, kDepositOnly>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
-      break;
-  }
+  auto run = [&](auto order) {
+    constexpr int O = decltype(order)::value;
+    const void* fn = mode == kPushReal    ? reinterpret_cast<const void*>(&k_push<T, kPushReal, O>)
+                     : mode == kPushTrial ? reinterpret_cast<const void*>(&k_push<T, kPushTrial, O>)
+                                          : reinterpret_cast<const void*>(&k_push<T, kDepositOnly, O>);
+    if (lds > 65536)   // opt in above 64 KiB (gfx950 offers 160 KiB per workgroup)
+      QSP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    switch (mode) {
+      case kPushReal:
+        hipLaunchKernelGGL((k_push<T, kPushReal, O>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
+        break;
+      case kPushTrial:
+        hipLaunchKernelGGL((k_push<T, kPushTrial, O>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
+        break;
+      default:
+        hipLaunchKernelGGL((k_push<T, kDepositOnly, O>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
+        break;
+    }
+  };
+  with_order(g.order, run);
   QSP_LAUNCH_CHECK();
 }
 

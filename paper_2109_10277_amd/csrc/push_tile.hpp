@@ -1,7 +1,6 @@
 // Device-side body of the fused plasma gather + Adams-Bashforth push +
-// deposit, shared by the per-launch kernels and the persistent
-// predictor-corrector kernel (HiPACE++, arXiv:2109.10277, Sec. III.B: plasma
-// pusher equations, CIC deposition zeroth order in zeta).
+// deposit (HiPACE++, arXiv:2109.10277, Sec. III.B: plasma pusher equations;
+// deposition zeroth order in zeta, transverse shape of order 0-3).
 //
 // Particles are stored SoA in lattice order and keep their lattice site for
 // life; positions are stored as displacements from that site (in cells) so
@@ -14,6 +13,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "shape.hpp"
 
 namespace qsp {
 namespace push_detail {
@@ -41,23 +41,6 @@ __host__ __device__ inline TileShape tile_shape(const Lattice& L, int rows, int 
   t.nw = (t.tx >> t.lpx) + 1 + 2 * halo;
   t.nh = (t.ty >> t.lpy) + 1 + 2 * halo;
   return t;
-}
-
-// cell index and offset inside the cell of a particle; clamps the upper
-// edge like the node range 0..n allows
-template <typename T>
-__device__ inline void locate(int c0, T t, int n, int& c, T& f) {
-  const T fl = floor(t);
-  c = c0 + static_cast<int>(fl);
-  f = t - fl;
-  if (c >= n) {
-    c = n - 1;
-    f = T(1);
-  }
-  if (c < 0) {
-    c = 0;
-    f = T(0);
-  }
 }
 
 template <typename T>
@@ -99,9 +82,12 @@ __device__ inline unsigned long long block_sum(unsigned int v, unsigned int* red
 }
 
 // Gather, push and deposit of the particles of lattice tile (tbx, tby) by
-// one workgroup; `tile` is the workgroup's LDS histogram (nch channels of
-// tile_shape's nw x nh nodes).  Safe to call repeatedly from one workgroup.
-template <typename T, int MODE>
+// one workgroup with the transverse shape of order O; `tile` is the
+// workgroup's LDS histogram (nch channels of tile_shape's nw x nh nodes).
+// Safe to call repeatedly from one workgroup.  The linear shape keeps a
+// gather of its own (four weights, value selects at the upper edge), which
+// the compiler allocates in fewer registers than the generic stencil.
+template <typename T, int MODE, int O>
 __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const PushArgs<T>& a,
                                           DevCounters* ctr, int tbx, int tby, double* tile) {
   // channels: trial push Jx, Jy; otherwise rho - Jz, Jx, Jy, Jz
@@ -149,18 +135,42 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
         h[2][c] = hist[(s3 * 5 + c) * np + p];
         h[3][c] = hist[(s4 * 5 + c) * np + p];
       }
-      int ci, cj;
-      T fx, fy;
-      locate(ci0, fx0 + xi, nx, ci, fx);
-      locate(cj0, fy0 + eta, ny, cj, fy);
-      const T w00 = (T(1) - fx) * (T(1) - fy), w10 = fx * (T(1) - fy);
-      const T w01 = (T(1) - fx) * fy, w11 = fx * fy;
-      const T e1 = gather(a.f.exmby, ci, cj, w00, w10, w01, w11, nx, ny);
-      const T e2 = gather(a.f.eypbx, ci, cj, w00, w10, w01, w11, nx, ny);
-      const T ez = gather(a.f.ez, ci, cj, w00, w10, w01, w11, nx, ny);
-      const T bx = gather(a.f.bx, ci, cj, w00, w10, w01, w11, nx, ny);
-      const T by = gather(a.f.by, ci, cj, w00, w10, w01, w11, nx, ny);
-      const T bz = gather(a.f.bz, ci, cj, w00, w10, w01, w11, nx, ny);
+      T e1, e2, ez, bx, by, bz;
+      if constexpr (O == 1) {
+        int ci, cj;
+        const T fx = shape::locate<1>(ci0, fx0 + xi, nx, ci);
+        const T fy = shape::locate<1>(cj0, fy0 + eta, ny, cj);
+        const T w00 = (T(1) - fx) * (T(1) - fy), w10 = fx * (T(1) - fy);
+        const T w01 = (T(1) - fx) * fy, w11 = fx * fy;
+        e1 = gather(a.f.exmby, ci, cj, w00, w10, w01, w11, nx, ny);
+        e2 = gather(a.f.eypbx, ci, cj, w00, w10, w01, w11, nx, ny);
+        ez = gather(a.f.ez, ci, cj, w00, w10, w01, w11, nx, ny);
+        bx = gather(a.f.bx, ci, cj, w00, w10, w01, w11, nx, ny);
+        by = gather(a.f.by, ci, cj, w00, w10, w01, w11, nx, ny);
+        bz = gather(a.f.bz, ci, cj, w00, w10, w01, w11, nx, ny);
+      } else {
+        int bi, bj;
+        const T dx = shape::locate<O>(ci0, fx0 + xi, nx, bi);
+        const T dy = shape::locate<O>(cj0, fy0 + eta, ny, bj);
+        T wx[O + 1], wy[O + 1];
+        int ix[O + 1], iy[O + 1];
+        bool okx[O + 1], oky[O + 1];
+        shape::weights<O>(dx, wx);
+        shape::weights<O>(dy, wy);
+        shape::axis_nodes<O>(bi, nx, ix, okx);
+        shape::axis_nodes<O>(bj, ny, iy, oky);
+#pragma unroll
+        for (int q = 0; q <= O; ++q) {
+          wx[q] = okx[q] ? wx[q] : T(0);
+          wy[q] = oky[q] ? wy[q] : T(0);
+        }
+        e1 = shape::interp<O>(a.f.exmby, ix, iy, wx, wy, nx);
+        e2 = shape::interp<O>(a.f.eypbx, ix, iy, wx, wy, nx);
+        ez = shape::interp<O>(a.f.ez, ix, iy, wx, wy, nx);
+        bx = shape::interp<O>(a.f.bx, ix, iy, wx, wy, nx);
+        by = shape::interp<O>(a.f.by, ix, iy, wx, wy, nx);
+        bz = shape::interp<O>(a.f.bz, ix, iy, wx, wy, nx);
+      }
       // right-hand side of the pusher equations for an electron (q = -1)
       const T draw = T(1) + psi;
       const T d = draw < floor_d ? floor_d : draw;
@@ -219,33 +229,37 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
       v[2] = static_cast<double>(-w * uy * id);
       v[3] = static_cast<double>(-w * uz * id);
     }
-    int ci, cj;
-    T fx, fy;
-    locate(ci0, fx0 + xi, nx, ci, fx);
-    locate(cj0, fy0 + eta, ny, cj, fy);
-    const double dfx = static_cast<double>(fx), dfy = static_cast<double>(fy);
-    const double s[4] = {(1.0 - dfx) * (1.0 - dfy), dfx * (1.0 - dfy), (1.0 - dfx) * dfy,
-                         dfx * dfy};
-    const int li = ci - ox, lj = cj - oy;
-    if (tiled && li >= 0 && li + 1 < ts.nw && lj >= 0 && lj + 1 < ts.nh) {
+    int bi, bj;
+    const T dx = shape::locate<O>(ci0, fx0 + xi, nx, bi);
+    const T dy = shape::locate<O>(cj0, fy0 + eta, ny, bj);
+    double sx[O + 1], sy[O + 1];
+    shape::weights<O>(static_cast<double>(dx), sx);
+    shape::weights<O>(static_cast<double>(dy), sy);
+    const int li = bi - ox, lj = bj - oy;
+    if (tiled && li >= 0 && li + O < ts.nw && lj >= 0 && lj + O < ts.nh) {
       const int base = lj * ts.nw + li;
-      const int off[4] = {0, 1, ts.nw, ts.nw + 1};
 #pragma unroll
       for (int c = 0; c < nch; ++c) {
         double* t = tile + c * ntile + base;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) lds_add(t + off[q], v[c] * s[q]);
+        for (int qb = 0; qb <= O; ++qb)
+#pragma unroll
+          for (int qa = 0; qa <= O; ++qa) lds_add(t + qb * ts.nw + qa, v[c] * (sx[qa] * sy[qb]));
       }
     } else {
       if (tiled) ++nglob;
-      const int gi[4] = {ci, ci + 1, ci, ci + 1};
-      const int gj[4] = {cj, cj, cj + 1, cj + 1};
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (gi[q] < 1 || gi[q] >= nx || gj[q] < 1 || gj[q] >= ny) continue;
-        const size_t o = static_cast<size_t>(gj[q]) * nx + gi[q];
+      for (int qb = 0; qb <= O; ++qb) {
+        const int gj = bj + qb;
 #pragma unroll
-        for (int c = 0; c < nch; ++c) global_add(a.dep.ch[c] + o, v[c] * s[q]);
+        for (int qa = 0; qa <= O; ++qa) {
+          const int gi = bi + qa;
+          if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
+          const size_t o = static_cast<size_t>(gj) * nx + gi;
+          const double s = sx[qa] * sy[qb];
+#pragma unroll
+          for (int c = 0; c < nch; ++c) global_add(a.dep.ch[c] + o, v[c] * s);
+        }
       }
     }
   }

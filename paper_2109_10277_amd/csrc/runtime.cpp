@@ -24,6 +24,33 @@ bool finite(double v) { return std::isfinite(v); }
 
 double default_pc_shift(double n0) { return 0.5 * kAB5[0] * n0; }
 
+namespace {
+template <int O>
+void deposit_lattice_point(int c, double t, int n, double scale, std::vector<double>& f) {
+  int b = 0;
+  const double d = shape::locate<O>(c, t, n, b);
+  double w[O + 1];
+  shape::weights<O>(d, w);
+  for (int a = 0; a <= O; ++a)
+    if (b + a >= 1 && b + a < n) f[b + a] += w[a] * scale;
+}
+}  // namespace
+
+std::vector<double> ion_profile(int n, int ppc, int order) {
+  // The ions sit on the electrons' rest lattice, c + (q + 1/2)/ppc in node
+  // units, and are deposited with the same shape; along one axis node i
+  // receives 1/ppc times the sum of the shape weights.  Boundary nodes are
+  // Dirichlet nodes and carry no source.
+  std::vector<double> f(n + 1, 0.0);
+  with_order(order, [&](auto o) {
+    constexpr int O = decltype(o)::value;
+    for (int c = 0; c < n; ++c)
+      for (int q = 0; q < ppc; ++q)
+        deposit_lattice_point<O>(c, (2.0 * q + 1.0) / (2.0 * ppc), n, 1.0 / ppc, f);
+  });
+  return f;
+}
+
 std::string validate(const qsp_config& c) {
   if (!pow2(c.nx) || c.nx < 16 || c.nx > 2048) return "nx must be a power of two in [16, 2048]";
   if (!pow2(c.ny) || c.ny < 16 || c.ny > 2048) return "ny must be a power of two in [16, 2048]";
@@ -42,6 +69,8 @@ std::string validate(const qsp_config& c) {
   if (!finite(c.psi_floor) || !(c.psi_floor > 0) || !(c.psi_floor < 1)) return "psi_floor must be in (0, 1)";
   if (c.mem_cap_bytes < 0) return "mem_cap_bytes must be >= 0";
   if (c.deposit_mode != 0 && c.deposit_mode != 1) return "deposit_mode must be 0 or 1";
+  if (c.shape_order < 0 || c.shape_order > 3) return "shape_order must be 0, 1, 2 or 3";
+  if (c.reserved1 != 0) return "reserved1 must be 0";
   return "";
 }
 
@@ -54,6 +83,7 @@ int64_t device_bytes_needed(const qsp_config& c) {
   b += plane * 8 * (3 * 5 + 2);                  // deposits, trial currents
   b += np * ts * (6 + 20);                       // particle SoA + history
   b += (c.nx + c.ny) * (3 * ts + 8 + 8) + 4096;  // tables, counters
+  b += (c.nx + c.ny + 2) * 8;                    // ion profile
   b += static_cast<int64_t>(c.ny) * 16 + 64;     // residual partials
   return b;
 }
@@ -158,6 +188,7 @@ class Box final : public BoxBase {
     geom_.hx = (cfg.x_hi - cfg.x_lo) / cfg.nx;
     geom_.hy = (cfg.y_hi - cfg.y_lo) / cfg.ny;
     geom_.rr = row_rows<T>(cfg.nx, cfg.ny);
+    geom_.order = cfg.shape_order;
     lat_.ppc_x = cfg.ppc_x;
     lat_.ppc_y = cfg.ppc_y;
     lat_.nX = cfg.nx * cfg.ppc_x;
@@ -933,12 +964,11 @@ class Box final : public BoxBase {
     std::swap(carry_j_[1], jp_[1]);
   }
 
-  // Lattice rows per push workgroup (64 sites wide): as many rows as keep
-  // >= 1024 workgroups per launch, between 4 and 16.
-  // Cells of LDS deposit histogram around a push tile: particles displaced
-  // further than this from their tile go to global atomics.
+  // Cells of LDS deposit histogram around a push tile: particles whose
+  // stencil reaches further than this from their tile go to global atomics.
+  // The wide stencils of orders 2 and 3 get one more cell.
   int default_tile_halo() const {
-    int h = 2;
+    int h = cfg_.shape_order >= 2 ? 3 : 2;
     if (const char* e = std::getenv("QSP_HALO")) {   // tuning override
       const int v = std::atoi(e);
       if (v >= 1 && v <= 16) h = v;
@@ -946,6 +976,8 @@ class Box final : public BoxBase {
     return h;
   }
 
+  // Lattice rows per push workgroup (64 sites wide): as many rows as keep
+  // >= 1024 workgroups per launch, between 4 and 16.
   int default_tile_rows() const {
     const int tx = lat_.nX < 64 ? lat_.nX : 64;
     int r = 16;
@@ -1039,6 +1071,10 @@ class Box final : public BoxBase {
     bgy_ = alloc<double>(cfg_.ny + 1);
     dbgx_ = alloc<double>(cfg_.nx + 1);
     dbgy_ = alloc<double>(cfg_.ny + 1);
+    if (cfg_.shape_order != 1) {
+      ionx_ = alloc<double>(cfg_.nx + 1);
+      iony_ = alloc<double>(cfg_.ny + 1);
+    }
     ctr_ = alloc<DevCounters>(1);
     partial_ = alloc<double>(2 * static_cast<size_t>(pc_partial_count(geom_)) + 2);
     if (cfg_.mem_cap_bytes > 0 && bytes_ > cfg_.mem_cap_bytes) throw std::bad_alloc();
@@ -1069,6 +1105,12 @@ class Box final : public BoxBase {
     QSP_HIP(hipMemcpy(bgy_, z.data(), (cfg_.ny + 1) * sizeof(double), hipMemcpyHostToDevice));
     QSP_HIP(hipMemcpy(dbgx_, z.data(), (cfg_.nx + 1) * sizeof(double), hipMemcpyHostToDevice));
     QSP_HIP(hipMemcpy(dbgy_, z.data(), (cfg_.ny + 1) * sizeof(double), hipMemcpyHostToDevice));
+    if (ionx_) {
+      const std::vector<double> fx = ion_profile(cfg_.nx, cfg_.ppc_x, cfg_.shape_order);
+      const std::vector<double> fy = ion_profile(cfg_.ny, cfg_.ppc_y, cfg_.shape_order);
+      QSP_HIP(hipMemcpy(ionx_, fx.data(), fx.size() * sizeof(double), hipMemcpyHostToDevice));
+      QSP_HIP(hipMemcpy(iony_, fy.data(), fy.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     QSP_HIP(hipMemset(ctr_, 0, sizeof(DevCounters)));
     QSP_HIP(hipDeviceSynchronize());
   }
@@ -1141,7 +1183,7 @@ class Box final : public BoxBase {
       timed(QSP_K_OTHER, [&] { launch_add_current(pl, cur_[k], dc[3], nullptr, st_); });
     // psi, Ez, Bz (Sec. II steps 4-6)
     {
-      SrcPEZ<T> s{dc[0], dc[1], dc[2], cfg_.n0, t1_};
+      SrcPEZ<T> s{dc[0], dc[1], dc[2], cfg_.n0, ionx_, iony_, t1_};
       timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_pez<T>(geom_, s, tx(), st_); });
       ColArgs<T> c{};
       c.in = t1_;
@@ -1221,6 +1263,8 @@ class Box final : public BoxBase {
     // outputs of slice k
     oc.beam_amp = amp;
     oc.n0 = cfg_.n0;
+    oc.ionx = ionx_;
+    oc.iony = iony_;
     oc.bgx = bgx_;
     oc.bgy = bgy_;
     if (oc.count) timed(QSP_K_OTHER, [&] { launch_out_copy(geom_, oc, st_); });
@@ -1304,6 +1348,7 @@ class Box final : public BoxBase {
   T *prex_ = nullptr, *prey_ = nullptr;
   double *lamx_ = nullptr, *lamy_ = nullptr, *bgx_ = nullptr, *bgy_ = nullptr;
   double *dbgx_ = nullptr, *dbgy_ = nullptr;
+  double *ionx_ = nullptr, *iony_ = nullptr;   // ion profile factors, null for order 1
   // adjoint: checkpoints, tape of one chunk, reverse work space
   std::vector<void*> adj_allocs_;
   int64_t adj_bytes_ = 0;

@@ -19,6 +19,10 @@ std::string validate(const qsp_config& c);
 // trial Adams-Bashforth step, (AB5_0 / 2) * n0.
 double default_pc_shift(double n0);
 
+// Ion density of the rest lattice along one axis (nodes 0..n) in units of
+// n0, for the given particles per cell and shape order.
+std::vector<double> ion_profile(int n, int ppc, int order);
+
 class BoxBase {
  public:
   virtual ~BoxBase() = default;

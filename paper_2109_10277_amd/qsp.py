@@ -50,7 +50,8 @@ class Config(C.Structure):
                 ("n0", C.c_double),
                 ("pc_max_iter", C.c_int32), ("deposit_mode", C.c_int32),
                 ("pc_tol", C.c_double), ("pc_shift", C.c_double),
-                ("psi_floor", C.c_double), ("mem_cap_bytes", C.c_int64)]
+                ("psi_floor", C.c_double), ("mem_cap_bytes", C.c_int64),
+                ("shape_order", C.c_int32), ("reserved1", C.c_int32)]
 
 
 class SliceOut(C.Structure):
@@ -161,6 +162,7 @@ def make_config(cfg, precision: str = "fp32", deposit_mode: int = 0,
     c.pc_shift = -1.0 if shift is None else float(shift)
     c.psi_floor = cfg.psi_floor
     c.mem_cap_bytes = mem_cap_bytes
+    c.shape_order = int(getattr(cfg, "shape_order", 1))
     return c
 
 

@@ -3,6 +3,7 @@ include/qsp.h is exported by libqsp.so, the ctypes structs match the C layout
 (checked against a gcc-compiled probe), and configuration validation rejects
 bad inputs without touching a device."""
 import ctypes
+import dataclasses
 import os
 import re
 import subprocess
@@ -98,6 +99,18 @@ def test_bad_precision_and_deposit_mode():
     assert not Q.validate_config(c)[0]
     c = Q.make_config(good())
     c.deposit_mode = 2
+    assert not Q.validate_config(c)[0]
+
+
+@pytest.mark.parametrize("order,ok", [(0, True), (1, True), (2, True), (3, True), (4, False),
+                                      (-1, False)])
+def test_shape_order_validation(order, ok):
+    c = Q.make_config(good())
+    c.shape_order = order
+    assert Q.validate_config(c)[0] == ok
+    c = Q.make_config(dataclasses.replace(good(), shape_order=2))
+    assert c.shape_order == 2
+    c.reserved1 = 1
     assert not Q.validate_config(c)[0]
 
 
