@@ -36,7 +36,7 @@ METRIC = "plasma particle-slice updates/s + DST solves/s; FP32 vs FP64; fwd+bwd/
 PUSH_TRAFFIC = {"sources": ["paper_2109_10277_amd/csrc/particles.hip",
                             "paper_2109_10277_amd/csrc/push_tile.hpp",
                             "paper_2109_10277_amd/csrc/shape.hpp"],
-                "sha256_prefix": "1667717135d8a419", "workload": "c2", "bytes": 64.24e6,
+                "sha256_prefix": "c23daf7e16d29cd6", "workload": "c2", "bytes": 64.24e6,
                 "summary": "profiles/hbm_traffic_c2_blowout_512x512x1024_fp32.md"}
 
 
@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--shape-order", type=int, default=1, choices=(0, 1, 2, 3),
+                    help="transverse particle shape of the timed workload (1: linear)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -303,6 +305,9 @@ def main():
         print(json.dumps({"adjoint": legs}))
         return
     cfg, beam, wname = workload(args.workload)
+    if args.shape_order != 1:
+        cfg.shape_order = args.shape_order
+        wname += f"_order{args.shape_order}"
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     box, dt, stats, kt = run_gpu(cfg, beam, "fp32", args.steps, args.warmup,
                                  args.timing_every)
@@ -326,7 +331,7 @@ def main():
         "config": {"workload": wname, "nx": cfg.nx, "ny": cfg.ny,
                    "slices": cfg.nzeta, "particles": n_p,
                    "pc": f"<= {cfg.pc_max_iter} iterations, tol {cfg.pc_tol}",
-                   "deposit_sums": "f64"},
+                   "shape_order": cfg.shape_order, "deposit_sums": "f64"},
         "dst_solves_per_s": solves / dt,
         "dst_solves_per_s_standalone_batch3": standalone,
         "pc_iterations_per_slice": sum(s["pc_iterations"] for s in stats) / (cfg.nzeta * args.steps),
