@@ -92,20 +92,9 @@ def forward_with_tape(cfg, beam):
 def shape_1d_grad(s, n: int, order: int):
     """Derivatives d w / d s of the ``shape_1d`` weights (orders 1-3; the
     order-0 shape is discontinuous and has no adjoint)."""
-    s = np.asarray(s, dtype=np.float64)
-    if order == 1:
-        b = np.clip(np.floor(s).astype(np.int64), 0, n - 1)
-        return [-np.ones_like(s), np.ones_like(s)]
-    if order == 2:
-        b = np.floor(s + 0.5).astype(np.int64)
-        d = s - b
-        return [-(0.5 - d), -2.0 * d, 0.5 + d]
-    if order == 3:
-        b = np.floor(s).astype(np.int64)
-        d = s - b
-        return [-0.5 * (1.0 - d) ** 2, (-12.0 * d + 9.0 * d * d) / 6.0,
-                (3.0 + 6.0 * d - 9.0 * d * d) / 6.0, 0.5 * d * d]
-    raise ValueError("the adjoint needs a shape of order 1, 2 or 3")
+    if order not in (1, 2, 3):
+        raise ValueError("the adjoint needs a shape of order 1, 2 or 3")
+    return O.shape_1d_slope(s, n, order)
 
 
 def cic_grad(cfg, x, y):

@@ -149,6 +149,22 @@ def shape_1d(s, n: int, order: int):
     raise ValueError("shape order must be 0, 1, 2 or 3")
 
 
+def shape_1d_slope(s, n: int, order: int):
+    """Derivatives d w / d s of the ``shape_1d`` weights, in the same node
+    order (orders 1-3; the order-0 shape is piecewise constant)."""
+    s = np.asarray(s, dtype=np.float64)
+    if order == 1:
+        return [-np.ones_like(s), np.ones_like(s)]
+    if order == 2:
+        d = s - np.floor(s + 0.5)
+        return [-(0.5 - d), -2.0 * d, 0.5 + d]
+    if order == 3:
+        d = s - np.floor(s)
+        return [-0.5 * (1.0 - d) ** 2, (-12.0 * d + 9.0 * d * d) / 6.0,
+                (3.0 + 6.0 * d - 9.0 * d * d) / 6.0, 0.5 * d * d]
+    raise ValueError("shape slopes exist for orders 1, 2 and 3")
+
+
 def shape_order(cfg) -> int:
     return int(getattr(cfg, "shape_order", 1))
 
@@ -196,6 +212,27 @@ def deposit_values(cfg, x, y, values: np.ndarray) -> np.ndarray:
         ok = _valid(cfg, i, j)
         out += np.bincount((j * (cfg.nx + 1) + i)[ok], weights=(values * s)[ok],
                            minlength=out.size)
+    return zero_boundary(out.reshape(cfg.ny + 1, cfg.nx + 1))
+
+
+def deposit_slopes(cfg, x, y, ax: np.ndarray, ay: np.ndarray) -> np.ndarray:
+    """Scatter-add of ax dS/dx_p + ay dS/dy_p per particle: the rate of
+    change of a deposit when the particle moves with velocity (ax, ay) per
+    unit of its weight (the shape's derivative with respect to the particle
+    position, tensor product of ``shape_1d_slope`` and ``shape_1d``)."""
+    o = shape_order(cfg)
+    sx = (x - cfg.x_lo) / cfg.hx
+    sy = (y - cfg.y_lo) / cfg.hy
+    ni, wi = shape_1d(sx, cfg.nx, o)
+    nj, wj = shape_1d(sy, cfg.ny, o)
+    gi = shape_1d_slope(sx, cfg.nx, o)
+    gj = shape_1d_slope(sy, cfg.ny, o)
+    out = np.zeros((cfg.ny + 1) * (cfg.nx + 1))
+    for j, wy, dwy in zip(nj, wj, gj):
+        for i, wx, dwx in zip(ni, wi, gi):
+            ok = _valid(cfg, i, j)
+            v = ax * dwx * wy / cfg.hx + ay * wx * dwy / cfg.hy
+            out += np.bincount((j * (cfg.nx + 1) + i)[ok], weights=v[ok], minlength=out.size)
     return zero_boundary(out.reshape(cfg.ny + 1, cfg.nx + 1))
 
 
@@ -530,6 +567,77 @@ def beam_source(cfg, beam, k: int) -> dict:
 
 
 # --------------------------------------------------------------------------
+# Explicit Bx/By solver
+# --------------------------------------------------------------------------
+
+def explicit_sources(cfg, p: Plasma, flds: dict) -> dict:
+    """Explicit d_zeta J_perp (Sec. III.B, the explicit Bx/By solver: the
+    longitudinal derivative is integrated analytically instead of iterated).
+
+    The plasma current is J_perp = sum_p q w_p S(x - x_p) u_p / D_p (per
+    cell area), so along the particle orbits of the Sec. III.B pusher
+      d_zeta J_perp = sum_p q w_p [ S d(u/D)/dzeta + (u/D) dS/dzeta ],
+      d(u/D)/dzeta  = (du/dzeta) / D - u (dPsi/dzeta) / D^2,
+      dS/dzeta      = grad_p S . dx_p/dzeta = -grad_p S . u / D.
+    du_x/dzeta = a_x + By and du_y/dzeta = a_y - Bx, where
+    a_x = gamma/D (Ex-By) + Bz u_y/D and a_y = gamma/D (Ey+Bx) - Bz u_x/D
+    hold only quantities known before the Bx/By solve.  Hence
+      d_zeta Jx = DJx - chi By,   d_zeta Jy = DJy + chi Bx,
+      chi = sum_p w_p S / D  (> 0 for electrons, q = -1),
+    with DJ the deposit of everything else.  The B_perp terms, gathered at
+    the particles, are taken at the node (chi B) so that the Bx/By equation
+    stays linear on the grid.  A floored D is constant along the orbit.
+    Returns {"chi", "djx", "djy"} (node arrays, boundary zero)."""
+    g = {k: gather(cfg, flds[k], p.x, p.y) for k in ("exmby", "eypbx", "ez", "bz")}
+    raw = 1.0 + p.psi
+    d = np.maximum(raw, cfg.psi_floor)
+    gam = gamma_of(p.ux, p.uy, d)
+    ax = gam / d * g["exmby"] + g["bz"] * p.uy / d
+    ay = gam / d * g["eypbx"] - g["bz"] * p.ux / d
+    apsi = np.where(raw < cfg.psi_floor, 0.0,
+                    (p.ux * g["exmby"] + p.uy * g["eypbx"]) / d - g["ez"])
+    wa = p.w / (cfg.hx * cfg.hy)
+    qn = -wa                                  # q w / cell area
+    vx, vy = p.ux / d, p.uy / d
+    djx = deposit_values(cfg, p.x, p.y, qn * (ax / d - p.ux * apsi / d ** 2))
+    djy = deposit_values(cfg, p.x, p.y, qn * (ay / d - p.uy * apsi / d ** 2))
+    djx = djx + deposit_slopes(cfg, p.x, p.y, -qn * vx * vx, -qn * vx * vy)
+    djy = djy + deposit_slopes(cfg, p.x, p.y, -qn * vy * vx, -qn * vy * vy)
+    chi = deposit_values(cfg, p.x, p.y, wa / d)
+    return {"chi": chi, "djx": djx, "djy": djy}
+
+
+def helmholtz_solve(cfg, rhs: np.ndarray, chi: np.ndarray) -> np.ndarray:
+    """Solve (lap_h - chi) u = rhs on the interior nodes, u = 0 on the
+    boundary, by a sparse direct factorisation of the 5-point operator
+    (a library primitive; chi varies from node to node)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    mx, my = cfg.nx - 1, cfg.ny - 1
+    lx = sp.diags([np.ones(mx - 1), -2.0 * np.ones(mx), np.ones(mx - 1)], [-1, 0, 1]) / cfg.hx ** 2
+    ly = sp.diags([np.ones(my - 1), -2.0 * np.ones(my), np.ones(my - 1)], [-1, 0, 1]) / cfg.hy ** 2
+    a = sp.kron(sp.identity(my), lx) + sp.kron(ly, sp.identity(mx))
+    a = (a - sp.diags(chi[1:-1, 1:-1].ravel())).tocsc()
+    u = np.zeros_like(rhs)
+    u[1:-1, 1:-1] = spl.spsolve(a, rhs[1:-1, 1:-1].ravel()).reshape(my, mx)
+    return u
+
+
+def explicit_bxby(cfg, jz_k: np.ndarray, src: dict):
+    """Eq. (bxby) with the explicit d_zeta J_perp of ``explicit_sources``:
+      lap Bx = -d_y Jz + DJy + chi Bx  ->  (lap - chi) Bx = -d_y Jz + DJy
+      lap By =  d_x Jz - DJx + chi By  ->  (lap - chi) By =  d_x Jz - DJx
+    a Helmholtz-like equation with a node-dependent coefficient."""
+    rx = zero_boundary(-ddy(cfg, jz_k) + src["djy"])
+    ry = zero_boundary(ddx(cfg, jz_k) - src["djx"])
+    return helmholtz_solve(cfg, rx, src["chi"]), helmholtz_solve(cfg, ry, src["chi"])
+
+
+def bxby_solver(cfg) -> str:
+    return getattr(cfg, "bxby_solver", "pc")
+
+
+# --------------------------------------------------------------------------
 # One slice and the box
 # --------------------------------------------------------------------------
 
@@ -602,14 +710,18 @@ def predictor_corrector(cfg, st: SliceState, flds: dict, dep: dict):
 
 def advance_slice(cfg, st: SliceState, beam):
     """Compute the fields of slice st.k and push the plasma to slice k+1
-    (the 2D slice routine of Sec. II, with the predictor-corrector as
-    step 7).  A macro-particle beam with a non-zero ``dt`` also has its
+    (the 2D slice routine of Sec. II, with the predictor-corrector or the
+    explicit solver as step 7).  A macro-particle beam with a non-zero ``dt`` also has its
     slice-k particles pushed by one time step once the slice's fields are
     final (mutating the beam).  Returns (state at k+1, record of slice k)."""
     k = st.k
     dep = total_deposit(cfg, st.plasma, beam, k)
     flds = solve_psi_ez_bz(cfg, dep)
-    bx, by, its, res, nclamp_pc = predictor_corrector(cfg, st, flds, dep)
+    if bxby_solver(cfg) == "explicit":
+        bx, by = explicit_bxby(cfg, dep["jz"], explicit_sources(cfg, st.plasma, flds))
+        its, res, nclamp_pc = 0, [], 0
+    else:
+        bx, by, its, res, nclamp_pc = predictor_corrector(cfg, st, flds, dep)
     flds["bx"], flds["by"] = bx, by
     if beam is not None and hasattr(beam, "zeta") and getattr(beam, "dt", 0.0):
         beam_push_slice(cfg, beam, k, flds, beam.dt)

@@ -60,6 +60,7 @@ class BoxConfig:
     pc_shift: Optional[float] = None   # None: the method's default screening
     psi_floor: float = ONE_PLUS_PSI_FLOOR
     shape_order: int = 1         # transverse particle shape: 0 NGP, 1 CIC, 2 and 3 B-splines
+    bxby_solver: str = "pc"      # "pc" predictor-corrector or "explicit"
 
     @property
     def hx(self) -> float:
