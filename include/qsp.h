@@ -53,6 +53,9 @@ typedef enum {
 
 enum { QSP_FP32 = 0, QSP_FP64 = 1 };
 
+/* Bx/By field solver (Sec. III.B offers two). */
+enum { QSP_BXBY_PC = 0, QSP_BXBY_EXPLICIT = 1 };
+
 /* Quantities a slice produces, in the order used by every output array
  * below.  The first seven are fields (precision of the context), the last
  * five are deposits of slice k including ions and beam (always double). */
@@ -99,7 +102,15 @@ enum {
  *            zero-initialised config selects 0.  The ions are the
  *            electrons' rest lattice deposited with the same shape, so the
  *            unperturbed plasma is neutral at every node.
- *   reserved1: set to 0. */
+ *   bxby_solver: QSP_BXBY_PC (the predictor-corrector above) or
+ *            QSP_BXBY_EXPLICIT: d_zeta J_perp integrated analytically along
+ *            the plasma orbits, which turns eq. (bxby) into
+ *            (lap - chi) B = R with chi = sum w S / (1 + Psi) per node; it is
+ *            solved by conjugate gradients preconditioned with the sine
+ *            transform of (lap - c0), c0 = pc_shift (< 0: n0).  For this
+ *            solver pc_max_iter bounds the conjugate-gradient iterations and
+ *            pc_tol is their relative residual target; it needs
+ *            shape_order >= 1 and has no adjoint. */
 typedef struct {
   int32_t nx, ny;
   double x_lo, x_hi, y_lo, y_hi;
@@ -115,7 +126,7 @@ typedef struct {
   double psi_floor;
   int64_t mem_cap_bytes;
   int32_t shape_order; /* 0..3 */
-  int32_t reserved1;
+  int32_t bxby_solver; /* QSP_BXBY_PC or QSP_BXBY_EXPLICIT */
 } qsp_config;
 
 /* Per-slice outputs of qsp_advance_slice: one device pointer per quantity
@@ -301,8 +312,9 @@ typedef struct {
  * about ceil(n_slices/ckpt_every) slice states plus ckpt_every records;
  * mem_cap_bytes applies.  Requires the cursor at 0, a Gaussian beam, and no
  * macro-particle beam that moves (dt != 0) -> else QSP_ERR_BAD_STATE;
- * 1 <= n_slices <= nzeta, ckpt_every >= 1 and shape_order >= 1 (the
- * nearest-node shape has no derivative) -> else QSP_ERR_INVALID_ARG.
+ * 1 <= n_slices <= nzeta, ckpt_every >= 1, shape_order >= 1 (the
+ * nearest-node shape has no derivative) and the predictor-corrector
+ * Bx/By solver -> else QSP_ERR_INVALID_ARG.
  * Synchronises. */
 qsp_status qsp_run_box_record(qsp_ctx ctx, int32_t n_slices, int32_t ckpt_every,
                               const qsp_box_out* out, qsp_stats* stats);

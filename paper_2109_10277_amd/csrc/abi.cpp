@@ -208,6 +208,8 @@ qsp_status qsp_run_box_record(qsp_ctx ctx, int32_t n_slices, int32_t ckpt_every,
     const qsp_config& c = b.config();
     if (c.shape_order < 1)
       return fail(ctx, QSP_ERR_INVALID_ARG, "the adjoint needs a shape order of 1, 2 or 3");
+    if (c.bxby_solver != QSP_BXBY_PC)
+      return fail(ctx, QSP_ERR_INVALID_ARG, "the adjoint transposes the predictor-corrector only");
     if (c.mem_cap_bytes > 0 && qsp::device_bytes_needed(c) + b.adjoint_bytes(n_slices, ckpt_every) >
                                    c.mem_cap_bytes)
       return fail(ctx, QSP_ERR_OUT_OF_MEMORY, "checkpoints and tape exceed mem_cap_bytes");

@@ -39,7 +39,7 @@ struct SrcBxBy {            // Bx, By corrector sources
 // Planes of FP64 scratch a kernel clears on the side (spread over its grid)
 // once their previous readers have finished.
 struct ZeroJob {
-  double* p[6];
+  double* p[8];
   int count;
   size_t n;                 // elements per plane
 };
@@ -137,7 +137,9 @@ struct DepOut {
   double* ch[4];            // rho-Jz, Jx, Jy, Jz (rho is formed as (rho - Jz) + Jz)
 };
 
-enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2 };
+// kExplicitDep: no push; deposit the explicit Bx/By solver's chi, DJx, DJy
+// (dep.ch[0..2]) from the slice-k state in the slice-k psi, Ez, Bz
+enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2, kExplicitDep = 3 };
 
 template <typename T>
 struct PushArgs {
@@ -170,6 +172,48 @@ template <typename T>
 void launch_export_state(const Geom&, const Lattice&, const Particles<T>&, double* x,
                          double* y, double* ux, double* uy, double* psi, double* w,
                          double* hist, int k, hipStream_t);
+
+// ------------------------------------------------- explicit Bx/By solver
+// Device scalars of the preconditioned conjugate-gradient solve of
+// (-lap + chi) B = -R (two systems: 0 Bx, 1 By).
+struct ExplicitScalars {
+  double bnorm2;            // ||b||^2 of both systems
+  double rho[2];            // z . r
+  double alpha[2];
+  double beta[2];
+  unsigned int blocks_arrived;
+  unsigned int pad;
+};
+
+template <typename T>
+struct ExplicitArgs {
+  const double* jz;         // Jz of slice k (plasma + particle beam)
+  double beam_amp;          // Gaussian beam Jz = -beam_amp bgx[i] bgy[j]
+  const double* bgx;
+  const double* bgy;
+  const double* chi;        // explicit deposits of slice k
+  const double* djx;
+  const double* djy;
+  T* b[2];                  // Bx, By: initial guess on entry, iterate after each update
+  double* x;                // FP64 Krylov vectors, 2 planes each
+  double* r;
+  double* q;
+  double* p[2];             // two buffers (iteration parity) of 2 planes
+  const T* col;             // column-pass output, input of the inverse row pass
+  T* fwd;                   // forward row-pass output, input of the column pass
+  T* z;                     // preconditioned residual
+  double* partial;          // explicit_partial_count doubles
+  ExplicitScalars* s;
+  double tol;               // relative residual target (<= 0: run every iteration)
+  int it;                   // 0 set-up, m >= 1 iteration m
+};
+
+enum ExplicitStep { kExplSetup = 0, kExplMatvec = 1, kExplUpdate = 2, kExplRowInv = 3 };
+
+template <typename T>
+void launch_explicit(const Geom&, const ExplicitArgs<T>&, ExplicitStep, const AxisTables<T>&,
+                     DevCounters*, hipStream_t);
+int explicit_partial_count(const Geom&);
 
 // ---------------------------------------------------------------- grid utils
 void launch_zero(double* p, size_t n, hipStream_t);

@@ -27,7 +27,12 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
       ctr->pc_not_converged += 1ull;
   }
   extern __shared__ unsigned char smem_raw[];
-  push_tile<T, MODE, O>(g, L, a, ctr, blockIdx.x, blockIdx.y, reinterpret_cast<double*>(smem_raw));
+  if constexpr (MODE == kExplicitDep)
+    push_detail::explicit_tile<T, O>(g, L, a, blockIdx.x, blockIdx.y,
+                                     reinterpret_cast<double*>(smem_raw));
+  else
+    push_tile<T, MODE, O>(g, L, a, ctr, blockIdx.x, blockIdx.y,
+                          reinterpret_cast<double*>(smem_raw));
 }
 
 template <typename T>
@@ -119,15 +124,20 @@ template <typename T>
 void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode mode,
                  DevCounters* ctr, hipStream_t st) {
   const TileShape ts = tile_shape(L, a.tile_rows, a.tile_halo);
-  const int nch = mode == kPushTrial ? 2 : 4;
+  const int nch = mode == kPushTrial ? 2 : (mode == kExplicitDep ? 3 : 4);
   const size_t lds = a.tiled ? static_cast<size_t>(nch) * ts.nw * ts.nh * sizeof(double) : 0;
   if (lds > 160 * 1024) throw std::invalid_argument("push tile histogram exceeds the LDS");
   const dim3 grid(L.nX / ts.tx, L.nY / ts.ty);
+  if (mode == kExplicitDep && g.order < 1)
+    throw std::invalid_argument("the explicit Bx/By solver needs a shape order of 1, 2 or 3");
   auto run = [&](auto order) {
     constexpr int O = decltype(order)::value;
+    constexpr int OE = O < 1 ? 1 : O;   // the explicit deposit has no order-0 form
     const void* fn = mode == kPushReal    ? reinterpret_cast<const void*>(&k_push<T, kPushReal, O>)
                      : mode == kPushTrial ? reinterpret_cast<const void*>(&k_push<T, kPushTrial, O>)
-                                          : reinterpret_cast<const void*>(&k_push<T, kDepositOnly, O>);
+                     : mode == kExplicitDep
+                         ? reinterpret_cast<const void*>(&k_push<T, kExplicitDep, OE>)
+                         : reinterpret_cast<const void*>(&k_push<T, kDepositOnly, O>);
     if (lds > 65536)   // opt in above 64 KiB (gfx950 offers 160 KiB per workgroup)
       QSP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
     switch (mode) {
@@ -136,6 +146,9 @@ void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode
         break;
       case kPushTrial:
         hipLaunchKernelGGL((k_push<T, kPushTrial, O>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
+        break;
+      case kExplicitDep:
+        hipLaunchKernelGGL((k_push<T, kExplicitDep, OE>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
         break;
       default:
         hipLaunchKernelGGL((k_push<T, kDepositOnly, O>), grid, dim3(kBlock), lds, st, g, L, a, ctr);

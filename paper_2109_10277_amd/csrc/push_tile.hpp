@@ -285,5 +285,122 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
   }
 }
 
+// Sources of the explicit Bx/By solver for the particles of lattice tile
+// (tbx, tby) at their slice-k state, in the final psi, Ez, Bz of slice k
+// (shape order O >= 1).  Along the pusher's orbits (dx_p/dzeta = -u/D)
+//   d_zeta J_perp = sum q w [ S d(u/D)/dzeta - (u/D) (grad_p S . u/D) ],
+// whose B_perp part is -chi By (x) and +chi Bx (y) with chi = sum w S / D;
+// the rest (DJx, DJy) and chi are deposited into dep.ch[0..2] = chi, DJx,
+// DJy (FP64).  du/dzeta without B_perp: a_x = gamma/D (Ex-By) + Bz u_y/D,
+// a_y = gamma/D (Ey+Bx) - Bz u_x/D; dPsi/dzeta = u.(E-vxB)_perp/D - Ez, and
+// a floored D does not change.
+template <typename T, int O>
+__device__ __forceinline__ void explicit_tile(const Geom& g, const Lattice& L,
+                                              const PushArgs<T>& a, int tbx, int tby,
+                                              double* tile) {
+  constexpr int nch = 3;
+  const TileShape ts = tile_shape(L, a.tile_rows, a.tile_halo);
+  const int ntile = ts.nw * ts.nh;
+  const bool tiled = a.tiled != 0;
+  if (tiled) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < nch * ntile; e += kBlock) tile[e] = 0.0;
+    __syncthreads();
+  }
+  const int I0 = tbx * ts.tx, J0 = tby * ts.ty;
+  const int ox = (I0 >> ts.lpx) - ts.halo, oy = (J0 >> ts.lpy) - ts.halo;
+  const int nx = g.nx, ny = g.ny;
+  const double ihx = 1.0 / a.hx, ihy = 1.0 / a.hy;
+  const T floor_d = static_cast<T>(a.psi_floor);
+
+  for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock) {
+    const int I = I0 + e % ts.tx, J = J0 + e / ts.tx;
+    const size_t p = static_cast<size_t>(J) * L.nX + I;
+    const T w = a.p.w[p];
+    const T xi = a.p.xi_x[p], eta = a.p.xi_y[p];
+    const T ux = a.p.ux[p], uy = a.p.uy[p], psi = a.p.psi[p];
+    const int ci0 = I >> ts.lpx, cj0 = J >> ts.lpy;
+    const T fx0 = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
+    const T fy0 = (T(2 * (J & (L.ppc_y - 1)) + 1)) / T(2 * L.ppc_y);
+    int bi, bj;
+    const T dx = shape::locate<O>(ci0, fx0 + xi, nx, bi);
+    const T dy = shape::locate<O>(cj0, fy0 + eta, ny, bj);
+    T wx[O + 1], wy[O + 1];
+    int ix[O + 1], iy[O + 1];
+    bool okx[O + 1], oky[O + 1];
+    shape::weights<O>(dx, wx);
+    shape::weights<O>(dy, wy);
+    shape::axis_nodes<O>(bi, nx, ix, okx);
+    shape::axis_nodes<O>(bj, ny, iy, oky);
+#pragma unroll
+    for (int q = 0; q <= O; ++q) {
+      wx[q] = okx[q] ? wx[q] : T(0);
+      wy[q] = oky[q] ? wy[q] : T(0);
+    }
+    const T e1 = shape::interp<O>(a.f.exmby, ix, iy, wx, wy, nx);
+    const T e2 = shape::interp<O>(a.f.eypbx, ix, iy, wx, wy, nx);
+    const T ez = shape::interp<O>(a.f.ez, ix, iy, wx, wy, nx);
+    const T bz = shape::interp<O>(a.f.bz, ix, iy, wx, wy, nx);
+    if (w == T(0)) continue;
+    const T draw = T(1) + psi;
+    const bool clamped = draw < floor_d;
+    const T d = clamped ? floor_d : draw;
+    const T id = T(1) / d;
+    const T gam = (T(1) + ux * ux + uy * uy + d * d) * T(0.5) * id;
+    const T ax = gam * id * e1 + bz * uy * id;
+    const T ay = gam * id * e2 - bz * ux * id;
+    const T apsi = clamped ? T(0) : (ux * e1 + uy * e2) * id - ez;
+    const T qn = -w;
+    const double cx = static_cast<double>(qn * (ax * id - ux * apsi * id * id));
+    const double cy = static_cast<double>(qn * (ay * id - uy * apsi * id * id));
+    const double vx = static_cast<double>(ux * id), vy = static_cast<double>(uy * id);
+    const double qd = static_cast<double>(qn);
+    const double chi_p = static_cast<double>(w * id);
+    double sx[O + 1], sy[O + 1], gx[O + 1], gy[O + 1];
+    shape::weights<O>(static_cast<double>(dx), sx);
+    shape::weights<O>(static_cast<double>(dy), sy);
+    shape::weight_slopes<O>(static_cast<double>(dx), gx);
+    shape::weight_slopes<O>(static_cast<double>(dy), gy);
+    const int li = bi - ox, lj = bj - oy;
+    const bool in_tile = tiled && li >= 0 && li + O < ts.nw && lj >= 0 && lj + O < ts.nh;
+#pragma unroll
+    for (int qb = 0; qb <= O; ++qb) {
+      const int gj = bj + qb;
+#pragma unroll
+      for (int qa = 0; qa <= O; ++qa) {
+        const int gi = bi + qa;
+        const double sw = sx[qa] * sy[qb];
+        const double vg = vx * (gx[qa] * sy[qb] * ihx) + vy * (sx[qa] * gy[qb] * ihy);
+        const double v0 = chi_p * sw;
+        // (u/D) dS/dzeta with dS/dzeta = -(grad_p S . u/D) = -vg
+        const double v1 = cx * sw - qd * vx * vg;
+        const double v2 = cy * sw - qd * vy * vg;
+        if (in_tile) {
+          double* t = tile + (lj + qb) * ts.nw + (li + qa);
+          lds_add(t, v0);
+          lds_add(t + ntile, v1);
+          lds_add(t + 2 * ntile, v2);
+        } else if (gi >= 1 && gi < nx && gj >= 1 && gj < ny) {
+          const size_t o = static_cast<size_t>(gj) * nx + gi;
+          global_add(a.dep.ch[0] + o, v0);
+          global_add(a.dep.ch[1] + o, v1);
+          global_add(a.dep.ch[2] + o, v2);
+        }
+      }
+    }
+  }
+
+  if (tiled) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < nch * ntile; e += kBlock) {
+      const int c = e / ntile, l = e % ntile;
+      const int gi = ox + l % ts.nw, gj = oy + l / ts.nw;
+      if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
+      const double val = tile[e];
+      if (val != 0.0) global_add(a.dep.ch[c] + static_cast<size_t>(gj) * nx + gi, val);
+    }
+  }
+}
+
 }  // namespace push_detail
 }  // namespace qsp

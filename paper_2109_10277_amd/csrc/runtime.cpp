@@ -70,7 +70,10 @@ std::string validate(const qsp_config& c) {
   if (c.mem_cap_bytes < 0) return "mem_cap_bytes must be >= 0";
   if (c.deposit_mode != 0 && c.deposit_mode != 1) return "deposit_mode must be 0 or 1";
   if (c.shape_order < 0 || c.shape_order > 3) return "shape_order must be 0, 1, 2 or 3";
-  if (c.reserved1 != 0) return "reserved1 must be 0";
+  if (c.bxby_solver != QSP_BXBY_PC && c.bxby_solver != QSP_BXBY_EXPLICIT)
+    return "bxby_solver must be QSP_BXBY_PC or QSP_BXBY_EXPLICIT";
+  if (c.bxby_solver == QSP_BXBY_EXPLICIT && c.shape_order < 1)
+    return "the explicit Bx/By solver needs shape_order 1, 2 or 3";
   return "";
 }
 
@@ -84,6 +87,7 @@ int64_t device_bytes_needed(const qsp_config& c) {
   b += np * ts * (6 + 20);                       // particle SoA + history
   b += (c.nx + c.ny) * (3 * ts + 8 + 8) + 4096;  // tables, counters
   b += (c.nx + c.ny + 2) * 8;                    // ion profile
+  if (c.bxby_solver == QSP_BXBY_EXPLICIT) b += plane * 8 * 13 + 4096;   // explicit solver
   b += static_cast<int64_t>(c.ny) * 16 + 64;     // residual partials
   return b;
 }
@@ -194,7 +198,10 @@ class Box final : public BoxBase {
     lat_.nX = cfg.nx * cfg.ppc_x;
     lat_.nY = cfg.ny * cfg.ppc_y;
     lat_.np = static_cast<int64_t>(lat_.nX) * lat_.nY;
-    shift_ = cfg.pc_shift < 0 ? default_pc_shift(cfg.n0) : cfg.pc_shift;
+    explicit_ = cfg.bxby_solver == QSP_BXBY_EXPLICIT;
+    // predictor-corrector screening, or the explicit solver's preconditioner
+    // shift (the unperturbed plasma's chi = n0)
+    shift_ = cfg.pc_shift >= 0 ? cfg.pc_shift : (explicit_ ? cfg.n0 : default_pc_shift(cfg.n0));
     tiled_ = cfg.deposit_mode == 0;
     tile_rows_ = default_tile_rows();
     tile_halo_ = default_tile_halo();
@@ -1071,6 +1078,16 @@ class Box final : public BoxBase {
     bgy_ = alloc<double>(cfg_.ny + 1);
     dbgx_ = alloc<double>(cfg_.nx + 1);
     dbgy_ = alloc<double>(cfg_.ny + 1);
+    if (explicit_) {
+      for (int c = 0; c < 3; ++c) ex_dep_[c] = alloc<double>(pl);
+      ex_x_ = alloc<double>(2 * pl);
+      ex_r_ = alloc<double>(2 * pl);
+      ex_q_ = alloc<double>(2 * pl);
+      ex_p_[0] = alloc<double>(2 * pl);
+      ex_p_[1] = alloc<double>(2 * pl);
+      ex_partial_ = alloc<double>(static_cast<size_t>(explicit_partial_count(geom_)));
+      ex_s_ = alloc<ExplicitScalars>(1);
+    }
     if (cfg_.shape_order != 1) {
       ionx_ = alloc<double>(cfg_.nx + 1);
       iony_ = alloc<double>(cfg_.ny + 1);
@@ -1112,6 +1129,7 @@ class Box final : public BoxBase {
       QSP_HIP(hipMemcpy(iony_, fy.data(), fy.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     QSP_HIP(hipMemset(ctr_, 0, sizeof(DevCounters)));
+    if (ex_s_) QSP_HIP(hipMemset(ex_s_, 0, sizeof(ExplicitScalars)));
     QSP_HIP(hipDeviceSynchronize());
   }
 
@@ -1195,6 +1213,8 @@ class Box final : public BoxBase {
       // the deposit planes of slice k+1 are free: clear them for the real push
       for (int q = 0; q < 4; ++q) c.zero.p[q] = dn[q];
       c.zero.count = 4;
+      if (explicit_)   // and the explicit solver's deposits for slice k
+        for (int q = 0; q < 3; ++q) c.zero.p[c.zero.count++] = ex_dep_[q];
       c.zero.n = pl;
       timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 3, ty(), lamx_, ctr_, st_); });
       RowInvArgs<T> r{};
@@ -1214,43 +1234,47 @@ class Box final : public BoxBase {
       timed(QSP_K_ROW_INV, [&] { launch_row_inv<T>(geom_, r, 4, tx(), st_); });
       dst_solves_ += 3;
     }
-    // Bx/By predictor-corrector (Sec. II step 7, Sec. III.B)
-    {
-      const PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
-      SrcBxBy<T> s{};
-      s.jz = dc[3];
-      s.jx_prev = dp[1];
-      s.jy_prev = dp[2];
-      s.jx_next = trial_[0];
-      s.jy_next = trial_[1];
-      s.bx = bxk;
-      s.by = byk;
-      s.shift = shift_;
-      s.dzeta = cfg_.dzeta;
-      s.beam_amp = amp;
-      s.bgx = bgx_;
-      s.bgy = bgy_;
-      s.out = t1_;
-      ColArgs<T> c{};
-      c.in = t1_;
-      c.out = t2_;
-      c.out_dy = nullptr;
-      c.shift[0] = c.shift[1] = shift_;
-      c.honor_done = 1;
-      c.w = col_width<T>(geom_, 2);
-      // the trial currents have been read: clear them for the next trial
-      c.zero.p[0] = trial_[0];
-      c.zero.p[1] = trial_[1];
-      c.zero.count = 2;
-      c.zero.n = pl;
-      for (int m = 0; m < cfg_.pc_max_iter; ++m) {
-        timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, ctr_, st_); });
-        timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_bxby<T>(geom_, s, tx(), ctr_, st_); });
-        timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
-        PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol,
-                     tape_slot_ ? tape_b(*tape_slot_, m + 1, 0) : nullptr,
-                     tape_slot_ ? tape_b(*tape_slot_, m + 1, 1) : nullptr};
-        timed(QSP_K_ROW_INV, [&] { launch_row_inv_pc<T>(geom_, pc, tx(), ctr_, st_); });
+    // Bx/By (Sec. II step 7, Sec. III.B): explicit solver or predictor-corrector
+    if (explicit_) {
+      explicit_bxby(k, dc, amp, bxk, byk);
+    } else {
+      {
+        const PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
+        SrcBxBy<T> s{};
+        s.jz = dc[3];
+        s.jx_prev = dp[1];
+        s.jy_prev = dp[2];
+        s.jx_next = trial_[0];
+        s.jy_next = trial_[1];
+        s.bx = bxk;
+        s.by = byk;
+        s.shift = shift_;
+        s.dzeta = cfg_.dzeta;
+        s.beam_amp = amp;
+        s.bgx = bgx_;
+        s.bgy = bgy_;
+        s.out = t1_;
+        ColArgs<T> c{};
+        c.in = t1_;
+        c.out = t2_;
+        c.out_dy = nullptr;
+        c.shift[0] = c.shift[1] = shift_;
+        c.honor_done = 1;
+        c.w = col_width<T>(geom_, 2);
+        // the trial currents have been read: clear them for the next trial
+        c.zero.p[0] = trial_[0];
+        c.zero.p[1] = trial_[1];
+        c.zero.count = 2;
+        c.zero.n = pl;
+        for (int m = 0; m < cfg_.pc_max_iter; ++m) {
+          timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, ctr_, st_); });
+          timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_bxby<T>(geom_, s, tx(), ctr_, st_); });
+          timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
+          PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol,
+                       tape_slot_ ? tape_b(*tape_slot_, m + 1, 0) : nullptr,
+                       tape_slot_ ? tape_b(*tape_slot_, m + 1, 1) : nullptr};
+          timed(QSP_K_ROW_INV, [&] { launch_row_inv_pc<T>(geom_, pc, tx(), ctr_, st_); });
+        }
       }
     }
     // beam particles of slice k take their time step in the final fields
@@ -1292,6 +1316,60 @@ class Box final : public BoxBase {
     ik_ = old2;
     ++cursor_;
     ++slices_done_;
+  }
+
+  // Explicit Bx/By solver of slice k (Sec. III.B): deposit chi, DJx, DJy
+  // from the slice-k plasma in the final psi, Ez, Bz, then solve
+  // (lap - chi) B = R by preconditioned conjugate gradients, starting from
+  // the guess 2 B_{k-1} - B_{k-2} already in bxk, byk; at most pc_max_iter
+  // iterations, relative residual target pc_tol.
+  void explicit_bxby(int k, double* const* dc, double amp, T* bxk, T* byk) {
+    const size_t pl = plane();
+    PushArgs<T> d = push_args(fields(bxk, byk), ex_dep_, k, 3);
+    timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, d, kExplicitDep, ctr_, st_); });
+    ExplicitArgs<T> a{};
+    a.jz = dc[3];
+    a.beam_amp = amp;
+    a.bgx = bgx_;
+    a.bgy = bgy_;
+    a.chi = ex_dep_[0];
+    a.djx = ex_dep_[1];
+    a.djy = ex_dep_[2];
+    a.b[0] = bxk;
+    a.b[1] = byk;
+    a.x = ex_x_;
+    a.r = ex_r_;
+    a.q = ex_q_;
+    a.p[0] = ex_p_[0];
+    a.p[1] = ex_p_[1];
+    a.fwd = t1_;
+    a.col = t2_;
+    a.z = t1_ + 2 * pl;
+    a.partial = ex_partial_;
+    a.s = ex_s_;
+    a.tol = cfg_.pc_tol;
+    ColArgs<T> c{};
+    c.in = t1_;
+    c.out = t2_;
+    c.out_dy = nullptr;
+    c.shift[0] = c.shift[1] = shift_;
+    c.honor_done = 1;
+    c.w = col_width<T>(geom_, 2);
+    auto precondition = [&](int it) {
+      a.it = it;
+      timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
+      timed(QSP_K_ROW_INV, [&] { launch_explicit<T>(geom_, a, kExplRowInv, tx(), ctr_, st_); });
+    };
+    a.it = 0;
+    timed(QSP_K_ROW_FWD, [&] { launch_explicit<T>(geom_, a, kExplSetup, tx(), ctr_, st_); });
+    precondition(0);
+    for (int m = 1; m <= cfg_.pc_max_iter; ++m) {
+      a.it = m;
+      timed(QSP_K_OTHER, [&] { launch_explicit<T>(geom_, a, kExplMatvec, tx(), ctr_, st_); });
+      timed(QSP_K_ROW_FWD, [&] { launch_explicit<T>(geom_, a, kExplUpdate, tx(), ctr_, st_); });
+      if (m < cfg_.pc_max_iter) precondition(m);
+    }
+    dst_solves_ += 2 * (cfg_.pc_max_iter);
   }
 
   PushArgs<T> push_args(const SliceFields<T>& f, double* const* ch, int k, int nch = 4) {
@@ -1371,6 +1449,13 @@ class Box final : public BoxBase {
   double* partial_ = nullptr;
   std::vector<double> amp_;
   double shift_ = 0.0;
+  bool explicit_ = false;
+  // explicit Bx/By solver: deposits chi, DJx, DJy and the Krylov vectors
+  double* ex_dep_[3] = {nullptr, nullptr, nullptr};
+  double *ex_x_ = nullptr, *ex_r_ = nullptr, *ex_q_ = nullptr;
+  double* ex_p_[2] = {nullptr, nullptr};
+  double* ex_partial_ = nullptr;
+  ExplicitScalars* ex_s_ = nullptr;
   int ip_ = 0, ic_ = 1, in_ = 2;   // deposit buffers of slices k-1, k, k+1
   int ik_ = 0, i1_ = 1, i2_ = 2;   // B buffers of slices k, k-1, k-2
   bool dep_valid_ = false;

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libqsp.so")
 QSP_OK, QSP_ERR_INVALID_ARG, QSP_ERR_BAD_STATE, QSP_ERR_OUT_OF_MEMORY, \
     QSP_ERR_DEVICE, QSP_ERR_NONFINITE = range(6)
 QSP_FP32, QSP_FP64 = 0, 1
+QSP_BXBY_PC, QSP_BXBY_EXPLICIT = 0, 1
 
 QUANTITIES = ("psi", "exmby", "eypbx", "ez", "bx", "by", "bz",
               "rho_mjz", "jx", "jy", "jz", "rho")
@@ -51,7 +52,7 @@ class Config(C.Structure):
                 ("pc_max_iter", C.c_int32), ("deposit_mode", C.c_int32),
                 ("pc_tol", C.c_double), ("pc_shift", C.c_double),
                 ("psi_floor", C.c_double), ("mem_cap_bytes", C.c_int64),
-                ("shape_order", C.c_int32), ("reserved1", C.c_int32)]
+                ("shape_order", C.c_int32), ("bxby_solver", C.c_int32)]
 
 
 class SliceOut(C.Structure):
@@ -163,6 +164,8 @@ def make_config(cfg, precision: str = "fp32", deposit_mode: int = 0,
     c.psi_floor = cfg.psi_floor
     c.mem_cap_bytes = mem_cap_bytes
     c.shape_order = int(getattr(cfg, "shape_order", 1))
+    c.bxby_solver = {"pc": QSP_BXBY_PC, "explicit": QSP_BXBY_EXPLICIT}[
+        getattr(cfg, "bxby_solver", "pc")]
     return c
 
 

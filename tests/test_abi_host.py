@@ -110,8 +110,17 @@ def test_shape_order_validation(order, ok):
     assert Q.validate_config(c)[0] == ok
     c = Q.make_config(dataclasses.replace(good(), shape_order=2))
     assert c.shape_order == 2
-    c.reserved1 = 1
+    c.bxby_solver = 2
     assert not Q.validate_config(c)[0]
+
+
+def test_explicit_solver_validation():
+    c = Q.make_config(dataclasses.replace(good(), bxby_solver="explicit"))
+    assert c.bxby_solver == Q.QSP_BXBY_EXPLICIT
+    assert Q.validate_config(c)[0]
+    c.shape_order = 0
+    ok, msg = Q.validate_config(c)
+    assert not ok and "explicit" in msg
 
 
 def test_status_strings():
