@@ -268,6 +268,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--shape-order", type=int, default=1, choices=(0, 1, 2, 3),
                     help="transverse particle shape of the timed workload (1: linear)")
+    ap.add_argument("--solver", default="pc", choices=("pc", "explicit"),
+                    help="Bx/By field solver: predictor-corrector or explicit "
+                         "(conjugate gradients to a relative residual of 1e-5, at most 6)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
@@ -308,6 +311,10 @@ def main():
     if args.shape_order != 1:
         cfg.shape_order = args.shape_order
         wname += f"_order{args.shape_order}"
+    if args.solver == "explicit":
+        cfg.bxby_solver = "explicit"
+        cfg.pc_max_iter, cfg.pc_tol = 6, 1e-5
+        wname += "_explicit"
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     box, dt, stats, kt = run_gpu(cfg, beam, "fp32", args.steps, args.warmup,
                                  args.timing_every)
@@ -330,8 +337,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wname, "nx": cfg.nx, "ny": cfg.ny,
                    "slices": cfg.nzeta, "particles": n_p,
-                   "pc": f"<= {cfg.pc_max_iter} iterations, tol {cfg.pc_tol}",
-                   "shape_order": cfg.shape_order, "deposit_sums": "f64"},
+                   "bxby_iterations": f"<= {cfg.pc_max_iter}, tol {cfg.pc_tol}",
+                   "shape_order": cfg.shape_order, "bxby_solver": cfg.bxby_solver,
+                   "deposit_sums": "f64"},
         "dst_solves_per_s": solves / dt,
         "dst_solves_per_s_standalone_batch3": standalone,
         "pc_iterations_per_slice": sum(s["pc_iterations"] for s in stats) / (cfg.nzeta * args.steps),

@@ -11,14 +11,18 @@
 // field precision T, so the Polak-Ribiere form of beta is used (it tolerates
 // an inexact preconditioner).
 //
-// One iteration is four launches:
-//   matvec    p = z + beta p_old, q = A p, alpha = rho / (p.q)
-//   update    x += alpha p, r -= alpha q, B = x, residual, then the forward
-//             sine transform along x of -r
-//   column    transform along y, division by (lambda - c0), inverse along y
-//   rowinv    inverse transform along x -> z = M^-1 r; rho = z.r and
-//             beta = -alpha (z.q) / rho_old
-// Every kernel returns at once after convergence (device-side flag).
+// One iteration m is four launches:
+//   matvec(m)  p_m = z_{m-1} + beta p_{m-1}, q_m = A p_m, partial p.q
+//   update(m)  alpha_m = rho_{m-1} / (p.q); x += alpha p, r -= alpha q,
+//              B = x, partial r.r, forward sine transform along x of -r
+//   column     transform along y, division by (lambda - c0), inverse along y
+//   rowinv(m)  residual test; inverse transform along x -> z_m = M^-1 r_m,
+//              partials of z.r and z.q
+// Dot products leave one partial sum per workgroup, which the next kernel
+// adds up in every workgroup in the same order: no atomics and no device-
+// wide fences inside the solve (a fence per workgroup writes back the XCD's
+// L2).  The scalars a later kernel needs are kept by workgroup 0 in
+// alternating slots.  After convergence every kernel returns at once.
 #include "dst_impl.hpp"
 
 namespace qsp {
@@ -27,14 +31,10 @@ using namespace dst_detail;
 
 namespace {
 
-// Adds v[0..NV-1] over the workgroup and stores the sums at partial[bid*NV];
-// the last of nblk workgroups to arrive returns true with the totals over
-// all workgroups in tot (valid in thread 0), summed in a fixed order.
+// Workgroup sums of v stored at part[bid * NV + k].
 template <int NV>
-__device__ bool reduce_last(double (&v)[NV], double* partial, int bid, int nblk,
-                            unsigned int* arrived, double (&tot)[NV]) {
+__device__ void store_partial(double (&v)[NV], double* part, int bid) {
   __shared__ double red[NV][kBlock / 64];
-  __shared__ bool last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; ++k)
@@ -44,26 +44,26 @@ __device__ bool reduce_last(double (&v)[NV], double* partial, int bid, int nblk,
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0)
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
       double s = 0.0;
       for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
-      partial[static_cast<size_t>(bid) * NV + k] = s;
+      part[static_cast<size_t>(bid) * NV + k] = s;
     }
-    __threadfence();
-    const unsigned int prev = atomicAdd(arrived, 1u);
-    last = (prev == static_cast<unsigned int>(nblk - 1));
-  }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
+}
+
+// Totals of nblk partial records, in a fixed order; every thread gets them.
+template <int NV>
+__device__ void sum_partials(const double* part, int nblk, double (&tot)[NV]) {
+  __shared__ double red[NV][kBlock / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double t[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) t[k] = 0.0;
   for (int b = threadIdx.x; b < nblk; b += kBlock)
 #pragma unroll
-    for (int k = 0; k < NV; ++k) t[k] += partial[static_cast<size_t>(b) * NV + k];
+    for (int k = 0; k < NV; ++k) t[k] += part[static_cast<size_t>(b) * NV + k];
 #pragma unroll
   for (int k = 0; k < NV; ++k)
     for (int off = 32; off > 0; off >>= 1) t[k] += __shfl_down(t[k], off, 64);
@@ -72,30 +72,41 @@ __device__ bool reduce_last(double (&v)[NV], double* partial, int bid, int nblk,
 #pragma unroll
     for (int k = 0; k < NV; ++k) red[k][wave] = t[k];
   __syncthreads();
-  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
-      tot[k] = s;
-    }
-    *arrived = 0u;
+  for (int k = 0; k < NV; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
+    tot[k] = s;
   }
-  return true;
 }
 
-// relative residual ||r|| / ||b|| of both systems together
-__device__ inline void close_residual(DevCounters* ctr, double rn, double bn, double tol) {
-  const double res = bn > 0.0 ? sqrt(rn / bn) : (rn == 0.0 ? 0.0 : INFINITY);
-  if (!isfinite(res) || !isfinite(rn) || !isfinite(bn)) ctr->nonfinite = 1u;
+__device__ inline bool first_thread() {
+  return blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
+}
+
+// relative residual of both systems and the stop decision
+__device__ inline double rel_residual(double rr, double bn) {
+  return bn > 0.0 ? sqrt(rr / bn) : (rr == 0.0 ? 0.0 : INFINITY);
+}
+
+__device__ inline bool stops(double rr, double res, double tol) {
+  return rr == 0.0 || (tol > 0.0 && res < tol) || !isfinite(res);
+}
+
+__device__ inline void record_residual(DevCounters* ctr, double rr, double bn, int iters, bool stop,
+                                       double res) {
   ctr->pc_resid = res;
-  if (rn == 0.0 || (tol > 0.0 && res < tol)) ctr->pc_done = 1u;
+  ctr->pc_iters = static_cast<unsigned int>(iters);
+  if (iters > 0) ctr->pc_iterations += 1ull;
+  if (!isfinite(res) || !isfinite(rr) || !isfinite(bn)) ctr->nonfinite = 1u;
+  if (stop) ctr->pc_done = 1u;
 }
 
 }  // namespace
 
 // Set-up: right-hand side b = -R, x0 = the initial guess held in B,
-// r0 = b - A x0, ||b||^2, and the forward transform along x of -r0.
+// r0 = b - A x0, partials of ||b||^2 and ||r0||^2, and the forward
+// transform along x of -r0.
 template <typename T, int LOGN>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_expl_setup(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
@@ -163,25 +174,41 @@ k_expl_setup(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     const int rr = e >> lx, i = e & (n - 1);
     out[(j0 + rr) * n + i] = buf[Pad<T>::rpos(n, ppitch, rr, i)];
   });
-  double v[2] = {bn, rn}, tot[2];
-  const int nrb = ny / R;
-  if (reduce_last<2>(v, a.partial, fld * nrb + blockIdx.x, 2 * nrb, &a.s->blocks_arrived, tot) &&
-      threadIdx.x == 0) {
-    a.s->bnorm2 = tot[0];
-    close_residual(ctr, tot[1], tot[0], a.tol);
-  }
+  double v[2] = {bn, rn};
+  store_partial<2>(v, a.part_s, fld * (ny / R) + blockIdx.x);
 }
 
-// Inverse transform along x of the column-pass output: z = M^-1 r; then
-// rho = z.r and, from the second round on, the Polak-Ribiere beta.
+// Residual test of r_m (partials of the set-up or of update(m)), then the
+// inverse transform along x of the column-pass output: z_m = M^-1 r_m, with
+// partials of z.r and z.q per system.
 template <typename T, int LOGN>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   if (ctr->pc_done) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* buf = reinterpret_cast<T*>(smem_raw);
   const int n = g.nx, ny = g.ny;
   const int R = g.rr;
+  const int nblk = 2 * (ny / R);
+  double bn, rr;
+  if (a.it == 0) {
+    double t[2];
+    sum_partials<2>(a.part_s, nblk, t);
+    bn = t[0];
+    rr = t[1];
+  } else {
+    double t[1];
+    sum_partials<1>(a.part_u, nblk, t);
+    bn = a.s->bnorm2;
+    rr = t[0];
+  }
+  const double res = rel_residual(rr, bn);
+  const bool stop = stops(rr, res, a.tol);
+  if (first_thread()) {
+    if (a.it == 0) a.s->bnorm2 = bn;
+    record_residual(ctr, rr, bn, a.it, stop, res);
+  }
+  if (stop) return;
+  extern __shared__ unsigned char smem_raw[];
+  T* buf = reinterpret_cast<T*>(smem_raw);
   const int ppitch = Pad<T>::pitch(n);
   const Cplx<T>* tw;
   const T* pre;
@@ -192,8 +219,8 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   const T* in = a.col + fld * plane;
   const int lx = g.lx;
   for_elems(R * n, [&](int e) {
-    const int rr = e >> lx, i = e & (n - 1);
-    buf[Pad<T>::rpos(n, ppitch, rr, i)] = in[(j0 + rr) * n + i];
+    const int rw = e >> lx, i = e & (n - 1);
+    buf[Pad<T>::rpos(n, ppitch, rw, i)] = in[(j0 + rw) * n + i];
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
@@ -203,10 +230,10 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   const bool with_q = a.it > 0;
   double zr = 0.0, zq = 0.0;
   for_elems(R * n, [&](int e) {
-    const int rr = e >> lx, i = e & (n - 1);
-    const int j = j0 + rr;
+    const int rw = e >> lx, i = e & (n - 1);
+    const int j = j0 + rw;
     const int o = j * n + i;
-    const T u = buf[Pad<T>::rpos(n, ppitch, rr, i)];
+    const T u = buf[Pad<T>::rpos(n, ppitch, rw, i)];
     const T zv = (i > 0 && j > 0) ? u : T(0);
     z[o] = zv;
     zr += static_cast<double>(zv) * r[o];
@@ -214,78 +241,105 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   });
   double v[4] = {fld == 0 ? zr : 0.0, fld == 1 ? zr : 0.0, fld == 0 ? zq : 0.0,
                  fld == 1 ? zq : 0.0};
-  double tot[4];
-  const int nrb = ny / R;
-  if (reduce_last<4>(v, a.partial, fld * nrb + blockIdx.x, 2 * nrb, &a.s->blocks_arrived, tot) &&
-      threadIdx.x == 0) {
-    for (int s = 0; s < 2; ++s) {
-      const double rho_old = a.s->rho[s];
-      a.s->beta[s] = (with_q && rho_old != 0.0) ? -a.s->alpha[s] * tot[2 + s] / rho_old : 0.0;
-      a.s->rho[s] = tot[s];
-    }
-  }
+  store_partial<4>(v, a.part_z, fld * (ny / R) + blockIdx.x);
 }
 
-// p = z + beta p_old (p_old unused in the first iteration), q = A p and
-// alpha = rho / (p.q) per system.
+// matvec(it): rho_{it-1} = z.r and the Polak-Ribiere
+// beta = -alpha_{it-1} (z.q) / rho_{it-2}; p = z + beta p_old (p_old unused
+// in the first iteration), q = A p and partials of p.q.  Grid (ny/R, 2).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_expl_matvec(Geom g, ExplicitArgs<T> a, DevCounters* ctr) {
   if (ctr->pc_done) return;
   const int n = g.nx, ny = g.ny;
-  const size_t plane = static_cast<size_t>(n) * ny;
+  const int R = g.rr;
+  const int nblk = 2 * (ny / R);
   const int fld = blockIdx.y;
+  double t[4];
+  sum_partials<4>(a.part_z, nblk, t);
+  const int it = a.it;
+  const bool use_old = it > 1;
+  double beta = 0.0;
+  if (use_old) {
+    const double rho_prev = a.s->rho[it & 1][fld];          // rho_{it-2}
+    const double alpha = a.s->alpha[(it - 1) & 1][fld];     // alpha_{it-1}
+    beta = rho_prev != 0.0 ? -alpha * t[2 + fld] / rho_prev : 0.0;
+  }
+  if (first_thread()) {
+    a.s->rho[(it - 1) & 1][0] = t[0];                      // rho_{it-1}
+    a.s->rho[(it - 1) & 1][1] = t[1];
+  }
+  const size_t plane = static_cast<size_t>(n) * ny;
   const T* z = a.z + fld * plane;
-  const double* pold = a.p[(a.it + 1) & 1] + fld * plane;
-  double* pnew = a.p[a.it & 1] + fld * plane;
+  const double* pold = a.p[(it + 1) & 1] + fld * plane;
+  double* pnew = a.p[it & 1] + fld * plane;
   double* q = a.q + fld * plane;
-  const double beta = a.it > 1 ? a.s->beta[fld] : 0.0;
-  const bool use_old = a.it > 1;
+  const double* chi = a.chi;
   const double ihx2 = 1.0 / (g.hx * g.hx), ihy2 = 1.0 / (g.hy * g.hy);
-  auto P = [&](int i, int j) -> double {
-    if (i < 1 || i >= n || j < 1 || j >= ny) return 0.0;
-    const size_t o = static_cast<size_t>(j) * n + i;
-    return static_cast<double>(z[o]) + (use_old ? beta * pold[o] : 0.0);
-  };
+  const int j0 = blockIdx.x * R;
+  const int lx = g.lx;
   double pq = 0.0;
-  for (size_t e = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; e < plane;
-       e += static_cast<size_t>(gridDim.x) * blockDim.x) {
-    const int i = static_cast<int>(e % n), j = static_cast<int>(e / n);
-    const double pc = P(i, j);
-    const double lap = (P(i + 1, j) - 2.0 * pc + P(i - 1, j)) * ihx2 +
-                       (P(i, j + 1) - 2.0 * pc + P(i, j - 1)) * ihy2;
+  for_elems(R * n, [&](int e) {
+    const int rw = e >> lx, i = e & (n - 1);
+    const int j = j0 + rw;
+    const int o = j * n + i;
+    // neighbours with clamped indices; nodes on or beyond the Dirichlet
+    // boundary are zero
+    const int ow = i > 0 ? o - 1 : o, oe = i + 1 < n ? o + 1 : o;
+    const int os = j > 0 ? o - n : o, on = j + 1 < ny ? o + n : o;
+    double pc = static_cast<double>(z[o]), pw = static_cast<double>(z[ow]);
+    double pe = static_cast<double>(z[oe]), ps = static_cast<double>(z[os]);
+    double pn = static_cast<double>(z[on]);
+    if (use_old) {
+      pc += beta * pold[o];
+      pw += beta * pold[ow];
+      pe += beta * pold[oe];
+      ps += beta * pold[os];
+      pn += beta * pold[on];
+    }
     const bool inner = i > 0 && j > 0;
-    const double qv = inner ? -lap + a.chi[e] * pc : 0.0;
-    pnew[e] = pc;
-    q[e] = qv;
+    pc = inner ? pc : 0.0;
+    pw = i > 1 ? pw : 0.0;
+    pe = i + 1 < n ? pe : 0.0;
+    ps = j > 1 ? ps : 0.0;
+    pn = j + 1 < ny ? pn : 0.0;
+    const double lap = (pe - 2.0 * pc + pw) * ihx2 + (pn - 2.0 * pc + ps) * ihy2;
+    const double qv = inner ? -lap + chi[o] * pc : 0.0;
+    pnew[o] = pc;
+    q[o] = qv;
     pq += pc * qv;
-  }
-  double v[2] = {fld == 0 ? pq : 0.0, fld == 1 ? pq : 0.0}, tot[2];
-  if (reduce_last<2>(v, a.partial, fld * gridDim.x + blockIdx.x, 2 * gridDim.x,
-                     &a.s->blocks_arrived, tot) &&
-      threadIdx.x == 0) {
-    for (int s = 0; s < 2; ++s) a.s->alpha[s] = tot[s] > 0.0 ? a.s->rho[s] / tot[s] : 0.0;
-  }
+  });
+  double v[2] = {fld == 0 ? pq : 0.0, fld == 1 ? pq : 0.0};
+  store_partial<2>(v, a.part_m, fld * (ny / R) + blockIdx.x);
 }
 
-// x += alpha p, r -= alpha q, B = x; residual; forward transform along x
-// of -r for the preconditioner.
+// update(it): alpha = rho_{it-1} / (p.q); x += alpha p, r -= alpha q, B = x;
+// partials of r.r; forward transform along x of -r for the preconditioner.
 template <typename T, int LOGN>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   if (ctr->pc_done) return;
-  extern __shared__ unsigned char smem_raw[];
-  T* buf = reinterpret_cast<T*>(smem_raw);
   const int n = g.nx, ny = g.ny;
   const int R = g.rr;
+  const int nblk = 2 * (ny / R);
+  const int fld = blockIdx.y;
+  const int it = a.it;
+  double t[2];
+  sum_partials<2>(a.part_m, nblk, t);
+  const double rho = a.s->rho[(it - 1) & 1][fld];
+  const double alpha = t[fld] > 0.0 ? rho / t[fld] : 0.0;
+  if (first_thread()) {
+    a.s->alpha[it & 1][0] = t[0] > 0.0 ? a.s->rho[(it - 1) & 1][0] / t[0] : 0.0;
+    a.s->alpha[it & 1][1] = t[1] > 0.0 ? a.s->rho[(it - 1) & 1][1] / t[1] : 0.0;
+  }
+  extern __shared__ unsigned char smem_raw[];
+  T* buf = reinterpret_cast<T*>(smem_raw);
   const int ppitch = Pad<T>::pitch(n);
   const Cplx<T>* tw;
   const T* pre;
   stage_tables(tx, n, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
-  const int fld = blockIdx.y;
   const int j0 = blockIdx.x * R;
   const size_t plane = static_cast<size_t>(n) * ny;
-  const double alpha = a.s->alpha[fld];
-  const double* p = a.p[a.it & 1] + fld * plane;
+  const double* p = a.p[it & 1] + fld * plane;
   const double* q = a.q + fld * plane;
   double* x = a.x + fld * plane;
   double* r = a.r + fld * plane;
@@ -293,8 +347,8 @@ k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   const int lx = g.lx;
   double rn = 0.0;
   for_elems(R * n, [&](int e) {
-    const int rr = e >> lx, i = e & (n - 1);
-    const int j = j0 + rr;
+    const int rw = e >> lx, i = e & (n - 1);
+    const int j = j0 + rw;
     const int o = j * n + i;
     const bool inner = i > 0 && j > 0;
     const double xv = inner ? x[o] + alpha * p[o] : 0.0;
@@ -303,23 +357,28 @@ k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     r[o] = rv;
     B[o] = static_cast<T>(xv);
     rn += rv * rv;
-    buf[Pad<T>::rpos(n, ppitch, rr, i)] = static_cast<T>(-rv);
+    buf[Pad<T>::rpos(n, ppitch, rw, i)] = static_cast<T>(-rv);
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.fwd + fld * plane;
   for_elems(R * n, [&](int e) {
-    const int rr = e >> lx, i = e & (n - 1);
-    out[(j0 + rr) * n + i] = buf[Pad<T>::rpos(n, ppitch, rr, i)];
+    const int rw = e >> lx, i = e & (n - 1);
+    out[(j0 + rw) * n + i] = buf[Pad<T>::rpos(n, ppitch, rw, i)];
   });
-  double v[1] = {rn}, tot[1];
-  const int nrb = ny / R;
-  if (reduce_last<1>(v, a.partial, fld * nrb + blockIdx.x, 2 * nrb, &a.s->blocks_arrived, tot) &&
-      threadIdx.x == 0) {
-    ctr->pc_iters += 1u;
-    ctr->pc_iterations += 1ull;
-    close_residual(ctr, tot[0], a.s->bnorm2, a.tol);
-  }
+  double v[1] = {rn};
+  store_partial<1>(v, a.part_u, fld * (ny / R) + blockIdx.x);
+}
+
+// Residual test after the last iteration (one workgroup).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_expl_close(Geom g, ExplicitArgs<T> a, DevCounters* ctr) {
+  if (ctr->pc_done) return;
+  double t[1];
+  sum_partials<1>(a.part_u, 2 * (g.ny / g.rr), t);
+  const double bn = a.s->bnorm2;
+  const double res = rel_residual(t[0], bn);
+  if (threadIdx.x == 0) record_residual(ctr, t[0], bn, a.it, stops(t[0], res, a.tol), res);
 }
 
 // ---------------------------------------------------------------------------
@@ -340,18 +399,8 @@ size_t row_lds(const Geom& g) {
 
 }  // namespace
 
-int explicit_matvec_blocks(const Geom& g) {
-  const size_t plane = static_cast<size_t>(g.nx) * g.ny;
-  size_t b = (plane + kBlock - 1) / kBlock;
-  if (b > 512) b = 512;
-  return static_cast<int>(b);
-}
-
-int explicit_partial_count(const Geom& g) {
-  const int rows = 2 * (g.ny / g.rr) * 4;
-  const int mv = 2 * explicit_matvec_blocks(g) * 2;
-  return rows > mv ? rows : mv;
-}
+// partial records of one row-blocked grid: one per workgroup of (ny/rr, 2)
+int explicit_partial_count(const Geom& g) { return 2 * (g.ny / g.rr); }
 
 template <typename T>
 void launch_explicit(const Geom& g, const ExplicitArgs<T>& a, ExplicitStep step,
@@ -359,8 +408,12 @@ void launch_explicit(const Geom& g, const ExplicitArgs<T>& a, ExplicitStep step,
   const int R = g.rr;
   const size_t lds = row_lds<T>(g);
   if (step == kExplMatvec) {
-    hipLaunchKernelGGL((k_expl_matvec<T>), dim3(explicit_matvec_blocks(g), 2), dim3(kBlock), 0,
-                       st, g, a, ctr);
+    hipLaunchKernelGGL((k_expl_matvec<T>), dim3(g.ny / R, 2), dim3(kBlock), 0, st, g, a, ctr);
+    QSP_LAUNCH_CHECK();
+    return;
+  }
+  if (step == kExplClose) {
+    hipLaunchKernelGGL((k_expl_close<T>), dim3(1), dim3(kBlock), 0, st, g, a, ctr);
     QSP_LAUNCH_CHECK();
     return;
   }

@@ -175,14 +175,12 @@ void launch_export_state(const Geom&, const Lattice&, const Particles<T>&, doubl
 
 // ------------------------------------------------- explicit Bx/By solver
 // Device scalars of the preconditioned conjugate-gradient solve of
-// (-lap + chi) B = -R (two systems: 0 Bx, 1 By).
+// (-lap + chi) B = -R (two systems: 0 Bx, 1 By), in alternating slots by
+// iteration parity.
 struct ExplicitScalars {
   double bnorm2;            // ||b||^2 of both systems
-  double rho[2];            // z . r
-  double alpha[2];
-  double beta[2];
-  unsigned int blocks_arrived;
-  unsigned int pad;
+  double rho[2][2];         // z . r
+  double alpha[2][2];
 };
 
 template <typename T>
@@ -202,13 +200,23 @@ struct ExplicitArgs {
   const T* col;             // column-pass output, input of the inverse row pass
   T* fwd;                   // forward row-pass output, input of the column pass
   T* z;                     // preconditioned residual
-  double* partial;          // explicit_partial_count doubles
+  // per-workgroup partial sums, explicit_partial_count records each
+  double* part_s;           // set-up: ||b||^2, ||r0||^2
+  double* part_z;           // inverse row pass: z.r, z.q per system
+  double* part_m;           // matvec: p.q per system
+  double* part_u;           // update: ||r||^2
   ExplicitScalars* s;
   double tol;               // relative residual target (<= 0: run every iteration)
   int it;                   // 0 set-up, m >= 1 iteration m
 };
 
-enum ExplicitStep { kExplSetup = 0, kExplMatvec = 1, kExplUpdate = 2, kExplRowInv = 3 };
+enum ExplicitStep {
+  kExplSetup = 0,
+  kExplMatvec = 1,
+  kExplUpdate = 2,
+  kExplRowInv = 3,
+  kExplClose = 4
+};
 
 template <typename T>
 void launch_explicit(const Geom&, const ExplicitArgs<T>&, ExplicitStep, const AxisTables<T>&,

@@ -1085,7 +1085,7 @@ class Box final : public BoxBase {
       ex_q_ = alloc<double>(2 * pl);
       ex_p_[0] = alloc<double>(2 * pl);
       ex_p_[1] = alloc<double>(2 * pl);
-      ex_partial_ = alloc<double>(static_cast<size_t>(explicit_partial_count(geom_)));
+      ex_partial_ = alloc<double>(static_cast<size_t>(explicit_partial_count(geom_)) * 9);
       ex_s_ = alloc<ExplicitScalars>(1);
     }
     if (cfg_.shape_order != 1) {
@@ -1345,7 +1345,11 @@ class Box final : public BoxBase {
     a.fwd = t1_;
     a.col = t2_;
     a.z = t1_ + 2 * pl;
-    a.partial = ex_partial_;
+    const size_t np = static_cast<size_t>(explicit_partial_count(geom_));
+    a.part_s = ex_partial_;
+    a.part_z = ex_partial_ + 2 * np;
+    a.part_m = ex_partial_ + 6 * np;
+    a.part_u = ex_partial_ + 8 * np;
     a.s = ex_s_;
     a.tol = cfg_.pc_tol;
     ColArgs<T> c{};
@@ -1369,6 +1373,8 @@ class Box final : public BoxBase {
       timed(QSP_K_ROW_FWD, [&] { launch_explicit<T>(geom_, a, kExplUpdate, tx(), ctr_, st_); });
       if (m < cfg_.pc_max_iter) precondition(m);
     }
+    a.it = cfg_.pc_max_iter;
+    timed(QSP_K_OTHER, [&] { launch_explicit<T>(geom_, a, kExplClose, tx(), ctr_, st_); });
     dst_solves_ += 2 * (cfg_.pc_max_iter);
   }
 
