@@ -75,7 +75,6 @@ struct AxisTables {
 struct DevCounters {
   unsigned int pc_done;        // 1 once the current slice's P-C converged
   unsigned int pc_iters;       // iterations done for the current slice
-  unsigned int blocks_arrived; // last-block-done counter of the residual
   unsigned int nonfinite;      // sticky: non-finite residual or norm seen
   double pc_resid;             // last residual of the current slice
   double max_resid;            // largest final residual over slices

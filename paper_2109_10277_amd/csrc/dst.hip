@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_row_inv_pc(Geom g, PCArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   if (ctr->pc_done) return;
   extern __shared__ unsigned char smem_raw[];
-  row_inv_pc_block<T, LOGN>(g, a, tx, ctr, blockIdx.x, blockIdx.y, smem_raw);
+  row_inv_pc_block<T, LOGN>(g, a, tx, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // ---------------------------------------------------------------------------

@@ -30,6 +30,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "partials.hpp"
 
 namespace qsp {
 namespace dst_detail {
@@ -596,16 +597,15 @@ __device__ __forceinline__ void col_block(const Geom& g, const ColArgs<T>& a,
 
 // Predictor-corrector epilogue: B_new from the inverse transform, FP64 sums
 // of |B_new - B_old|^2 and |B_new|^2, B_old overwritten by B_new in place.
-// The last workgroup to finish forms the relative change and decides
-// convergence for the whole slice.
+// Each workgroup leaves its two sums in a.partial; the next trial push (or
+// the real push after the last iteration) forms the relative change and
+// decides convergence.
 template <typename T, int LOGN>
 __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>& a,
-                                                 const AxisTables<T>& tx, DevCounters* ctr,
-                                                 int bxi, int fld, unsigned char* smem_raw) {
+                                                 const AxisTables<T>& tx, int bxi, int fld,
+                                                 unsigned char* smem_raw) {
   __syncthreads();   // the workgroup's previous use of LDS is complete
   T* buf = reinterpret_cast<T*>(smem_raw);
-  __shared__ double red[2][kBlock / 64];
-  __shared__ bool last;
   const int n = g.nx;
   const int R = g.rr;
   const int ppitch = Pad<T>::pitch(n);
@@ -636,64 +636,8 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
     b[j * n + i] = u;
     if (tp) tp[j * n + i] = u;
   });
-  // workgroup reduction
-  for (int off = 32; off > 0; off >>= 1) {
-    dsum += __shfl_down(dsum, off, 64);
-    nsum += __shfl_down(nsum, off, 64);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-    red[0][wave] = dsum;
-    red[1][wave] = nsum;
-  }
-  __syncthreads();
-  const int nrb = g.ny / R;
-  const int nblk = 2 * nrb;
-  const int bid = fld * nrb + bxi;
-  if (threadIdx.x == 0) {
-    double d = 0.0, s = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-      d += red[0][w];
-      s += red[1][w];
-    }
-    a.partial[2 * bid] = d;
-    a.partial[2 * bid + 1] = s;
-    __threadfence();
-    const unsigned int prev = atomicAdd(&ctr->blocks_arrived, 1u);
-    last = (prev == static_cast<unsigned int>(nblk - 1));
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double d = 0.0, s = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += kBlock) {
-    d += a.partial[2 * k];
-    s += a.partial[2 * k + 1];
-  }
-  for (int off = 32; off > 0; off >>= 1) {
-    d += __shfl_down(d, off, 64);
-    s += __shfl_down(s, off, 64);
-  }
-  __syncthreads();
-  if (lane == 0) {
-    red[0][wave] = d;
-    red[1][wave] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double dd = 0.0, ss = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) {
-      dd += red[0][w];
-      ss += red[1][w];
-    }
-    double res = ss > 0.0 ? sqrt(dd / ss) : (dd == 0.0 ? 0.0 : INFINITY);
-    if (!isfinite(res) || !isfinite(dd) || !isfinite(ss)) ctr->nonfinite = 1u;
-    ctr->pc_resid = res;
-    ctr->pc_iters += 1u;
-    ctr->pc_iterations += 1ull;
-    ctr->blocks_arrived = 0u;
-    if (a.tol > 0.0 && res < a.tol) ctr->pc_done = 1u;
-  }
+  double v[2] = {dsum, nsum};
+  partials::store<2>(v, a.partial, fld * (g.ny / R) + bxi);
 }
 
 }  // namespace dst_detail

@@ -24,61 +24,13 @@
 // L2).  The scalars a later kernel needs are kept by workgroup 0 in
 // alternating slots.  After convergence every kernel returns at once.
 #include "dst_impl.hpp"
+#include "partials.hpp"
 
 namespace qsp {
 
 using namespace dst_detail;
 
 namespace {
-
-// Workgroup sums of v stored at part[bid * NV + k].
-template <int NV>
-__device__ void store_partial(double (&v)[NV], double* part, int bid) {
-  __shared__ double red[NV][kBlock / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < NV; ++k)
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_down(v[k], off, 64);
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[k][wave] = v[k];
-  __syncthreads();
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-      double s = 0.0;
-      for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
-      part[static_cast<size_t>(bid) * NV + k] = s;
-    }
-}
-
-// Totals of nblk partial records, in a fixed order; every thread gets them.
-template <int NV>
-__device__ void sum_partials(const double* part, int nblk, double (&tot)[NV]) {
-  __shared__ double red[NV][kBlock / 64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  double t[NV];
-#pragma unroll
-  for (int k = 0; k < NV; ++k) t[k] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += kBlock)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) t[k] += part[static_cast<size_t>(b) * NV + k];
-#pragma unroll
-  for (int k = 0; k < NV; ++k)
-    for (int off = 32; off > 0; off >>= 1) t[k] += __shfl_down(t[k], off, 64);
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < NV; ++k) red[k][wave] = t[k];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < NV; ++k) {
-    double s = 0.0;
-    for (int w = 0; w < kBlock / 64; ++w) s += red[k][w];
-    tot[k] = s;
-  }
-}
 
 __device__ inline bool first_thread() {
   return blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
@@ -175,7 +127,7 @@ k_expl_setup(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     out[(j0 + rr) * n + i] = buf[Pad<T>::rpos(n, ppitch, rr, i)];
   });
   double v[2] = {bn, rn};
-  store_partial<2>(v, a.part_s, fld * (ny / R) + blockIdx.x);
+  partials::store<2>(v, a.part_s, fld * (ny / R) + blockIdx.x);
 }
 
 // Residual test of r_m (partials of the set-up or of update(m)), then the
@@ -191,12 +143,12 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   double bn, rr;
   if (a.it == 0) {
     double t[2];
-    sum_partials<2>(a.part_s, nblk, t);
+    partials::sum<2>(a.part_s, nblk, t);
     bn = t[0];
     rr = t[1];
   } else {
     double t[1];
-    sum_partials<1>(a.part_u, nblk, t);
+    partials::sum<1>(a.part_u, nblk, t);
     bn = a.s->bnorm2;
     rr = t[0];
   }
@@ -241,7 +193,7 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   });
   double v[4] = {fld == 0 ? zr : 0.0, fld == 1 ? zr : 0.0, fld == 0 ? zq : 0.0,
                  fld == 1 ? zq : 0.0};
-  store_partial<4>(v, a.part_z, fld * (ny / R) + blockIdx.x);
+  partials::store<4>(v, a.part_z, fld * (ny / R) + blockIdx.x);
 }
 
 // matvec(it): rho_{it-1} = z.r and the Polak-Ribiere
@@ -255,7 +207,7 @@ __global__ void __launch_bounds__(kBlock) k_expl_matvec(Geom g, ExplicitArgs<T> 
   const int nblk = 2 * (ny / R);
   const int fld = blockIdx.y;
   double t[4];
-  sum_partials<4>(a.part_z, nblk, t);
+  partials::sum<4>(a.part_z, nblk, t);
   const int it = a.it;
   const bool use_old = it > 1;
   double beta = 0.0;
@@ -309,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_expl_matvec(Geom g, ExplicitArgs<T> 
     pq += pc * qv;
   });
   double v[2] = {fld == 0 ? pq : 0.0, fld == 1 ? pq : 0.0};
-  store_partial<2>(v, a.part_m, fld * (ny / R) + blockIdx.x);
+  partials::store<2>(v, a.part_m, fld * (ny / R) + blockIdx.x);
 }
 
 // update(it): alpha = rho_{it-1} / (p.q); x += alpha p, r -= alpha q, B = x;
@@ -324,7 +276,7 @@ k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   const int fld = blockIdx.y;
   const int it = a.it;
   double t[2];
-  sum_partials<2>(a.part_m, nblk, t);
+  partials::sum<2>(a.part_m, nblk, t);
   const double rho = a.s->rho[(it - 1) & 1][fld];
   const double alpha = t[fld] > 0.0 ? rho / t[fld] : 0.0;
   if (first_thread()) {
@@ -367,7 +319,7 @@ k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     out[(j0 + rw) * n + i] = buf[Pad<T>::rpos(n, ppitch, rw, i)];
   });
   double v[1] = {rn};
-  store_partial<1>(v, a.part_u, fld * (ny / R) + blockIdx.x);
+  partials::store<1>(v, a.part_u, fld * (ny / R) + blockIdx.x);
 }
 
 // Residual test after the last iteration (one workgroup).
@@ -375,7 +327,7 @@ template <typename T>
 __global__ void __launch_bounds__(kBlock) k_expl_close(Geom g, ExplicitArgs<T> a, DevCounters* ctr) {
   if (ctr->pc_done) return;
   double t[1];
-  sum_partials<1>(a.part_u, 2 * (g.ny / g.rr), t);
+  partials::sum<1>(a.part_u, 2 * (g.ny / g.rr), t);
   const double bn = a.s->bnorm2;
   const double res = rel_residual(t[0], bn);
   if (threadIdx.x == 0) record_residual(ctr, t[0], bn, a.it, stops(t[0], res, a.tol), res);

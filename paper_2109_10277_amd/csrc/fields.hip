@@ -2,6 +2,7 @@
 // initial guess and bookkeeping, output copies and layout conversions.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "partials.hpp"
 
 namespace qsp {
 
@@ -51,8 +52,9 @@ __global__ void k_add_current(size_t n, const double* src, double* jz, double* r
 }
 
 __global__ void k_slice_end(DevCounters* ctr, int32_t* iters_out, double* resid_out,
-                            double tol, int max_iter) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+                            double tol, int max_iter, const double* pc_partial, int pc_nblk) {
+  if (pc_partial && !ctr->pc_done) partials::pc_consume(pc_partial, pc_nblk, tol, ctr, true);
+  if (threadIdx.x != 0) return;
   const double r = ctr->pc_resid;
   if (iters_out) *iters_out = static_cast<int32_t>(ctr->pc_iters);
   if (resid_out) *resid_out = r;
@@ -172,9 +174,9 @@ void launch_add_current(size_t n, const double* src, double* jz, double* rho, hi
 }
 
 void launch_slice_end(DevCounters* ctr, int32_t* iters_out, double* resid_out, double tol,
-                      int max_iter, hipStream_t st) {
-  hipLaunchKernelGGL(k_slice_end, dim3(1), dim3(64), 0, st, ctr, iters_out, resid_out, tol,
-                     max_iter);
+                      int max_iter, const double* pc_partial, int pc_nblk, hipStream_t st) {
+  hipLaunchKernelGGL(k_slice_end, dim3(1), dim3(kBlock), 0, st, ctr, iters_out, resid_out, tol,
+                     max_iter, pc_partial, pc_nblk);
   QSP_LAUNCH_CHECK();
 }
 

@@ -156,6 +156,11 @@ struct PushArgs {
   double* resid_out;
   double pc_tol;
   int pc_max_iter;
+  // partial records of the last corrector solve (null: nothing to test);
+  // a trial push tests them from its second iteration of a slice on
+  const double* pc_partial;
+  int pc_nblk;
+  int pc_iter;              // trial push: P-C iteration index within the slice
 };
 
 template <typename T>
@@ -231,7 +236,7 @@ template <typename T>
 void launch_guess(const Geom&, T* bx, T* by, const T* bx1, const T* by1, const T* bx2,
                   const T* by2, DevCounters*, hipStream_t);
 void launch_slice_end(DevCounters*, int32_t* iters_out, double* resid_out, double tol,
-                      int max_iter, hipStream_t);
+                      int max_iter, const double* pc_partial, int pc_nblk, hipStream_t);
 
 // copy a stored [ny][nx] grid into an [ny+1][nx+1] node array
 struct OutCopy {

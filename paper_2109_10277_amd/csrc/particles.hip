@@ -5,6 +5,7 @@
 // push_tile.hpp.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "partials.hpp"
 #include "push_tile.hpp"
 
 namespace qsp {
@@ -16,8 +17,17 @@ using push_detail::TileShape;
 template <typename T, int MODE, int O>
 __global__ void __launch_bounds__(kBlock)
 k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
-  if (MODE == kPushTrial && ctr->pc_done) return;
-  if (MODE == kPushReal && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+  const bool first = blockIdx.x == 0 && blockIdx.y == 0;
+  if (MODE == kPushTrial) {
+    if (ctr->pc_done) return;
+    // convergence of the previous corrector solve of this slice
+    if (a.pc_partial && a.pc_iter > 0 &&
+        partials::pc_consume(a.pc_partial, a.pc_nblk, a.pc_tol, ctr, first))
+      return;
+  }
+  if (MODE == kPushReal && first && a.pc_partial && !ctr->pc_done)
+    partials::pc_consume(a.pc_partial, a.pc_nblk, a.pc_tol, ctr, true);   // the last solve
+  if (MODE == kPushReal && first && threadIdx.x == 0) {
     // close the slice's predictor-corrector bookkeeping
     const double r = ctr->pc_resid;
     if (a.iters_out) *a.iters_out = static_cast<int32_t>(ctr->pc_iters);

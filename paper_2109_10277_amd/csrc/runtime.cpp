@@ -1239,7 +1239,9 @@ class Box final : public BoxBase {
       explicit_bxby(k, dc, amp, bxk, byk);
     } else {
       {
-        const PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
+        PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
+        a.pc_partial = partial_;
+        a.pc_nblk = pc_partial_count(geom_);
         SrcBxBy<T> s{};
         s.jz = dc[3];
         s.jx_prev = dp[1];
@@ -1267,6 +1269,7 @@ class Box final : public BoxBase {
         c.zero.count = 2;
         c.zero.n = pl;
         for (int m = 0; m < cfg_.pc_max_iter; ++m) {
+          a.pc_iter = m;
           timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, ctr_, st_); });
           timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_bxby<T>(geom_, s, tx(), ctr_, st_); });
           timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
@@ -1296,13 +1299,18 @@ class Box final : public BoxBase {
     // slice); it also closes the predictor-corrector bookkeeping of slice k
     if (k + 1 < cfg_.nzeta) {
       PushArgs<T> a = push_args(fields(bxk, byk), dn, k);
+      if (!explicit_) {   // the last corrector solve's convergence test
+        a.pc_partial = partial_;
+        a.pc_nblk = pc_partial_count(geom_);
+      }
       a.iters_out = iters_out;
       a.resid_out = resid_out;
       timed(QSP_K_PUSH, [&] { launch_push<T>(geom_, lat_, a, kPushReal, ctr_, st_); });
       pushes_ += lat_.np;
     } else {
       timed(QSP_K_OTHER, [&] {
-        launch_slice_end(ctr_, iters_out, resid_out, cfg_.pc_tol, cfg_.pc_max_iter, st_);
+        launch_slice_end(ctr_, iters_out, resid_out, cfg_.pc_tol, cfg_.pc_max_iter,
+                         explicit_ ? nullptr : partial_, pc_partial_count(geom_), st_);
       });
     }
     // hand-off: J_perp of k becomes the previous slice's, B rotates
