@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 
 namespace qsp {
 
@@ -108,6 +109,7 @@ class KernelTimer {
     std::fill(std::begin(n_), std::end(n_), 0);
   }
   bool active(int k) const { return every_ > 0 && k % every_ == 0; }
+  int every() const { return every_; }
   void begin(int cls, hipStream_t st) {
     cur_ = {get(), get(), cls};
     QSP_HIP(hipEventRecord(cur_.a, st));
@@ -205,6 +207,7 @@ class Box final : public BoxBase {
     tiled_ = cfg.deposit_mode == 0;
     tile_rows_ = default_tile_rows();
     tile_halo_ = default_tile_halo();
+    if (const char* e = std::getenv("QSP_GRAPH")) graphs_ = std::atoi(e) != 0;   // 0: launch eagerly
     QSP_HIP(hipSetDevice(device_));
     try {
       allocate();
@@ -218,15 +221,21 @@ class Box final : public BoxBase {
   }
 
   ~Box() override {
+    free_graph();
+    if (cap_st_) (void)hipStreamDestroy(cap_st_);
     free_beam();
     free_adjoint();
     clear_beam_currents();
     release();
   }
 
-  void set_deposit_tiled(bool on) override { tiled_ = on; }
+  void set_deposit_tiled(bool on) override {
+    tiled_ = on;
+    ++launch_version_;
+  }
   void set_timing(int every) override {
     timer_.collect();
+    if (every != timer_.every()) ++launch_version_;   // the sampled launches change
     timer_.reset(every);
   }
   void get_kernel_times(qsp_kernel_times* out) override { timer_.read(out); }
@@ -254,6 +263,10 @@ class Box final : public BoxBase {
     slices_done_ = 0;
     dst_solves_ = 0;
     pushes_ = 0;
+    // every buffer is clear: start the rotations from one fixed state, so
+    // that each box from the head launches the same sequence
+    ip_ = 0, ic_ = 1, in_ = 2;
+    ik_ = 0, i1_ = 1, i2_ = 2;
   }
 
   // A beam pushed during a box is sorted by slice again before the next box
@@ -270,6 +283,7 @@ class Box final : public BoxBase {
   void set_beam_gaussian(const double* amp, double sx, double sy, double x0,
                          double y0) override {
     rec_valid_ = false;
+    ++launch_version_;
     amp_.assign(amp, amp + cfg_.nzeta);
     // profile factors and their derivatives with respect to sigma
     std::vector<double> gx(cfg_.nx + 1, 0.0), gy(cfg_.ny + 1, 0.0);
@@ -295,6 +309,7 @@ class Box final : public BoxBase {
   void set_beam_particles(int64_t n, const float* soa, double dt) override {
     QSP_HIP(hipSetDevice(device_));
     rec_valid_ = false;
+    ++launch_version_;
     free_beam();
     if (n == 0) return;
     const int nz = cfg_.nzeta;
@@ -327,6 +342,7 @@ class Box final : public BoxBase {
   void set_beam_current(int k, const double* jz) override {
     QSP_HIP(hipSetDevice(device_));
     rec_valid_ = false;
+    ++launch_version_;
     if (cur_.empty()) cur_.assign(cfg_.nzeta, nullptr);
     if (!jz) {
       if (cur_[k]) {
@@ -353,6 +369,7 @@ class Box final : public BoxBase {
   }
 
   void clear_beam_currents() override {
+    ++launch_version_;
     if (cur_.empty()) return;
     (void)hipStreamSynchronize(st_);
     const int64_t b = static_cast<int64_t>(std::max<size_t>(plane() * sizeof(double), 256));
@@ -525,14 +542,13 @@ class Box final : public BoxBase {
   void run_box(const qsp_box_out* out) override {
     QSP_HIP(hipSetDevice(device_));
     rec_valid_ = false;
-    const int k0 = cursor_;
-    QSP_HIP(hipEventRecord(ev0_, st_));
-    while (cursor_ < cfg_.nzeta) {
-      const int rel = cursor_ - k0;
-      OutCopy oc = box_outputs(out, rel);
-      step(oc, out && out->pc_iters ? out->pc_iters + rel : nullptr,
-           out && out->pc_resid ? out->pc_resid + rel : nullptr);
+    if (graph_eligible()) {
+      if (!graph_matches(out)) build_graph(out);
+      replay_graph();
+      return;
     }
+    QSP_HIP(hipEventRecord(ev0_, st_));
+    box_loop(out);
     QSP_HIP(hipEventRecord(ev1_, st_));
     QSP_HIP(hipEventSynchronize(ev1_));
     float ms = 0.f;
@@ -540,6 +556,162 @@ class Box final : public BoxBase {
     last_ms_ = ms;
   }
 
+ private:
+  void box_loop(const qsp_box_out* out) {
+    const int k0 = cursor_;
+    while (cursor_ < cfg_.nzeta) {
+      const int rel = cursor_ - k0;
+      OutCopy oc = box_outputs(out, rel);
+      step(oc, out && out->pc_iters ? out->pc_iters + rel : nullptr,
+           out && out->pc_resid ? out->pc_resid + rel : nullptr);
+    }
+  }
+
+  // ------------------------------------------------------- graph replay
+  // A box run from the head launches the same ~24 kernels per slice every
+  // time; it is captured once into HIP graphs and replayed, which halves the
+  // per-launch overhead.  The launches that the kernel timer samples (the
+  // real push) run outside the graphs between graph segments, so that
+  // their events bracket exactly one kernel.  Everything that changes what a
+  // box launches bumps launch_version_ and forces a new capture.
+  struct HostState {
+    int cursor, ip, ic, in, ik, i1, i2;
+    bool dep_valid, beam_dirty;
+    int64_t slices, pushes, dst;
+  };
+  struct GraphItem {
+    hipGraphExec_t exec;
+    std::function<void()> eager;
+    int cls;
+  };
+  struct BoxGraph {
+    bool valid = false;
+    uint64_t version = 0;
+    bool has_out = false;
+    qsp_box_out out{};
+    HostState start{}, end{};
+    std::vector<GraphItem> items;
+  };
+
+  HostState save_host() const {
+    return {cursor_, ip_, ic_, in_, ik_, i1_, i2_, dep_valid_, beam_dirty_,
+            slices_done_, pushes_, dst_solves_};
+  }
+  void restore_host(const HostState& h) {
+    cursor_ = h.cursor;
+    ip_ = h.ip, ic_ = h.ic, in_ = h.in;
+    ik_ = h.ik, i1_ = h.i1, i2_ = h.i2;
+    dep_valid_ = h.dep_valid;
+    beam_dirty_ = h.beam_dirty;
+    slices_done_ = h.slices;
+    pushes_ = h.pushes;
+    dst_solves_ = h.dst;
+  }
+  static bool same_host(const HostState& a, const HostState& b) {
+    return a.cursor == b.cursor && a.ip == b.ip && a.ic == b.ic && a.in == b.in &&
+           a.ik == b.ik && a.i1 == b.i1 && a.i2 == b.i2 && a.dep_valid == b.dep_valid;
+  }
+
+  // whole boxes from the head, without a macro-particle beam (whose slice
+  // offsets change from box to box)
+  bool graph_eligible() const {
+    return graphs_ && cursor_ == 0 && beam_n_ == 0 && tape_slot_ == nullptr;
+  }
+
+  bool graph_matches(const qsp_box_out* out) const {
+    if (!graph_.valid || graph_.version != launch_version_) return false;
+    if (graph_.has_out != (out != nullptr)) return false;
+    if (out && std::memcmp(&graph_.out, out, sizeof(qsp_box_out)) != 0) return false;
+    const HostState h = save_host();
+    return same_host(graph_.start, h) && graph_.start.slices == h.slices &&
+           graph_.start.pushes == h.pushes && graph_.start.dst == h.dst;
+  }
+
+  void begin_segment() {
+    QSP_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeRelaxed));
+  }
+  void end_segment() {
+    hipGraph_t g = nullptr;
+    QSP_HIP(hipStreamEndCapture(st_, &g));
+    size_t nodes = 0;
+    QSP_HIP(hipGraphGetNodes(g, nullptr, &nodes));
+    if (nodes > 0) {
+      hipGraphExec_t ge = nullptr;
+      const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      QSP_HIP(e);
+      graph_.items.push_back({ge, {}, 0});
+    } else {
+      (void)hipGraphDestroy(g);
+    }
+  }
+
+  // The capture runs on a stream of the library's own (the caller's stream
+  // may be the legacy default stream, which cannot be captured); the graphs
+  // are then launched on the caller's stream.
+  void build_graph(const qsp_box_out* out) {
+    free_graph();
+    if (!cap_st_) QSP_HIP(hipStreamCreateWithFlags(&cap_st_, hipStreamNonBlocking));
+    QSP_HIP(hipStreamSynchronize(st_));
+    const HostState s0 = save_host();
+    hipStream_t user = st_;
+    st_ = cap_st_;
+    capturing_ = true;
+    try {
+      begin_segment();
+      box_loop(out);
+      end_segment();
+    } catch (...) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(st_, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(st_, &g);
+        if (g) (void)hipGraphDestroy(g);
+      }
+      st_ = user;
+      capturing_ = false;
+      restore_host(s0);
+      free_graph();
+      throw;
+    }
+    st_ = user;
+    capturing_ = false;
+    graph_.end = save_host();
+    restore_host(s0);
+    graph_.start = s0;
+    graph_.version = launch_version_;
+    graph_.has_out = out != nullptr;
+    graph_.out = out ? *out : qsp_box_out{};
+    graph_.valid = true;
+  }
+
+  void replay_graph() {
+    QSP_HIP(hipEventRecord(ev0_, st_));
+    for (auto& it : graph_.items) {
+      if (it.exec) {
+        QSP_HIP(hipGraphLaunch(it.exec, st_));
+      } else {
+        timer_.begin(it.cls, st_);
+        it.eager();
+        timer_.end(st_);
+      }
+    }
+    QSP_HIP(hipEventRecord(ev1_, st_));
+    QSP_HIP(hipEventSynchronize(ev1_));
+    float ms = 0.f;
+    QSP_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+    last_ms_ = ms;
+    restore_host(graph_.end);
+  }
+
+  void free_graph() {
+    for (auto& it : graph_.items)
+      if (it.exec) (void)hipGraphExecDestroy(it.exec);
+    graph_.items.clear();
+    graph_.valid = false;
+  }
+
+ public:
   // ---------------------------------------------------------------- adjoint
   // Device bytes of the checkpoints, the tape of one chunk and the reverse
   // work space for a record of n_slices slices with checkpoints every K.
@@ -1305,7 +1477,15 @@ class Box final : public BoxBase {
       }
       a.iters_out = iters_out;
       a.resid_out = resid_out;
-      timed(QSP_K_PUSH, [&] { launch_push<T>(geom_, lat_, a, kPushReal, ctr_, st_); });
+      const auto job = [this, a] { launch_push<T>(geom_, lat_, a, kPushReal, ctr_, st_); };
+      if (capturing_ && timer_.active(cursor_)) {
+        // the sampled launch runs between graph segments, under its events
+        end_segment();
+        graph_.items.push_back({nullptr, std::function<void()>(job), QSP_K_PUSH});
+        begin_segment();
+      } else {
+        timed(QSP_K_PUSH, job);
+      }
       pushes_ += lat_.np;
     } else {
       timed(QSP_K_OTHER, [&] {
@@ -1404,9 +1584,14 @@ class Box final : public BoxBase {
     return a;
   }
 
-  // brackets one launch with timer events when slice k is sampled
+  // brackets one launch with timer events when slice k is sampled; while a
+  // box is captured into graphs there are no events
   template <typename F>
   void timed(int cls, F&& launch) {
+    if (capturing_) {
+      launch();
+      return;
+    }
     const bool on = timer_.active(cursor_);
     if (on) timer_.begin(cls, st_);
     launch();
@@ -1464,6 +1649,11 @@ class Box final : public BoxBase {
   std::vector<double> amp_;
   double shift_ = 0.0;
   bool explicit_ = false;
+  bool graphs_ = true;            // replay whole boxes from HIP graphs
+  bool capturing_ = false;
+  hipStream_t cap_st_ = nullptr;  // capture stream
+  uint64_t launch_version_ = 0;
+  BoxGraph graph_;
   // explicit Bx/By solver: deposits chi, DJx, DJy and the Krylov vectors
   double* ex_dep_[3] = {nullptr, nullptr, nullptr};
   double *ex_x_ = nullptr, *ex_r_ = nullptr, *ex_q_ = nullptr;
