@@ -122,6 +122,46 @@ def standalone_solves(box, cfg, reps: int = 50) -> float:
     return 3 * reps / (time.perf_counter() - t0)
 
 
+# one time step of the paper's single-GPU table (Sec. VI, A100): 1024^2 x 1024
+# cells, 1 ppc, driver + witness macro-particle beams, seconds per step
+PAPER_A100_STEP_S = {"fp32_pc": 12.9, "fp64_pc": 16.6, "fp32_explicit": 20.6,
+                     "fp64_explicit": 23.8}
+
+
+def c3_leg() -> dict:
+    """Wall time of one full time step of the paper-scale box (1024^2 x 1024,
+    1 ppc, 2 x 2^21 beam macro-particles pushed in every slice), from the
+    beam sort to the last slice, for both precisions and both Bx/By solvers.
+    One untimed step first."""
+    import torch
+    import workloads as W
+    from paper_2109_10277_amd import qsp
+    cfg, beam = W.c3()
+    soa = torch.tensor(beam.soa(), device="cuda")
+    out = {"workload": "c3_paper_step_1024x1024x1024_1ppc_2x2^21_beam", "step_s": {},
+           "updates_per_s": {}, "paper_a100_step_s": PAPER_A100_STEP_S}
+    n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
+    for solver in ("pc", "explicit"):
+        c = W.BoxConfig(**{f: getattr(cfg, f) for f in cfg.__dataclass_fields__})
+        if solver == "explicit":
+            c.bxby_solver, c.pc_max_iter, c.pc_tol = "explicit", 6, 1e-5
+        for prec in ("fp32", "fp64"):
+            box = qsp.Box(c, prec)
+            box.set_beam_particles(soa.clone(), beam.dt)
+            box.init_plasma()
+            box.run_box()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            box.init_plasma()
+            box.run_box()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            box.close()
+            out["step_s"][f"{prec}_{solver}"] = dt
+            out["updates_per_s"][f"{prec}_{solver}"] = n_p * cfg.nzeta / dt
+    return out
+
+
 def adjoint_leg(name: str, precision: str, ckpt_every: int, reps: int = 2) -> dict:
     """Forward+backward / forward on the adjoint workloads.
 
@@ -269,6 +309,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the paper-scale time step (1024^2 x 1024 with beams)")
     ap.add_argument("--shape-order", type=int, default=1, choices=(0, 1, 2, 3),
                     help="transverse particle shape of the timed workload (1: linear)")
     ap.add_argument("--solver", default="pc", choices=("pc", "explicit"),
@@ -367,6 +409,8 @@ def main():
         out["adjoint"] = [adj]
         for K in filter(None, args.adjoint_c5.split(",")):
             out["adjoint"].append(adjoint_leg("c5", "fp32", int(K), reps=1))
+    if not args.no_c3:
+        out["c3_paper_step"] = c3_leg()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, beam, args.cpu_slices)
     print(json.dumps(out))
