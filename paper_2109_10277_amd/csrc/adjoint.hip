@@ -15,6 +15,7 @@
 // particles and floored 1+Psi are locally constant.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "push_tile.hpp"
 #include "shape.hpp"
 
 namespace qsp {
@@ -87,27 +88,6 @@ __device__ inline void interp(const T* __restrict__ F, const Axis<O, R>& X, cons
   }
 }
 
-// FP64 scatter of v S (weights in FP64 from the fraction) onto the interior
-// nodes: the transpose of the gather
-template <int O, typename R>
-__device__ inline void scatter(double* P, const Axis<O, R>& X, const Axis<O, R>& Y, int nx, int ny,
-                               double v) {
-  if (v == 0.0) return;
-  double sx[O + 1], sy[O + 1];
-  shape::weights<O>(static_cast<double>(X.d), sx);
-  shape::weights<O>(static_cast<double>(Y.d), sy);
-#pragma unroll
-  for (int b = 0; b <= O; ++b) {
-    const int j = Y.b + b;
-#pragma unroll
-    for (int a = 0; a <= O; ++a) {
-      const int i = X.b + a;
-      if (i >= 1 && i < nx && j >= 1 && j < ny)
-        gadd(P + static_cast<size_t>(j) * nx + i, v * (sx[a] * sy[b]));
-    }
-  }
-}
-
 template <typename T>
 __device__ inline bool inside_c(int c0, T t, int n) {
   const T fl = floor(t);
@@ -123,15 +103,15 @@ __device__ inline bool inside_c(int c0, T t, int n) {
 // f_k is consumed.  Trial: the adjoint of the trial state comes from the
 // trial-current adjoints (Jx~ = +lsb_y/2dz, Jy~ = -lsb_x/2dz) gathered at the
 // trial position and is added to lam_y.
-template <typename T, int MODE, int O>
-__global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushArgs<T> a) {
+template <typename T, int MODE, int O, typename Scatter>
+__device__ __forceinline__ void adj_push_one(const Geom& g, const Lattice& L,
+                                             const AdjPushArgs<T>& a, int I, int J,
+                                             Scatter&& scat) {
   const int64_t np = L.np;
-  const int64_t p = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (p >= np) return;
+  const int64_t p = static_cast<int64_t>(J) * L.nX + I;
   const T w = a.p.w[p];
   if (w == T(0)) return;
   const int nx = g.nx, ny = g.ny;
-  const int I = static_cast<int>(p % L.nX), J = static_cast<int>(p / L.nX);
   const int lpx = 31 - __clz(L.ppc_x), lpy = 31 - __clz(L.ppc_y);
   const int ci0 = I >> lpx, cj0 = J >> lpy;
   const T fx0 = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
@@ -248,7 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushA
   for (int c = 0; c < 6; ++c) {
     lam[0] += lg[c] * gx[c];
     lam[1] += lg[c] * gy[c];
-    scatter(a.lam_F[c], X, Y, nx, ny, static_cast<double>(lg[c]));
+    scat(c, X, Y, static_cast<double>(lg[c]));
   }
   if (MODE == 0) {
 #pragma unroll
@@ -256,6 +236,59 @@ __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushA
   } else {
 #pragma unroll
     for (int c = 0; c < 5; ++c) ly[c * np + p] += lam[c];
+  }
+}
+
+// One workgroup per lattice tile (the tiles of the forward push): the
+// transposed gathers of the six fields accumulate in FP64 LDS histograms of
+// the tile's cells plus a halo and reach the global planes with one atomic
+// per non-zero node; stencils outside the histogram go straight to global
+// atomics.
+template <typename T, int MODE, int O>
+__global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  double* tile = reinterpret_cast<double*>(smem_raw);
+  const push_detail::TileShape ts = push_detail::tile_shape(L, a.tile_rows, a.tile_halo);
+  const int ntile = ts.nw * ts.nh;
+  const int nx = g.nx, ny = g.ny;
+  for (int e = threadIdx.x; e < 6 * ntile; e += kBlock) tile[e] = 0.0;
+  __syncthreads();
+  const int I0 = blockIdx.x * ts.tx, J0 = blockIdx.y * ts.ty;
+  const int ox = (I0 >> ts.lpx) - ts.halo, oy = (J0 >> ts.lpy) - ts.halo;
+  auto scat = [&](int c, const Axis<O, T>& X, const Axis<O, T>& Y, double v) {
+    if (v == 0.0) return;
+    double sx[O + 1], sy[O + 1];
+    shape::weights<O>(static_cast<double>(X.d), sx);
+    shape::weights<O>(static_cast<double>(Y.d), sy);
+    const int li = X.b - ox, lj = Y.b - oy;
+    if (li >= 0 && li + O < ts.nw && lj >= 0 && lj + O < ts.nh) {
+      double* t = tile + c * ntile + lj * ts.nw + li;
+#pragma unroll
+      for (int qb = 0; qb <= O; ++qb)
+#pragma unroll
+        for (int qa = 0; qa <= O; ++qa) push_detail::lds_add(t + qb * ts.nw + qa, v * (sx[qa] * sy[qb]));
+    } else {
+#pragma unroll
+      for (int qb = 0; qb <= O; ++qb) {
+        const int j = Y.b + qb;
+#pragma unroll
+        for (int qa = 0; qa <= O; ++qa) {
+          const int i = X.b + qa;
+          if (i >= 1 && i < nx && j >= 1 && j < ny)
+            gadd(a.lam_F[c] + static_cast<size_t>(j) * nx + i, v * (sx[qa] * sy[qb]));
+        }
+      }
+    }
+  };
+  for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock)
+    adj_push_one<T, MODE, O>(g, L, a, I0 + e % ts.tx, J0 + e / ts.tx, scat);
+  __syncthreads();
+  for (int e = threadIdx.x; e < 6 * ntile; e += kBlock) {
+    const int c = e / ntile, l = e % ntile;
+    const int gi = ox + l % ts.nw, gj = oy + l / ts.nw;
+    if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
+    const double val = tile[e];
+    if (val != 0.0) gadd(a.lam_F[c] + static_cast<size_t>(gj) * nx + gi, val);
   }
 }
 
@@ -533,16 +566,21 @@ void with_adj_order(int order, F&& f) {
 template <typename T>
 void launch_adj_push(const Geom& g, const Lattice& L, const AdjPushArgs<T>& a, bool trial,
                      hipStream_t st) {
-  if (trial)
-    with_adj_order(g.order, [&](auto order) {
-      hipLaunchKernelGGL((k_adj_push<T, 1, decltype(order)::value>), gp(L.np), dim3(kBlock), 0,
-                         st, g, L, a);
-    });
-  else
-    with_adj_order(g.order, [&](auto order) {
-      hipLaunchKernelGGL((k_adj_push<T, 0, decltype(order)::value>), gp(L.np), dim3(kBlock), 0,
-                         st, g, L, a);
-    });
+  const push_detail::TileShape ts = push_detail::tile_shape(L, a.tile_rows, a.tile_halo);
+  const size_t lds = static_cast<size_t>(6) * ts.nw * ts.nh * sizeof(double);
+  if (lds > 160 * 1024) throw std::invalid_argument("adjoint push histogram exceeds the LDS");
+  const dim3 grid(L.nX / ts.tx, L.nY / ts.ty);
+  with_adj_order(g.order, [&](auto order) {
+    constexpr int O = decltype(order)::value;
+    const void* fn = trial ? reinterpret_cast<const void*>(&k_adj_push<T, 1, O>)
+                           : reinterpret_cast<const void*>(&k_adj_push<T, 0, O>);
+    if (lds > 65536)
+      QSP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    if (trial)
+      hipLaunchKernelGGL((k_adj_push<T, 1, O>), grid, dim3(kBlock), lds, st, g, L, a);
+    else
+      hipLaunchKernelGGL((k_adj_push<T, 0, O>), grid, dim3(kBlock), lds, st, g, L, a);
+  });
   QSP_LAUNCH_CHECK();
 }
 

@@ -300,6 +300,7 @@ struct AdjPushArgs {
   double* lam_F[6];         // scatter targets: Ex-By, Ey+Bx, Ez, Bx, By, Bz
   int k;
   double dzeta, hx, hy, psi_floor, inv2dz;
+  int tile_rows, tile_halo;   // lattice tiles of the forward push
 };
 
 template <typename T>

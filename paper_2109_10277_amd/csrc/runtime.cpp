@@ -1043,6 +1043,8 @@ class Box final : public BoxBase {
     pa.hy = geom_.hy;
     pa.psi_floor = cfg_.psi_floor;
     pa.inv2dz = 0.5 / cfg_.dzeta;
+    pa.tile_rows = tile_rows_;
+    pa.tile_halo = tile_halo_;
     // real push k -> k+1 (none after the last recorded slice)
     if (!last) {
       pa.f = {t.f[1], t.f[2], t.f[3], bxM, byM, t.f[4]};
