@@ -229,7 +229,7 @@ qsp_status qsp_set_beam_gaussian(qsp_ctx ctx, const double* amp, double sx,
  * in n0 k_p^-3).  The context copies the particles, stably sorted by their
  * nearest slice (NGP in zeta); particles outside the box in zeta are kept,
  * sorted last, and neither deposit nor move.  Each
- * slice deposits its beam particles (CIC transversely) before the field
+ * slice deposits its beam particles (with the configured transverse shape) before the field
  * solves and, once the slice's fields are final, advances them by one
  * time step dt (drift-kick-drift, Boris kick; dt = 0: no push).  n = 0
  * removes the particle beam.  Replaces any previous particle beam.  A beam

@@ -17,14 +17,19 @@ What it computes (HiPACE++, arXiv:2109.10277), in normalised units
 * the plasma pusher, Sec. III.B eqs. for d_zeta x_perp, d_zeta u_perp,
   d_zeta Psi and the Lorentz factor gamma(u_perp, Psi), for electrons
   (q = -1, M = m_e) with a fifth-order Adams-Bashforth step in zeta;
-* zeroth-order longitudinal, first-order (CIC) transverse deposition,
-  Sec. III.B ("current deposition");
+* deposition zeroth order in zeta with a transverse shape of order 0-3
+  (centred B-splines; order 1, CIC, by default), Sec. III.B, the ions
+  deposited from the electrons' rest lattice with the same shape;
 * Dirichlet fast Poisson solves by a type-I discrete sine transform plus
   finite-difference operators, Sec. III.B ("solving a transverse Poisson
   equation");
-* the Bx/By predictor-corrector, Sec. III.B ("predictor-corrector field
-  solver"), with the initial guess built from Bx/By of the two previous
-  slices (Sec. V.B, the list of per-cell quantities S_cell).
+* the Bx/By predictor-corrector, Sec. III.B, with the initial guess built
+  from Bx/By of the two previous slices (Sec. V.B, the list of per-cell
+  quantities S_cell), or the explicit Bx/By solver (Sec. III.B, second
+  option): d_zeta J_perp integrated along the pusher's orbits and the
+  resulting Helmholtz-like equation solved by a sparse factorisation;
+* beams: rigid Gaussian sources or macro-particles sorted by slice once per
+  time step and pushed once per slice, and the multi-time-step loop.
 
 Where the paper is silent, this file takes the readings listed beside each
 function (node-centred grid, centred differences, linear-extrapolation
@@ -180,21 +185,6 @@ def shape_weights(cfg, x, y):
         for i, wx in zip(ni, wi):
             nodes.append((i, j))
             wts.append(wx * wy)
-    return nodes, wts
-
-
-def cic_weights(cfg, x, y):
-    """Linear (CIC) shape: the particle in cell (i, j) with fractional
-    offsets (fx, fy) gives weights (1-fx)(1-fy), fx(1-fy), (1-fx)fy, fx*fy
-    to nodes (i,j), (i+1,j), (i,j+1), (i+1,j+1)."""
-    sx = (x - cfg.x_lo) / cfg.hx
-    sy = (y - cfg.y_lo) / cfg.hy
-    i = np.clip(np.floor(sx).astype(np.int64), 0, cfg.nx - 1)
-    j = np.clip(np.floor(sy).astype(np.int64), 0, cfg.ny - 1)
-    fx = sx - i
-    fy = sy - j
-    nodes = [(i, j), (i + 1, j), (i, j + 1), (i + 1, j + 1)]
-    wts = [(1 - fx) * (1 - fy), fx * (1 - fy), (1 - fx) * fy, fx * fy]
     return nodes, wts
 
 
