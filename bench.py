@@ -122,6 +122,47 @@ def standalone_solves(box, cfg, reps: int = 50) -> float:
     return 3 * reps / (time.perf_counter() - t0)
 
 
+ACC_FIELDS = ("psi", "exmby", "eypbx", "ez", "bx", "by", "bz", "rho_mjz", "jx", "jy", "jz")
+
+
+def fp32_vs_fp64(cfg, beam, every: int = 8) -> dict:
+    """Relative L2 difference of the FP32 box from the FP64 box, per field,
+    over interior nodes of every `every`-th slice: over all those slices
+    together and the largest and median per slice (slices where the FP64
+    field is non-zero).  Bz is measured against the norm of (Bx, By), which
+    it is second order small against for a round beam."""
+    import torch
+    from paper_2109_10277_amd import qsp
+    stacks = {}
+    n_stack = (cfg.nzeta + every - 1) // every
+    for prec in ("fp64", "fp32"):
+        with qsp.Box(cfg, prec) as box:
+            box.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
+            box.init_plasma()
+            st = {q: box.empty(q, n_stack) for q in ACC_FIELDS}
+            box.run_box(stack=st, stack_every=every)
+            torch.cuda.synchronize()
+        stacks[prec] = st
+    ref, got = stacks["fp64"], stacks["fp32"]
+
+    def norms(t):   # per-slice L2 norm over interior nodes
+        return torch.linalg.vector_norm(t[:, 1:-1, 1:-1].double(), dim=(1, 2))
+
+    bperp = torch.sqrt(norms(ref["bx"]) ** 2 + norms(ref["by"]) ** 2)
+    out = {}
+    for q in ACC_FIELDS:
+        d = norms(got[q].double() - ref[q])
+        den = bperp if q == "bz" else norms(ref[q])
+        ok = den > 0
+        per = (d[ok] / den[ok]).cpu()
+        box_rel = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(den))
+        out[q] = {"box": box_rel, "max_slice": float(per.max()) if per.numel() else 0.0,
+                  "median_slice": float(per.median()) if per.numel() else 0.0}
+    del stacks, ref, got
+    torch.cuda.empty_cache()
+    return {"slices_compared": n_stack, "every": every, "rel_l2": out}
+
+
 # one time step of the paper's single-GPU table (Sec. VI, A100): 1024^2 x 1024
 # cells, 1 ppc, driver + witness macro-particle beams, seconds per step
 PAPER_A100_STEP_S = {"fp32_pc": 12.9, "fp64_pc": 16.6, "fp32_explicit": 20.6,
@@ -309,6 +350,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the FP32-against-FP64 field comparison of the timed box")
     ap.add_argument("--no-c3", action="store_true",
                     help="skip the paper-scale time step (1024^2 x 1024 with beams)")
     ap.add_argument("--shape-order", type=int, default=1, choices=(0, 1, 2, 3),
@@ -327,9 +370,9 @@ def main():
                     help="comma-separated checkpoint intervals for the c5 adjoint leg")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the slice loop of one box is not "
-              "split across GPUs in this build (see DESIGN.md for how it would "
-              "shard); rerun with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: the slice loop of one box runs on a "
+              "single GPU and is not split across GPUs; rerun with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.copy_calibration:
@@ -403,6 +446,8 @@ def main():
         v64 = n_p * cfg.nzeta * max(1, args.steps // 2) / dt64
         out["fp64_value"] = v64
         out["fp32_over_fp64"] = value / v64
+        if not args.no_accuracy:
+            out["fp32_vs_fp64"] = fp32_vs_fp64(cfg, beam)
     if not args.no_adjoint:
         adj = adjoint_leg("c4", "fp32", 32)
         out["fwd_bwd_over_fwd"] = adj["fwd_bwd_over_fwd"]
