@@ -139,7 +139,9 @@ struct DepOut {
 
 // kExplicitDep: no push; deposit the explicit Bx/By solver's chi, DJx, DJy
 // (dep.ch[0..2]) from the slice-k state in the slice-k psi, Ez, Bz
-enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2, kExplicitDep = 3 };
+// kTrialLater: trial push of a later predictor-corrector iteration of the
+// slice, from the record the first trial push of the slice left (rec).
+enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2, kExplicitDep = 3, kTrialLater = 4 };
 
 template <typename T>
 struct PushArgs {
@@ -161,6 +163,11 @@ struct PushArgs {
   const double* pc_partial;
   int pc_nblk;
   int pc_iter;              // trial push: P-C iteration index within the slice
+  // trial record (5 planes of np): position at k+1 (x and y offsets), the
+  // momentum at k+1 without the Bx/By kick, -w/D at k+1 (0: no deposit).
+  // The first trial push of a slice writes it (if non-null), later ones
+  // read it.
+  T* rec;
 };
 
 template <typename T>

@@ -81,6 +81,51 @@ __device__ inline unsigned long long block_sum(unsigned int v, unsigned int* red
   return s;
 }
 
+// Deposit of one particle: nch values v at offset (xi, eta) from its
+// lattice cell origin (ci0 + fx0, cj0 + fy0) into the tile histogram, or
+// straight to the global planes when the stencil leaves the tile (counted
+// in nglob).
+template <typename T, int O, int nch>
+__device__ __forceinline__ void deposit_particle(const DepOut& dep, double* tile, const TileShape& ts,
+                                                 int ox, int oy, int nx, int ny, bool tiled, int ci0,
+                                                 int cj0, T fx0, T fy0, T xi, T eta,
+                                                 const double (&v)[4], unsigned int& nglob) {
+  const int ntile = ts.nw * ts.nh;
+  int bi, bj;
+  const T dx = shape::locate<O>(ci0, fx0 + xi, nx, bi);
+  const T dy = shape::locate<O>(cj0, fy0 + eta, ny, bj);
+  double sx[O + 1], sy[O + 1];
+  shape::weights<O>(static_cast<double>(dx), sx);
+  shape::weights<O>(static_cast<double>(dy), sy);
+  const int li = bi - ox, lj = bj - oy;
+  if (tiled && li >= 0 && li + O < ts.nw && lj >= 0 && lj + O < ts.nh) {
+    const int base = lj * ts.nw + li;
+#pragma unroll
+    for (int c = 0; c < nch; ++c) {
+      double* t = tile + c * ntile + base;
+#pragma unroll
+      for (int qb = 0; qb <= O; ++qb)
+#pragma unroll
+        for (int qa = 0; qa <= O; ++qa) lds_add(t + qb * ts.nw + qa, v[c] * (sx[qa] * sy[qb]));
+    }
+  } else {
+    if (tiled) ++nglob;
+#pragma unroll
+    for (int qb = 0; qb <= O; ++qb) {
+      const int gj = bj + qb;
+#pragma unroll
+      for (int qa = 0; qa <= O; ++qa) {
+        const int gi = bi + qa;
+        if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
+        const size_t o = static_cast<size_t>(gj) * nx + gi;
+        const double s = sx[qa] * sy[qb];
+#pragma unroll
+        for (int c = 0; c < nch; ++c) global_add(dep.ch[c] + o, v[c] * s);
+      }
+    }
+  }
+}
+
 // Gather, push and deposit of the particles of lattice tile (tbx, tby) by
 // one workgroup with the transverse shape of order O; `tile` is the
 // workgroup's LDS histogram (nch channels of tile_shape's nw x nh nodes).
@@ -91,7 +136,8 @@ template <typename T, int MODE, int O>
 __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const PushArgs<T>& a,
                                           DevCounters* ctr, int tbx, int tby, double* tile) {
   // channels: trial push Jx, Jy; otherwise rho - Jz, Jx, Jy, Jz
-  constexpr int nch = MODE == kPushTrial ? 2 : 4;
+  constexpr bool trial = MODE == kPushTrial || MODE == kTrialLater;
+  constexpr int nch = trial ? 2 : 4;
   __shared__ unsigned int red[kBlock / 64];
   const TileShape ts = tile_shape(L, a.tile_rows, a.tile_halo);
   const int ntile = ts.nw * ts.nh;
@@ -117,6 +163,56 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
   for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock) {
     const int I = I0 + e % ts.tx, J = J0 + e / ts.tx;
     const size_t p = static_cast<size_t>(J) * L.nX + I;
+    if constexpr (MODE == kTrialLater) {
+      // Between predictor-corrector iterations only Bx, By change, and
+      // they enter the push as a kick -dz b0 (By, -Bx) on the momentum:
+      // the new position, Psi and the rest of the momentum come from the
+      // slice's first trial push; Bx, By are gathered at the slice-k
+      // position as there.
+      const T* r = a.rec;
+      const T fac = r[4 * np + p];
+      const T xk = a.p.xi_x[p], ek = a.p.xi_y[p];
+      const T xn = r[p], en = r[np + p];
+      const T cx = r[2 * np + p], cy = r[3 * np + p];
+      const int ci0 = I >> ts.lpx, cj0 = J >> ts.lpy;
+      const T fx0 = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
+      const T fy0 = (T(2 * (J & (L.ppc_y - 1)) + 1)) / T(2 * L.ppc_y);
+      if (fac == T(0)) continue;
+      T bx, by;
+      if constexpr (O == 1) {
+        int ci, cj;
+        const T fx = shape::locate<1>(ci0, fx0 + xk, nx, ci);
+        const T fy = shape::locate<1>(cj0, fy0 + ek, ny, cj);
+        const T w00 = (T(1) - fx) * (T(1) - fy), w10 = fx * (T(1) - fy);
+        const T w01 = (T(1) - fx) * fy, w11 = fx * fy;
+        bx = gather(a.f.bx, ci, cj, w00, w10, w01, w11, nx, ny);
+        by = gather(a.f.by, ci, cj, w00, w10, w01, w11, nx, ny);
+      } else {
+        int bi, bj;
+        const T dx = shape::locate<O>(ci0, fx0 + xk, nx, bi);
+        const T dy = shape::locate<O>(cj0, fy0 + ek, ny, bj);
+        T wx[O + 1], wy[O + 1];
+        int ix[O + 1], iy[O + 1];
+        bool okx[O + 1], oky[O + 1];
+        shape::weights<O>(dx, wx);
+        shape::weights<O>(dy, wy);
+        shape::axis_nodes<O>(bi, nx, ix, okx);
+        shape::axis_nodes<O>(bj, ny, iy, oky);
+#pragma unroll
+        for (int q = 0; q <= O; ++q) {
+          wx[q] = okx[q] ? wx[q] : T(0);
+          wy[q] = oky[q] ? wy[q] : T(0);
+        }
+        bx = shape::interp<O>(a.f.bx, ix, iy, wx, wy, nx);
+        by = shape::interp<O>(a.f.by, ix, iy, wx, wy, nx);
+      }
+      const T kick = dz * b0;
+      const double v[4] = {static_cast<double>(fac * (cx - kick * by)),
+                           static_cast<double>(fac * (cy + kick * bx)), 0.0, 0.0};
+      deposit_particle<T, O, nch>(a.dep, tile, ts, ox, oy, nx, ny, tiled, ci0, cj0, fx0, fy0, xn,
+                                  en, v, nglob);
+      continue;
+    }
     // every load of the particle is issued before any decision on it
     const T w = a.p.w[p];
     T xi = a.p.xi_x[p], eta = a.p.xi_y[p];
@@ -180,13 +276,35 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
       T f[5];
       f[0] = -ux * id * inv_hx;
       f[1] = -uy * id * inv_hy;
-      f[2] = gam * id * e1 + by + bz * uy * id;
-      f[3] = gam * id * e2 - bx - bz * ux * id;
+      if constexpr (MODE == kPushTrial) {   // the Bx/By kick is added below
+        f[2] = gam * id * e1 + bz * uy * id;
+        f[3] = gam * id * e2 - bz * ux * id;
+      } else {
+        f[2] = gam * id * e1 + by + bz * uy * id;
+        f[3] = gam * id * e2 - bx - bz * ux * id;
+      }
       f[4] = (ux * e1 + uy * e2) * id - ez;
       T y[5] = {xi, eta, ux, uy, psi};
 #pragma unroll
       for (int c = 0; c < 5; ++c)
         y[c] = y[c] - dz * (b0 * f[c] + b1 * h[0][c] + b2 * h[1][c] + b3 * h[2][c] + b4 * h[3][c]);
+      if constexpr (MODE == kPushTrial) {
+        const T cx = y[2], cy = y[3];
+        const T kick = dz * b0;
+        y[2] = cx - kick * by;
+        y[3] = cy + kick * bx;
+        if (a.rec) {   // what the later iterations of this slice start from
+          const bool in_box = inside(ci0, fx0 + y[0], nx) && inside(cj0, fy0 + y[1], ny);
+          const T dn = T(1) + y[4];
+          const T idn = T(1) / (dn < floor_d ? floor_d : dn);
+          T* r = a.rec;
+          r[p] = y[0];
+          r[np + p] = y[1];
+          r[2 * np + p] = cx;
+          r[3 * np + p] = cy;
+          r[4 * np + p] = alive && in_box ? -w * idn : T(0);
+        }
+      }
       if (!alive) continue;
       if (!inside(ci0, fx0 + y[0], nx) || !inside(cj0, fy0 + y[1], ny)) {
         ++nabs;
@@ -229,39 +347,8 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
       v[2] = static_cast<double>(-w * uy * id);
       v[3] = static_cast<double>(-w * uz * id);
     }
-    int bi, bj;
-    const T dx = shape::locate<O>(ci0, fx0 + xi, nx, bi);
-    const T dy = shape::locate<O>(cj0, fy0 + eta, ny, bj);
-    double sx[O + 1], sy[O + 1];
-    shape::weights<O>(static_cast<double>(dx), sx);
-    shape::weights<O>(static_cast<double>(dy), sy);
-    const int li = bi - ox, lj = bj - oy;
-    if (tiled && li >= 0 && li + O < ts.nw && lj >= 0 && lj + O < ts.nh) {
-      const int base = lj * ts.nw + li;
-#pragma unroll
-      for (int c = 0; c < nch; ++c) {
-        double* t = tile + c * ntile + base;
-#pragma unroll
-        for (int qb = 0; qb <= O; ++qb)
-#pragma unroll
-          for (int qa = 0; qa <= O; ++qa) lds_add(t + qb * ts.nw + qa, v[c] * (sx[qa] * sy[qb]));
-      }
-    } else {
-      if (tiled) ++nglob;
-#pragma unroll
-      for (int qb = 0; qb <= O; ++qb) {
-        const int gj = bj + qb;
-#pragma unroll
-        for (int qa = 0; qa <= O; ++qa) {
-          const int gi = bi + qa;
-          if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
-          const size_t o = static_cast<size_t>(gj) * nx + gi;
-          const double s = sx[qa] * sy[qb];
-#pragma unroll
-          for (int c = 0; c < nch; ++c) global_add(a.dep.ch[c] + o, v[c] * s);
-        }
-      }
-    }
+    deposit_particle<T, O, nch>(a.dep, tile, ts, ox, oy, nx, ny, tiled, ci0, cj0, fx0, fy0, xi, eta,
+                                v, nglob);
   }
 
   if (tiled) {
@@ -281,7 +368,7 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
   if (threadIdx.x == 0) {
     if (tc) atomicAdd(&ctr->n_clamped, tc);
     if (MODE == kPushReal && ta) atomicAdd(&ctr->n_absorbed, ta);
-    if (MODE != kPushTrial && tg) atomicAdd(&ctr->n_dep_global, tg);
+    if (!trial && tg) atomicAdd(&ctr->n_dep_global, tg);
   }
 }
 

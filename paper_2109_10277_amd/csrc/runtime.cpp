@@ -86,6 +86,7 @@ int64_t device_bytes_needed(const qsp_config& c) {
   b += plane * ts * (5 + 6 + 8);                 // fields, B history, DST scratch
   b += plane * 8 * (3 * 5 + 2);                  // deposits, trial currents
   b += np * ts * (6 + 20);                       // particle SoA + history
+  if (c.bxby_solver != QSP_BXBY_EXPLICIT) b += np * ts * 5;   // trial record
   b += (c.nx + c.ny) * (3 * ts + 8 + 8) + 4096;  // tables, counters
   b += (c.nx + c.ny + 2) * 8;                    // ion profile
   if (c.bxby_solver == QSP_BXBY_EXPLICIT) b += plane * 8 * 13 + 4096;   // explicit solver
@@ -1234,6 +1235,7 @@ class Box final : public BoxBase {
       for (int c = 0; c < 5; ++c) dep_[d][c] = alloc<double>(pl);
     trial_[0] = alloc<double>(pl);
     trial_[1] = alloc<double>(pl);
+    if (!explicit_) trial_rec_ = alloc<T>(5 * static_cast<size_t>(lat_.np));
     const size_t np = static_cast<size_t>(lat_.np);
     p_.xi_x = alloc<T>(np);
     p_.xi_y = alloc<T>(np);
@@ -1414,6 +1416,7 @@ class Box final : public BoxBase {
     } else {
       {
         PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
+        a.rec = trial_rec_;
         a.pc_partial = partial_;
         a.pc_nblk = pc_partial_count(geom_);
         SrcBxBy<T> s{};
@@ -1444,7 +1447,10 @@ class Box final : public BoxBase {
         c.zero.n = pl;
         for (int m = 0; m < cfg_.pc_max_iter; ++m) {
           a.pc_iter = m;
-          timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, kPushTrial, ctr_, st_); });
+          // the first trial push of the slice leaves the record the later
+          // ones start from
+          const PushMode tm = m == 0 ? kPushTrial : kTrialLater;
+          timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, tm, ctr_, st_); });
           timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_bxby<T>(geom_, s, tx(), ctr_, st_); });
           timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
           PCArgs<T> pc{t2_, bxk, byk, partial_, cfg_.pc_tol,
@@ -1621,6 +1627,7 @@ class Box final : public BoxBase {
   T *t1_ = nullptr, *t2_ = nullptr;
   double* dep_[3][5] = {};
   double* trial_[2] = {};
+  T* trial_rec_ = nullptr;   // record of the slice's first trial push
   Particles<T> p_{};
   Cplx<T>* twx_ = nullptr;
   Cplx<T>* twy_ = nullptr;
