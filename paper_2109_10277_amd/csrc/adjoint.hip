@@ -161,6 +161,7 @@ __device__ __forceinline__ void adj_push_one(const Geom& g, const Lattice& L,
   T* lr = a.lam_ring;
   T lnew[5] = {0, 0, 0, 0, 0};
   T lf[5];
+  T lf_own[2] = {0, 0};   // trial: lf[2], lf[3] of this iteration's deposit alone
   if (MODE == 0) {
     // adjoint of the pushed state and of the history slot holding f_k
 #pragma unroll
@@ -195,6 +196,13 @@ __device__ __forceinline__ void adj_push_one(const Geom& g, const Lattice& L,
       lnew[3] = qn * tid * gjy;
       lnew[4] = tun ? (-qn * tux * tid * tid * gjx - qn * tuy * tid * tid * gjy) : T(0);
     }
+    // this iteration's own Bx, By terms use its own deposit adjoint only;
+    // the later iterations' sums join everything they share with it
+#pragma unroll
+    for (int c = 2; c < 4; ++c) lf_own[c - 2] = -dz * b[0] * lnew[c];
+    if (a.acc)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) lnew[c] += a.acc[c * np + p];
 #pragma unroll
     for (int c = 0; c < 5; ++c) lf[c] = -dz * b[0] * lnew[c];
   }
@@ -221,14 +229,18 @@ __device__ __forceinline__ void adj_push_one(const Geom& g, const Lattice& L,
   lg[0] = lf[2] * G + lf[4] * ux * id;
   lg[1] = lf[3] * G + lf[4] * uy * id;
   lg[2] = -lf[4];
-  lg[3] = -lf[3];
-  lg[4] = lf[2];
+  lg[3] = MODE == 0 ? -lf[3] : -lf_own[1];
+  lg[4] = MODE == 0 ? lf[2] : lf_own[0];
   lg[5] = lf[2] * uy * id - lf[3] * ux * id;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     lam[0] += lg[c] * gx[c];
     lam[1] += lg[c] * gy[c];
     scat(c, X, Y, static_cast<double>(lg[c]));
+  }
+  if (MODE == 1 && a.acc) {   // the later iterations' own Bx, By position terms
+    lam[0] += a.acc[5 * np + p];
+    lam[1] += a.acc[6 * np + p];
   }
   if (MODE == 0) {
 #pragma unroll
@@ -289,6 +301,130 @@ __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushA
     if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
     const double val = tile[e];
     if (val != 0.0) gadd(a.lam_F[c] + static_cast<size_t>(gj) * nx + gi, val);
+  }
+}
+
+// Transpose of a later predictor-corrector trial push (iteration m >= 1),
+// which the forward computes from the slice's trial record: the deposit of
+// Jx, Jy at the recorded position with u = u0 - dz b0 (By, -Bx)(x_k).  Its
+// Bx, By adjoints are scattered at the slice-k position (the B cotangent of
+// iteration m); the adjoints of the recorded quantities, which the first
+// trial push's transpose carries back to the state, history and E fields,
+// are summed per particle into acc (with the slice-k position terms of this
+// iteration's own Bx, By gradients).
+template <typename T, int O, typename Scatter>
+__device__ __forceinline__ void adj_trial_later_one(const Geom& g, const Lattice& L,
+                                                    const AdjPushArgs<T>& a, int I, int J,
+                                                    Scatter&& scat) {
+  const int64_t np = L.np;
+  const int64_t p = static_cast<int64_t>(J) * L.nX + I;
+  const T* r = a.rec;
+  T* acc = a.acc;
+  const bool store = a.acc_mode == 1;
+  const T fac = r[4 * np + p];
+  if (fac == T(0)) {   // dead, or absorbed by the step: nothing deposited
+    if (store)
+#pragma unroll
+      for (int c = 0; c < 7; ++c) acc[c * np + p] = T(0);
+    return;
+  }
+  const T w = a.p.w[p];
+  const T xk = a.p.xi_x[p], ek = a.p.xi_y[p];
+  const T xn = r[p], en = r[np + p], cx = r[2 * np + p], cy = r[3 * np + p];
+  const T psin = r[5 * np + p];
+  const int nx = g.nx, ny = g.ny;
+  const int lpx = 31 - __clz(L.ppc_x), lpy = 31 - __clz(L.ppc_y);
+  const int ci0 = I >> lpx, cj0 = J >> lpy;
+  const T fx0 = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
+  const T fy0 = (T(2 * (J & (L.ppc_y - 1)) + 1)) / T(2 * L.ppc_y);
+  const T floor_d = static_cast<T>(a.psi_floor);
+  const T dz = static_cast<T>(a.dzeta);
+  const T b0 = T(kAB5[0]);
+  // this iteration's Bx, By at the slice-k position, with gradients
+  const Axis<O, T> X = locate_axis<O>(ci0, fx0 + xk, nx);
+  const Axis<O, T> Y = locate_axis<O>(cj0, fy0 + ek, ny);
+  T bx, bx_x, bx_y, by, by_x, by_y;
+  interp(a.f.bx, X, Y, nx, bx, bx_x, bx_y);
+  interp(a.f.by, X, Y, nx, by, by_x, by_y);
+  const T kick = dz * b0;
+  const T tux = cx - kick * by, tuy = cy + kick * bx;
+  const T tdraw = T(1) + psin;
+  const bool tun = !(tdraw < floor_d);
+  const T tid = T(1) / (tun ? tdraw : floor_d);
+  const T qn = -w;
+  // deposit transpose of Jx~, Jy~ at the trial position
+  const Axis<O, T> TX = locate_axis<O>(ci0, fx0 + xn, nx);
+  const Axis<O, T> TY = locate_axis<O>(cj0, fy0 + en, ny);
+  T gjx, gjx_x, gjx_y, gjy, gjy_x, gjy_y;
+  interp(a.lsb_y, TX, TY, nx, gjx, gjx_x, gjx_y);
+  interp(a.lsb_x, TX, TY, nx, gjy, gjy_x, gjy_y);
+  const T s2 = static_cast<T>(a.inv2dz);
+  gjx *= s2; gjx_x *= s2; gjx_y *= s2;
+  gjy *= -s2; gjy_x *= -s2; gjy_y *= -s2;
+  const T vjx = qn * tux * tid, vjy = qn * tuy * tid;
+  T v[7];
+  v[0] = vjx * gjx_x + vjy * gjy_x;
+  v[1] = vjx * gjx_y + vjy * gjy_y;
+  v[2] = qn * tid * gjx;
+  v[3] = qn * tid * gjy;
+  v[4] = tun ? (-qn * tux * tid * tid * gjx - qn * tuy * tid * tid * gjy) : T(0);
+  // f_x carries +By, f_y -Bx, each times -dz b0 in the step
+  const T lgbx = dz * b0 * v[3], lgby = -dz * b0 * v[2];
+  scat(0, X, Y, static_cast<double>(lgbx));
+  scat(1, X, Y, static_cast<double>(lgby));
+  v[5] = lgbx * bx_x + lgby * by_x;
+  v[6] = lgbx * bx_y + lgby * by_y;
+#pragma unroll
+  for (int c = 0; c < 7; ++c) acc[c * np + p] = store ? v[c] : acc[c * np + p] + v[c];
+}
+
+// Tiles as in k_adj_push; two LDS histograms (Bx, By adjoints of the
+// iteration, lam_F[3] and lam_F[4]).
+template <typename T, int O>
+__global__ void __launch_bounds__(kBlock) k_adj_trial_later(Geom g, Lattice L, AdjPushArgs<T> a) {
+  extern __shared__ unsigned char smem_raw[];
+  double* tile = reinterpret_cast<double*>(smem_raw);
+  const push_detail::TileShape ts = push_detail::tile_shape(L, a.tile_rows, a.tile_halo);
+  const int ntile = ts.nw * ts.nh;
+  const int nx = g.nx, ny = g.ny;
+  for (int e = threadIdx.x; e < 2 * ntile; e += kBlock) tile[e] = 0.0;
+  __syncthreads();
+  const int I0 = blockIdx.x * ts.tx, J0 = blockIdx.y * ts.ty;
+  const int ox = (I0 >> ts.lpx) - ts.halo, oy = (J0 >> ts.lpy) - ts.halo;
+  auto scat = [&](int c, const Axis<O, T>& X, const Axis<O, T>& Y, double v) {
+    if (v == 0.0) return;
+    double sx[O + 1], sy[O + 1];
+    shape::weights<O>(static_cast<double>(X.d), sx);
+    shape::weights<O>(static_cast<double>(Y.d), sy);
+    const int li = X.b - ox, lj = Y.b - oy;
+    if (li >= 0 && li + O < ts.nw && lj >= 0 && lj + O < ts.nh) {
+      double* t = tile + c * ntile + lj * ts.nw + li;
+#pragma unroll
+      for (int qb = 0; qb <= O; ++qb)
+#pragma unroll
+        for (int qa = 0; qa <= O; ++qa) push_detail::lds_add(t + qb * ts.nw + qa, v * (sx[qa] * sy[qb]));
+    } else {
+#pragma unroll
+      for (int qb = 0; qb <= O; ++qb) {
+        const int j = Y.b + qb;
+#pragma unroll
+        for (int qa = 0; qa <= O; ++qa) {
+          const int i = X.b + qa;
+          if (i >= 1 && i < nx && j >= 1 && j < ny)
+            gadd(a.lam_F[3 + c] + static_cast<size_t>(j) * nx + i, v * (sx[qa] * sy[qb]));
+        }
+      }
+    }
+  };
+  for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock)
+    adj_trial_later_one<T, O>(g, L, a, I0 + e % ts.tx, J0 + e / ts.tx, scat);
+  __syncthreads();
+  for (int e = threadIdx.x; e < 2 * ntile; e += kBlock) {
+    const int c = e / ntile, l = e % ntile;
+    const int gi = ox + l % ts.nw, gj = oy + l / ts.nw;
+    if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
+    const double val = tile[e];
+    if (val != 0.0) gadd(a.lam_F[3 + c] + static_cast<size_t>(gj) * nx + gi, val);
   }
 }
 
@@ -585,6 +721,25 @@ void launch_adj_push(const Geom& g, const Lattice& L, const AdjPushArgs<T>& a, b
 }
 
 template <typename T>
+void launch_adj_trial_later(const Geom& g, const Lattice& L, const AdjPushArgs<T>& a,
+                            hipStream_t st) {
+  if (!a.rec || !a.acc || (a.acc_mode != 1 && a.acc_mode != 2))
+    throw std::invalid_argument("a later trial push transpose needs the record and the sums");
+  const push_detail::TileShape ts = push_detail::tile_shape(L, a.tile_rows, a.tile_halo);
+  const size_t lds = static_cast<size_t>(2) * ts.nw * ts.nh * sizeof(double);
+  if (lds > 160 * 1024) throw std::invalid_argument("adjoint push histogram exceeds the LDS");
+  const dim3 grid(L.nX / ts.tx, L.nY / ts.ty);
+  with_adj_order(g.order, [&](auto order) {
+    constexpr int O = decltype(order)::value;
+    if (lds > 65536)
+      QSP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_adj_trial_later<T, O>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    hipLaunchKernelGGL((k_adj_trial_later<T, O>), grid, dim3(kBlock), lds, st, g, L, a);
+  });
+  QSP_LAUNCH_CHECK();
+}
+
+template <typename T>
 void launch_adj_deposit(const Geom& g, const Lattice& L, const AdjDepArgs<T>& a, hipStream_t st) {
   with_adj_order(g.order, [&](auto order) {
     hipLaunchKernelGGL((k_adj_deposit<T, decltype(order)::value>), gp(L.np), dim3(kBlock), 0, st,
@@ -652,6 +807,8 @@ void launch_copy_planes(size_t n, int count, const CopyPlanes<T, U>& c, hipStrea
 #define QSP_INST(T)                                                                             \
   template void launch_adj_push<T>(const Geom&, const Lattice&, const AdjPushArgs<T>&, bool,    \
                                    hipStream_t);                                               \
+  template void launch_adj_trial_later<T>(const Geom&, const Lattice&, const AdjPushArgs<T>&,   \
+                                          hipStream_t);                                        \
   template void launch_adj_deposit<T>(const Geom&, const Lattice&, const AdjDepArgs<T>&,        \
                                       hipStream_t);                                            \
   template void launch_adj_seed<T>(const Geom&, const AdjSeedArgs<T>&, hipStream_t);            \

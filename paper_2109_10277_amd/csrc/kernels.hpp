@@ -163,10 +163,10 @@ struct PushArgs {
   const double* pc_partial;
   int pc_nblk;
   int pc_iter;              // trial push: P-C iteration index within the slice
-  // trial record (5 planes of np): position at k+1 (x and y offsets), the
-  // momentum at k+1 without the Bx/By kick, -w/D at k+1 (0: no deposit).
-  // The first trial push of a slice writes it (if non-null), later ones
-  // read it.
+  // trial record (6 planes of np): position at k+1 (x and y offsets), the
+  // momentum at k+1 without the Bx/By kick, -w/D at k+1 (0: no deposit),
+  // Psi at k+1.  The first trial push of a slice writes it (if non-null),
+  // later ones read it.
   T* rec;
 };
 
@@ -308,6 +308,14 @@ struct AdjPushArgs {
   int k;
   double dzeta, hx, hy, psi_floor, inv2dz;
   int tile_rows, tile_halo;   // lattice tiles of the forward push
+  // later predictor-corrector iterations: the slice's trial record and the
+  // per-particle sums [7][np] of their adjoints that the first iteration's
+  // transpose takes up (adjoints of the new x, y offsets, u_x, u_y, Psi and
+  // of the slice-k offsets through their own Bx, By); acc_mode 1 stores, 2
+  // adds (later iterations), 0 with acc set: the first iteration reads them
+  const T* rec;
+  T* acc;
+  int acc_mode;
 };
 
 template <typename T>
@@ -384,6 +392,8 @@ struct CopyPlanes {
 
 template <typename T>
 void launch_adj_push(const Geom&, const Lattice&, const AdjPushArgs<T>&, bool trial, hipStream_t);
+template <typename T>
+void launch_adj_trial_later(const Geom&, const Lattice&, const AdjPushArgs<T>&, hipStream_t);
 template <typename T>
 void launch_adj_deposit(const Geom&, const Lattice&, const AdjDepArgs<T>&, hipStream_t);
 template <typename T>

@@ -303,6 +303,7 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
           r[2 * np + p] = cx;
           r[3 * np + p] = cy;
           r[4 * np + p] = alive && in_box ? -w * idn : T(0);
+          r[5 * np + p] = y[4];
         }
       }
       if (!alive) continue;

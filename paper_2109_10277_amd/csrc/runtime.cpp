@@ -86,7 +86,7 @@ int64_t device_bytes_needed(const qsp_config& c) {
   b += plane * ts * (5 + 6 + 8);                 // fields, B history, DST scratch
   b += plane * 8 * (3 * 5 + 2);                  // deposits, trial currents
   b += np * ts * (6 + 20);                       // particle SoA + history
-  if (c.bxby_solver != QSP_BXBY_EXPLICIT) b += np * ts * 5;   // trial record
+  if (c.bxby_solver != QSP_BXBY_EXPLICIT) b += np * ts * 6;   // trial record
   b += (c.nx + c.ny) * (3 * ts + 8 + 8) + 4096;  // tables, counters
   b += (c.nx + c.ny + 2) * 8;                    // ion profile
   if (c.bxby_solver == QSP_BXBY_EXPLICIT) b += plane * 8 * 13 + 4096;   // explicit solver
@@ -171,6 +171,7 @@ struct TapeSlot {
   Particles<T> p;
   T* f[5];        // psi, Ex-By, Ey+Bx, Ez, Bz
   T* b;           // [pc_max_iter + 1][2][plane]
+  T* rec;         // the slice's trial record [6][np]
 };
 
 // Full slice state at the start of a chunk of slices.
@@ -722,8 +723,8 @@ class Box final : public BoxBase {
     const int64_t slots = std::min(K, n_slices);
     const int64_t part = 26 * np * ts;
     const int64_t ck = part + 2 * pl * 8 + 4 * pl * ts;
-    const int64_t slot = part + 5 * pl * ts + 2 * (cfg_.pc_max_iter + 1) * pl * ts;
-    const int64_t work = 25 * np * ts + 18 * pl * 8 + 4 * static_cast<int64_t>(cfg_.nzeta) + 1024;
+    const int64_t slot = part + 6 * np * ts + 5 * pl * ts + 2 * (cfg_.pc_max_iter + 1) * pl * ts;
+    const int64_t work = 32 * np * ts + 18 * pl * 8 + 4 * static_cast<int64_t>(cfg_.nzeta) + 1024;
     return nck * ck + slots * slot + work + 256 * (8 * (nck + slots) + 32);
   }
 
@@ -878,10 +879,12 @@ class Box final : public BoxBase {
         T* f = adj_alloc<T>(5 * pl);
         for (int q = 0; q < 5; ++q) ts.f[q] = f + q * pl;
         ts.b = adj_alloc<T>(2 * static_cast<size_t>(cfg_.pc_max_iter + 1) * pl);
+        ts.rec = adj_alloc<T>(6 * np);
         tape_.push_back(ts);
       }
       lam_y_ = adj_alloc<T>(5 * np);
       lam_ring_ = adj_alloc<T>(20 * np);
+      lam_acc_ = adj_alloc<T>(7 * np);
       double* w = adj_alloc<double>(18 * pl);
       for (int q = 0; q < 6; ++q) lam_f_[q] = w + q * pl;
       lam_psi_ = w + 6 * pl;
@@ -1052,9 +1055,12 @@ class Box final : public BoxBase {
       for (int c = 0; c < 6; ++c) pa.lam_F[c] = lam_f_[c];
       launch_adj_push<T>(geom_, lat_, pa, false, st_);
     }
-    // predictor-corrector iterations in reverse
+    // predictor-corrector iterations in reverse; those after the first
+    // transpose only what their own Bx, By change (the rest is summed per
+    // particle and taken up by the first iteration's transpose)
     const double* lbx = lam_f_[3];
     const double* lby = lam_f_[4];
+    pa.rec = t.rec;
     for (int m = M - 1; m >= 0; --m) {
       AdjSrcArgs<T> s{};
       s.count = 2;
@@ -1085,7 +1091,14 @@ class Box final : public BoxBase {
       pa.lam_F[3] = lam_b_[0];
       pa.lam_F[4] = lam_b_[1];
       pa.lam_F[5] = lam_f_[5];
-      launch_adj_push<T>(geom_, lat_, pa, true, st_);
+      pa.acc = M > 1 ? lam_acc_ : nullptr;
+      if (m > 0) {
+        pa.acc_mode = m == M - 1 ? 1 : 2;
+        launch_adj_trial_later<T>(geom_, lat_, pa, st_);
+      } else {
+        pa.acc_mode = 0;
+        launch_adj_push<T>(geom_, lat_, pa, true, st_);
+      }
       lbx = lam_b_[0];
       lby = lam_b_[1];
     }
@@ -1235,7 +1248,7 @@ class Box final : public BoxBase {
       for (int c = 0; c < 5; ++c) dep_[d][c] = alloc<double>(pl);
     trial_[0] = alloc<double>(pl);
     trial_[1] = alloc<double>(pl);
-    if (!explicit_) trial_rec_ = alloc<T>(5 * static_cast<size_t>(lat_.np));
+    if (!explicit_) trial_rec_ = alloc<T>(6 * static_cast<size_t>(lat_.np));
     const size_t np = static_cast<size_t>(lat_.np);
     p_.xi_x = alloc<T>(np);
     p_.xi_y = alloc<T>(np);
@@ -1416,7 +1429,8 @@ class Box final : public BoxBase {
     } else {
       {
         PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
-        a.rec = trial_rec_;
+        // taped slices keep their record for the reverse pass
+        a.rec = tape_slot_ ? tape_slot_->rec : trial_rec_;
         a.pc_partial = partial_;
         a.pc_nblk = pc_partial_count(geom_);
         SrcBxBy<T> s{};
@@ -1646,6 +1660,7 @@ class Box final : public BoxBase {
   int32_t* iters_dev_ = nullptr;
   std::vector<int32_t> iters_host_;
   T *lam_y_ = nullptr, *lam_ring_ = nullptr;
+  T* lam_acc_ = nullptr;   // later P-C iterations' adjoint sums [7][np]
   double* lam_f_[6] = {};
   double *lam_psi_ = nullptr, *lam_jz_ = nullptr;
   double* jp_[2] = {};
