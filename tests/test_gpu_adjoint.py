@@ -240,3 +240,39 @@ def test_adjoint_memory_cap():
         assert e.value.status == qsp.QSP_ERR_OUT_OF_MEMORY
         box.record(cfg.nzeta, 4)
         assert box.stats()["device_bytes"] <= 1_400_000
+
+
+@pytest.mark.parametrize("tol", [0.03, 0.0036])
+def test_adjoint_with_early_exit_matches_oracle(tol):
+    # predictor-corrector to a tolerance: the slices take different numbers
+    # of iterations (1-3 at 0.03, 2-4 at 0.0036; every recorded residual is
+    # at least a factor 1.4 from the tolerance), and the transpose follows
+    # the recorded counts
+    cfg, beam = W.small(n=32, nzeta=14, ppc=1, nb=0.9, sigma=0.8, pc_max_iter=4, pc_tol=tol,
+                        extent=5.0)
+    k_lo, k_hi = cfg.nzeta // 2, cfg.nzeta - 2
+    w = cotangents(cfg, k_lo, k_hi)
+    recs, tape = A.forward_with_tape(cfg, beam)
+    counts = [r["pc_iters"] for r in recs[:k_hi + 1]]
+    assert len(set(counts)) >= 3, counts
+
+    def cot(k):
+        if k < k_lo or k > k_hi:
+            return {}
+        return {q: w[k - k_lo, i] for i, q in enumerate(FIELDS)}
+    ga_o, gsx, gsy = A.adjoint_box(cfg, beam, tape, cot)
+    gs_o = np.array([gsx, gsy])
+    print(f"adjoint with early exit, tol {tol}, counts {counts}", flush=True)
+    with Q().Box(cfg, "fp64") as box:
+        box.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
+        box.init_plasma()
+        iters = torch.zeros(k_hi + 1, dtype=torch.int32, device="cuda")
+        box.record(k_hi + 1, 4, pc_iters=iters)
+        c = {q: torch.tensor(w[:, i], dtype=box.fdtype, device="cuda") for i, q in enumerate(FIELDS)}
+        ga, gs, _ = box.adjoint(k_lo, c)
+        torch.cuda.synchronize()
+        ga, gs = ga.cpu().numpy(), gs.cpu().numpy()
+    assert list(iters.cpu().numpy()) == counts
+    err = np.abs(ga - ga_o).max() / np.abs(ga_o).max()
+    assert err <= 1e-9, err
+    assert np.all(np.abs(gs - gs_o) <= 1e-9 * np.abs(gs_o)), (gs, gs_o)
