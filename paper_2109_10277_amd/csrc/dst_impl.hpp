@@ -642,11 +642,14 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
 
 }  // namespace dst_detail
 
-// rows per row-pass workgroup (even, at most ny, within 144 KiB of LDS)
+// rows per row-pass workgroup (even, at most ny, within 144 KiB of LDS).
+// Up to 512 columns one busy wave per workgroup (more, smaller workgroups
+// fill the chip; measured best from HIP graphs at 64^2 and 512^2), above
+// two (1024^2 and beyond).
 template <typename T>
 int row_rows(int nx, int ny) {
   const int per = nx >= 512 ? 1 : 512 / nx;
-  int r = 2 * per * dst_detail::pass_waves("QSP_ROW_WAVES", 2);
+  int r = 2 * per * dst_detail::pass_waves("QSP_ROW_WAVES", nx <= 512 ? 1 : 2);
   if (r > ny) r = ny;
   while (r > 2 && dst_detail::pass_lds<T>(r, nx) > 147456) r >>= 1;
   return r;
