@@ -380,12 +380,16 @@ inline size_t pass_lds(int rows, int n) {
          static_cast<size_t>(n) * sizeof(double);
 }
 
-// columns per column-pass workgroup (even, at most nx, within 64 KiB of LDS)
+// columns per column-pass workgroup (even, at most nx, within 64 KiB of LDS).
+// One busy wave (one column pair) per workgroup up to 512 rows; from 1024
+// rows two, whose four-column strips halve the strided row segments each
+// workgroup reads (measured from HIP graphs: 8 % off a 1024^2 time step in
+// FP32, no change in FP64 or at 512^2).
 template <typename T>
 inline int col_strip(int nx, int ny, int nfield) {
   (void)nfield;
   const int per = ny >= 512 ? 1 : 512 / ny;
-  int w = 2 * per * pass_waves("QSP_COL_WAVES", 1);
+  int w = 2 * per * pass_waves("QSP_COL_WAVES", ny >= 1024 ? 2 : 1);
   if (const char* e = std::getenv("QSP_COL_W")) {   // tuning override
     const int v = std::atoi(e);
     if (v >= 2 && (v & (v - 1)) == 0) w = v;
@@ -645,11 +649,12 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
 // rows per row-pass workgroup (even, at most ny, within 144 KiB of LDS).
 // Up to 512 columns one busy wave per workgroup (more, smaller workgroups
 // fill the chip; measured best from HIP graphs at 64^2 and 512^2), above
-// two (1024^2 and beyond).
+// two in FP32 and four in FP64 (measured at 1024^2).
 template <typename T>
 int row_rows(int nx, int ny) {
   const int per = nx >= 512 ? 1 : 512 / nx;
-  int r = 2 * per * dst_detail::pass_waves("QSP_ROW_WAVES", nx <= 512 ? 1 : 2);
+  const int waves = nx <= 512 ? 1 : (sizeof(T) == 8 ? 4 : 2);
+  int r = 2 * per * dst_detail::pass_waves("QSP_ROW_WAVES", waves);
   if (r > ny) r = ny;
   while (r > 2 && dst_detail::pass_lds<T>(r, nx) > 147456) r >>= 1;
   return r;
