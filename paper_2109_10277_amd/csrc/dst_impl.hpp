@@ -380,7 +380,7 @@ inline size_t pass_lds(int rows, int n) {
          static_cast<size_t>(n) * sizeof(double);
 }
 
-// columns per column-pass workgroup (even, at most nx, within 64 KiB of LDS).
+// columns per column-pass workgroup (even, at most nx, within 80 KiB of LDS).
 // One busy wave (one column pair) per workgroup up to 512 rows; from 1024
 // rows two, whose four-column strips halve the strided row segments each
 // workgroup reads (measured from HIP graphs: 8 % off a 1024^2 time step in
@@ -395,7 +395,7 @@ inline int col_strip(int nx, int ny, int nfield) {
     if (v >= 2 && (v & (v - 1)) == 0) w = v;
   }
   if (w > nx) w = nx;
-  while (w > 2 && pass_lds<T>(w, ny) > 65536) w >>= 1;
+  while (w > 2 && pass_lds<T>(w, ny) > 81920) w >>= 1;   // two workgroups per CU
   return w;
 }
 
