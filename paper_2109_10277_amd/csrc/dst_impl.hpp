@@ -381,15 +381,16 @@ inline size_t pass_lds(int rows, int n) {
 }
 
 // columns per column-pass workgroup (even, at most nx, within 80 KiB of LDS).
-// One busy wave (one column pair) per workgroup up to 512 rows; from 1024
-// rows two, whose four-column strips halve the strided row segments each
-// workgroup reads (measured from HIP graphs: 8 % off a 1024^2 time step in
-// FP32, no change in FP64 or at 512^2).
+// One busy wave (one column pair) per workgroup up to 512 rows (FP32) or
+// 256 rows (FP64); beyond, two, whose four-column strips halve the strided
+// row segments each workgroup reads (measured from HIP graphs: 8 % off a
+// 1024^2 time step in FP32, 2 % off the 512^2 box in FP64).
 template <typename T>
 inline int col_strip(int nx, int ny, int nfield) {
   (void)nfield;
   const int per = ny >= 512 ? 1 : 512 / ny;
-  int w = 2 * per * pass_waves("QSP_COL_WAVES", ny >= 1024 ? 2 : 1);
+  const int waves = ny >= (sizeof(T) == 8 ? 512 : 1024) ? 2 : 1;
+  int w = 2 * per * pass_waves("QSP_COL_WAVES", waves);
   if (const char* e = std::getenv("QSP_COL_W")) {   // tuning override
     const int v = std::atoi(e);
     if (v >= 2 && (v & (v - 1)) == 0) w = v;
