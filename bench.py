@@ -36,7 +36,7 @@ METRIC = "plasma particle-slice updates/s + DST solves/s; FP32 vs FP64; fwd+bwd/
 PUSH_TRAFFIC = {"sources": ["paper_2109_10277_amd/csrc/particles.hip",
                             "paper_2109_10277_amd/csrc/push_tile.hpp",
                             "paper_2109_10277_amd/csrc/shape.hpp"],
-                "sha256_prefix": "6e4ce64fa5360faa", "workload": "c2", "bytes": 64.23e6,
+                "sha256_prefix": "5d1424f6cf536825", "workload": "c2", "bytes": 64.24e6,
                 "summary": "profiles/hbm_traffic_c2_blowout_512x512x1024_fp32.md"}
 
 

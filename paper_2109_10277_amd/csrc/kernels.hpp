@@ -141,7 +141,11 @@ struct DepOut {
 // (dep.ch[0..2]) from the slice-k state in the slice-k psi, Ez, Bz
 // kTrialLater: trial push of a later predictor-corrector iteration of the
 // slice, from the record the first trial push of the slice left (rec).
-enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2, kExplicitDep = 3, kTrialLater = 4 };
+// kPushTrialTape: kPushTrial that also copies the slice-k particle state it
+// reads into `tape` (slices the reverse pass starts from); a kernel of its
+// own so that the untaped trial push keeps its register allocation.
+enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2, kExplicitDep = 3, kTrialLater = 4,
+                kPushTrialTape = 5 };
 
 template <typename T>
 struct PushArgs {
@@ -168,6 +172,9 @@ struct PushArgs {
   // Psi at k+1.  The first trial push of a slice writes it (if non-null),
   // later ones read it.
   T* rec;
+  // kPushTrialTape: copy of the slice-k particle state the push reads, 26
+  // planes of np in the order xi_x, xi_y, ux, uy, psi, w, hist[4][5]
+  T* tape;
 };
 
 template <typename T>

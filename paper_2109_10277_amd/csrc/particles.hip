@@ -18,7 +18,7 @@ template <typename T, int MODE, int O>
 __global__ void __launch_bounds__(kBlock)
 k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
   const bool first = blockIdx.x == 0 && blockIdx.y == 0;
-  if (MODE == kPushTrial || MODE == kTrialLater) {
+  if (MODE == kPushTrial || MODE == kPushTrialTape || MODE == kTrialLater) {
     if (ctr->pc_done) return;
     // convergence of the previous corrector solve of this slice
     if (a.pc_partial && a.pc_iter > 0 &&
@@ -40,6 +40,9 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
   if constexpr (MODE == kExplicitDep)
     push_detail::explicit_tile<T, O>(g, L, a, blockIdx.x, blockIdx.y,
                                      reinterpret_cast<double*>(smem_raw));
+  else if constexpr (MODE == kPushTrialTape)
+    push_tile<T, kPushTrial, O, true>(g, L, a, ctr, blockIdx.x, blockIdx.y,
+                                      reinterpret_cast<double*>(smem_raw));
   else
     push_tile<T, MODE, O>(g, L, a, ctr, blockIdx.x, blockIdx.y,
                           reinterpret_cast<double*>(smem_raw));
@@ -134,12 +137,15 @@ template <typename T>
 void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode mode,
                  DevCounters* ctr, hipStream_t st) {
   const TileShape ts = tile_shape(L, a.tile_rows, a.tile_halo);
-  const int nch = mode == kPushTrial || mode == kTrialLater ? 2 : (mode == kExplicitDep ? 3 : 4);
+  const bool trial = mode == kPushTrial || mode == kPushTrialTape || mode == kTrialLater;
+  const int nch = trial ? 2 : (mode == kExplicitDep ? 3 : 4);
   const size_t lds = a.tiled ? static_cast<size_t>(nch) * ts.nw * ts.nh * sizeof(double) : 0;
   if (lds > 160 * 1024) throw std::invalid_argument("push tile histogram exceeds the LDS");
   const dim3 grid(L.nX / ts.tx, L.nY / ts.ty);
   if (mode == kTrialLater && !a.rec)
     throw std::invalid_argument("a later trial push needs the first one's record");
+  if (mode == kPushTrialTape && !a.tape)
+    throw std::invalid_argument("a taped trial push needs the tape's particle planes");
   if (mode == kExplicitDep && g.order < 1)
     throw std::invalid_argument("the explicit Bx/By solver needs a shape order of 1, 2 or 3");
   auto run = [&](auto order) {
@@ -147,6 +153,8 @@ void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode
     constexpr int OE = O < 1 ? 1 : O;   // the explicit deposit has no order-0 form
     const void* fn = mode == kPushReal    ? reinterpret_cast<const void*>(&k_push<T, kPushReal, O>)
                      : mode == kPushTrial ? reinterpret_cast<const void*>(&k_push<T, kPushTrial, O>)
+                     : mode == kPushTrialTape
+                         ? reinterpret_cast<const void*>(&k_push<T, kPushTrialTape, O>)
                      : mode == kTrialLater
                          ? reinterpret_cast<const void*>(&k_push<T, kTrialLater, O>)
                      : mode == kExplicitDep
@@ -160,6 +168,10 @@ void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode
         break;
       case kPushTrial:
         hipLaunchKernelGGL((k_push<T, kPushTrial, O>), grid, dim3(kBlock), lds, st, g, L, a, ctr);
+        break;
+      case kPushTrialTape:
+        hipLaunchKernelGGL((k_push<T, kPushTrialTape, O>), grid, dim3(kBlock), lds, st, g, L, a,
+                           ctr);
         break;
       case kTrialLater:
         hipLaunchKernelGGL((k_push<T, kTrialLater, O>), grid, dim3(kBlock), lds, st, g, L, a, ctr);

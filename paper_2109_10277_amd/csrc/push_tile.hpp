@@ -132,7 +132,7 @@ __device__ __forceinline__ void deposit_particle(const DepOut& dep, double* tile
 // Safe to call repeatedly from one workgroup.  The linear shape keeps a
 // gather of its own (four weights, value selects at the upper edge), which
 // the compiler allocates in fewer registers than the generic stencil.
-template <typename T, int MODE, int O>
+template <typename T, int MODE, int O, bool TAPE = false>
 __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const PushArgs<T>& a,
                                           DevCounters* ctr, int tbx, int tby, double* tile) {
   // channels: trial push Jx, Jy; otherwise rho - Jz, Jx, Jy, Jz
@@ -230,6 +230,24 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
         h[1][c] = hist[(s2 * 5 + c) * np + p];
         h[2][c] = hist[(s3 * 5 + c) * np + p];
         h[3][c] = hist[(s4 * 5 + c) * np + p];
+      }
+      if constexpr (MODE == kPushTrial && TAPE) {
+        // the state the reverse pass of this slice starts from
+        T* t = a.tape;
+        t[p] = xi;
+        t[np + p] = eta;
+        t[2 * np + p] = ux;
+        t[3 * np + p] = uy;
+        t[4 * np + p] = psi;
+        t[5 * np + p] = w;
+        T* th = t + 6 * np;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          th[(s1 * 5 + c) * np + p] = h[0][c];
+          th[(s2 * 5 + c) * np + p] = h[1][c];
+          th[(s3 * 5 + c) * np + p] = h[2][c];
+          th[(s4 * 5 + c) * np + p] = h[3][c];
+        }
       }
       T e1, e2, ez, bx, by, bz;
       if constexpr (O == 1) {

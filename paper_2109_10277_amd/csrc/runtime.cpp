@@ -954,7 +954,7 @@ class Box final : public BoxBase {
   // of this slice reads
   void taped_step(OutCopy& oc, TapeSlot<T>* slot, double* resid_out) {
     const int k = cursor_;
-    if (slot) launch_copy_particles<T>(lat_, p_, slot->p, st_);
+    // the slice's first trial push copies the particle state into the slot
     tape_slot_ = slot;
     step(oc, iters_dev_ + k, resid_out);
     tape_slot_ = nullptr;
@@ -1431,6 +1431,9 @@ class Box final : public BoxBase {
         PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
         // taped slices keep their record for the reverse pass
         a.rec = tape_slot_ ? tape_slot_->rec : trial_rec_;
+        // a slot's particle arrays are one block of 26 planes (alloc_particles)
+        if (tape_slot_) a.tape = tape_slot_->p.xi_x;
+        const PushMode first_trial = tape_slot_ ? kPushTrialTape : kPushTrial;
         a.pc_partial = partial_;
         a.pc_nblk = pc_partial_count(geom_);
         SrcBxBy<T> s{};
@@ -1462,8 +1465,8 @@ class Box final : public BoxBase {
         for (int m = 0; m < cfg_.pc_max_iter; ++m) {
           a.pc_iter = m;
           // the first trial push of the slice leaves the record the later
-          // ones start from
-          const PushMode tm = m == 0 ? kPushTrial : kTrialLater;
+          // ones start from (and on a taped slice the slice-k particle state)
+          const PushMode tm = m == 0 ? first_trial : kTrialLater;
           timed(QSP_K_TRIAL, [&] { launch_push<T>(geom_, lat_, a, tm, ctr_, st_); });
           timed(QSP_K_ROW_FWD, [&] { launch_src_fwd_bxby<T>(geom_, s, tx(), ctr_, st_); });
           timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
