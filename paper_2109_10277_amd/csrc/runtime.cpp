@@ -954,7 +954,9 @@ class Box final : public BoxBase {
   // of this slice reads
   void taped_step(OutCopy& oc, TapeSlot<T>* slot, double* resid_out) {
     const int k = cursor_;
-    // the slice's first trial push copies the particle state into the slot
+    // the slice's first trial push copies the particle state into the slot,
+    // so a tape needs the predictor-corrector
+    if (slot && explicit_) throw std::logic_error("a taped slice needs the predictor-corrector");
     tape_slot_ = slot;
     step(oc, iters_dev_ + k, resid_out);
     tape_slot_ = nullptr;
