@@ -1,20 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark of the quasi-static PIC slice loop on one MI355X.
 
-One step = one full box of the per-slice loop (plasma reset to the lattice,
-then every slice: deposit, beam source, psi/Ez/Bz solves, Bx/By
-predictor-corrector, real push) on the blowout workload: 512 x 512 nodes
-over [-6, 6]^2, 1024 slices over 10 k_p^-1, 1 plasma electron per cell
-(262,144 particles), rigid Gaussian driver n_b/n0 = 10, sigma_r = 0.3,
-sigma_z = 1.41, predictor-corrector to 1e-4 (at most 5 iterations), FP32
-with FP64 deposition sums.  Inputs are synthetic and resident on the GPU
-before the timed region.
+Headline: one full time step of the paper-scale box (Sec. VI, the single-GPU
+table): 1024 x 1024 transverse cells over [-8, 8]^2 k_p^-1, 1024 slices over
+zeta in (-7, 5], 1 plasma electron per cell (1,048,576 particles), a driver
+(n_b/n0 = 5, sigma_r = 0.25, sigma_z = 1) and a witness (n_b/n0 = 20,
+sigma_r = 0.1, sigma_z = 0.2, 5 behind it) of 2^21 FP32 macro-particles
+each with seeded normal positions and gamma = 2000, pushed in every slice
+(dt = 6), Bx/By predictor-corrector to 1e-4 (at most 5 iterations), FP32
+particles and fields with FP64 deposition sums.  One step = re-sort the
+beam by slice, reset the plasma ahead of the box, compute every slice
+(deposit, beam deposit, psi/Ez/Bz solves, predictor-corrector, beam push,
+real plasma push).  Inputs are synthetic and resident on the GPU before the
+timed region; the beam evolves from step to step as in a run.
 
 Prints one JSON line: particle-slice updates/s (whole job), DST solves/s,
-the FP64 rate and FP32/FP64 ratio, the roofline of the dominant kernel (the
-fused gather + push + deposit, timed with HIP events on the library's stream
-inside the timed region) and the FP64 CPU oracle timed on a bounded sample
-of the same workload.
+the per-kernel-class device time, the roofline of the real push (the fused
+gather + push + deposit, the largest HBM stream; timed with HIP events on
+the library's stream inside the timed region) and the time-dominant kernel
+class, the FP64 CPU oracle on the first slices of the same box, and extra
+legs: FP64 and the explicit Bx/By solver on the same step, the 512^2
+blowout box (C2) and the 4-ppc box (C5) replayed from HIP graphs, the
+FP32-against-FP64 accuracy, and the adjoint (forward+backward / forward).
 """
 from __future__ import annotations
 
@@ -29,46 +36,53 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 METRIC = "plasma particle-slice updates/s + DST solves/s; FP32 vs FP64; fwd+bwd/fwd ratio"
+KCLASSES = ("push", "trial", "row_fwd", "col", "row_inv", "other")
 
-# HBM bytes per real-push launch at c2 FP32 from the FETCH_SIZE / WRITE_SIZE
-# counter runs (scaled by a 256 MiB copy), valid while the push kernel's
-# sources hash to this value
-PUSH_TRAFFIC = {"sources": ["paper_2109_10277_amd/csrc/particles.hip",
-                            "paper_2109_10277_amd/csrc/push_tile.hpp",
-                            "paper_2109_10277_amd/csrc/shape.hpp"],
-                "sha256_prefix": "5d1424f6cf536825", "workload": "c2", "bytes": 64.24e6,
-                "summary": "profiles/hbm_traffic_c2_blowout_512x512x1024_fp32.md"}
+# HBM bytes per real-push launch from the FETCH_SIZE / WRITE_SIZE counter
+# runs (each scaled by what the counter reads for a plain 256 MiB copy),
+# valid while the push kernel's sources hash to the recorded value
+PUSH_SOURCES = ["paper_2109_10277_amd/csrc/particles.hip",
+                "paper_2109_10277_amd/csrc/push_tile.hpp",
+                "paper_2109_10277_amd/csrc/shape.hpp"]
+PUSH_TRAFFIC = {
+    "c2": {"sha256_prefix": "5d1424f6cf536825", "bytes": 64.24e6,
+           "summary": "profiles/hbm_traffic_c2_blowout_512x512x1024_fp32.md"},
+    "c3": {"sha256_prefix": "", "bytes": None, "summary": ""},
+}
 
 
 def push_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in PUSH_TRAFFIC["sources"]:
+    for f in PUSH_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def push_traffic(workload_name: str):
+def push_traffic(key: str):
     """Counter-measured bytes per launch, or None once the kernel changed."""
-    if PUSH_TRAFFIC["bytes"] is None or not PUSH_TRAFFIC["sha256_prefix"]:
+    t = PUSH_TRAFFIC.get(key)
+    if not t or t["bytes"] is None or not t["sha256_prefix"]:
         return None
-    if not workload_name.startswith(PUSH_TRAFFIC["workload"] + "_"):
-        return None
-    return PUSH_TRAFFIC["bytes"] if push_source_hash().startswith(PUSH_TRAFFIC["sha256_prefix"]) else None
+    return t["bytes"] if push_source_hash().startswith(t["sha256_prefix"]) else None
 
 
 def workload(name: str):
+    """(config, beam, workload label, traffic key)."""
     import workloads as W
+    if name == "c3":
+        cfg, beam = W.c3()
+        return cfg, beam, "c3_paper_step_1024x1024x1024_1ppc_2x2^21_beam", "c3"
     if name == "c2":
         cfg, beam = W.c2()
-        return cfg, beam, "c2_blowout_512x512x1024_1ppc"
+        return cfg, beam, "c2_blowout_512x512x1024_1ppc", "c2"
     if name == "c1":
         cfg, beam = W.c1()
-        return cfg, beam, "c1_linear_64x64x64_1ppc"
+        return cfg, beam, "c1_linear_64x64x64_1ppc", "c1"
     if name == "c5fwd":
         cfg, beam = W.c5()
-        return cfg, beam, "c5_forward_1024x1024x1024_4ppc"
+        return cfg, beam, "c5_forward_1024x1024x1024_4ppc", "c5"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -82,12 +96,23 @@ def push_bytes(cfg, fsize: int) -> int:
     return n_p * (26 + 10) * fsize + 6 * plane * fsize + 4 * plane * 8
 
 
-def run_gpu(cfg, beam, precision: str, steps: int, warmup: int, timing_every: int):
-    import torch
+def make_box(cfg, beam, precision, soa=None):
     from paper_2109_10277_amd import qsp
     box = qsp.Box(cfg, precision)
-    box.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
-    # the sampling period is set before the warm-up so that the box graphs
+    if hasattr(beam, "amp"):
+        box.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
+    else:
+        box.set_beam_particles(soa.clone(), beam.dt)
+    return box
+
+
+def run_gpu(cfg, beam, precision: str, steps: int, warmup: int, timing_every: int, soa=None):
+    """Warm-up boxes, then `steps` timed boxes (each from the plasma reset;
+    a macro-particle beam is re-sorted by slice at the reset and pushed in
+    every slice).  Returns (box, seconds, per-box stats, kernel times)."""
+    import torch
+    box = make_box(cfg, beam, precision, soa)
+    # the sampling period is set before the warm-up so that box graphs
     # captured there are the ones the timed boxes replay
     box.set_timing(timing_every)
     for _ in range(warmup):
@@ -107,6 +132,25 @@ def run_gpu(cfg, beam, precision: str, steps: int, warmup: int, timing_every: in
     return box, (t1 - t0), stats, kt
 
 
+def graph_replayed(cfg, beam) -> bool:
+    """Boxes without a moving macro-particle beam are replayed from HIP
+    graphs, where only the real push is timed with events."""
+    return hasattr(beam, "amp") and os.environ.get("QSP_GRAPH", "1") != "0"
+
+
+def kernel_summary(kt, steps: int, every: int, graphs: bool) -> dict:
+    """Device ms per step by kernel class, scaled from the sampled slices;
+    None for the classes a graph replay does not time."""
+    out = {}
+    for c in KCLASSES:
+        ms, n = kt[c]
+        if graphs and c != "push":
+            out[c] = None
+        else:
+            out[c] = ms / steps * every if every else None
+    return out
+
+
 def standalone_solves(box, cfg, reps: int = 50) -> float:
     """Batched (3-field) Dirichlet solves per second through the C ABI."""
     import torch
@@ -122,6 +166,39 @@ def standalone_solves(box, cfg, reps: int = 50) -> float:
     return 3 * reps / (time.perf_counter() - t0)
 
 
+def note(msg: str) -> None:
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def leg(cfg, beam, label, key, precision, steps, warmup, every, soa=None, solves=False) -> dict:
+    """One timed workload: throughput, kernel classes and the real push's
+    event-timed roofline."""
+    note(f"{label} {precision}: {warmup} warm-up + {steps} timed boxes")
+    graphs = graph_replayed(cfg, beam)
+    box, dt, stats, kt = run_gpu(cfg, beam, precision, steps, warmup, every, soa)
+    n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
+    fsize = 4 if precision == "fp32" else 8
+    push_ms, push_n = kt["push"]
+    avg = push_ms / push_n if push_n else float("nan")
+    nbytes = push_bytes(cfg, fsize)
+    achieved = nbytes / (avg * 1e-3) / 1e9
+    out = {"workload": label, "precision": precision, "steps": steps,
+           "value": n_p * cfg.nzeta * steps / dt, "ms_per_step": dt / steps * 1e3,
+           "dst_solves_per_s": sum(s["dst_solves"] for s in stats) / dt,
+           "pc_iterations_per_slice": sum(s["pc_iterations"] for s in stats) / (cfg.nzeta * steps),
+           "n_clamped_per_step": sum(s["n_clamped"] for s in stats) / steps,
+           "graph_replay": graphs,
+           "kernel_ms_per_step": kernel_summary(kt, steps, every, graphs),
+           "push": {"achieved": achieved, "frac": achieved / HBM_PEAK_GBS,
+                    "bytes_per_launch": nbytes, "avg_launch_ms": avg, "launches_timed": push_n,
+                    "traffic": push_traffic(key) if precision == "fp32" else None}}
+    if solves:
+        out["dst_solves_per_s_standalone_batch3"] = standalone_solves(box, cfg)
+    box.close()
+    return out
+
+
 ACC_FIELDS = ("psi", "exmby", "eypbx", "ez", "bx", "by", "bz", "rho_mjz", "jx", "jy", "jz")
 
 
@@ -133,6 +210,7 @@ def fp32_vs_fp64(cfg, beam, every: int = 8) -> dict:
     it is second order small against for a round beam."""
     import torch
     from paper_2109_10277_amd import qsp
+    note("FP32 against FP64 fields")
     stacks = {}
     n_stack = (cfg.nzeta + every - 1) // every
     for prec in ("fp64", "fp32"):
@@ -169,41 +247,27 @@ PAPER_A100_STEP_S = {"fp32_pc": 12.9, "fp64_pc": 16.6, "fp32_explicit": 20.6,
                      "fp64_explicit": 23.8}
 
 
-def c3_leg() -> dict:
-    """Wall time of one full time step of the paper-scale box (1024^2 x 1024,
-    1 ppc, 2 x 2^21 beam macro-particles pushed in every slice), from the
-    beam sort to the last slice, for both precisions and both Bx/By solvers.
-    One untimed step first."""
-    import torch
+def c3_variants(cfg, beam, soa, steps: int) -> dict:
+    """Seconds per time step of the paper-scale box in both precisions and
+    with both Bx/By solvers (one untimed step first)."""
     import workloads as W
-    from paper_2109_10277_amd import qsp
-    cfg, beam = W.c3()
-    soa = torch.tensor(beam.soa(), device="cuda")
-    out = {"workload": "c3_paper_step_1024x1024x1024_1ppc_2x2^21_beam", "step_s": {},
-           "updates_per_s": {}, "paper_a100_step_s": PAPER_A100_STEP_S}
+    out = {"step_s": {}, "updates_per_s": {}, "paper_a100_step_s": PAPER_A100_STEP_S}
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     for solver in ("pc", "explicit"):
         c = W.BoxConfig(**{f: getattr(cfg, f) for f in cfg.__dataclass_fields__})
         if solver == "explicit":
             c.bxby_solver, c.pc_max_iter, c.pc_tol = "explicit", 6, 1e-5
         for prec in ("fp32", "fp64"):
-            box = qsp.Box(c, prec)
-            box.set_beam_particles(soa.clone(), beam.dt)
-            box.init_plasma()
-            box.run_box()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            box.init_plasma()
-            box.run_box()
-            torch.cuda.synchronize()
-            dt = time.perf_counter() - t0
+            note(f"paper-scale step {prec} {solver}")
+            box, dt, _, _ = run_gpu(c, beam, prec, steps, 1, 0, soa)
             box.close()
-            out["step_s"][f"{prec}_{solver}"] = dt
-            out["updates_per_s"][f"{prec}_{solver}"] = n_p * cfg.nzeta / dt
+            out["step_s"][f"{prec}_{solver}"] = dt / steps
+            out["updates_per_s"][f"{prec}_{solver}"] = n_p * cfg.nzeta * steps / dt
     return out
 
 
-def adjoint_leg(name: str, precision: str, ckpt_every: int, reps: int = 2) -> dict:
+def adjoint_leg(name: str, precision: str, ckpt_every: int, reps: int = 2,
+                fp64_check: bool = False) -> dict:
     """Forward+backward / forward on the adjoint workloads.
 
     c4: 256 x 256 nodes, 512 slices, 1 plasma electron per cell, loss = mean
@@ -211,24 +275,32 @@ def adjoint_leg(name: str, precision: str, ckpt_every: int, reps: int = 2) -> di
     two beam sizes.  c5: 1024 x 1024 nodes, 2 x 2 electrons per cell (4.19M),
     loss = witness-weighted Ez integral over the slices the witness covers.
     Forward = the plain slice loop over the same slices; forward+backward =
-    checkpointed record + reverse pass (with the per-chunk recompute)."""
+    checkpointed record + reverse pass (with the per-chunk recompute).
+    With fp64_check the gradient is also computed in FP64 and the FP32
+    gradient's largest deviation reported relative to its largest entry."""
+    import numpy as np
     import torch
     import workloads as W
     from paper_2109_10277_amd import qsp
-    box_dtype = torch.float32 if precision == "fp32" else torch.float64
-    if name == "c4":
-        cfg, beam = W.c4()
-        k_lo, k_hi = W.C4_LOSS_SLICES
-        n = k_hi + 1
-        wts = torch.zeros(n - k_lo, cfg.ny + 1, cfg.nx + 1, dtype=box_dtype, device="cuda")
-        wts[:, cfg.ny // 2, cfg.nx // 2] = 1.0 / (n - k_lo)
-    else:
-        cfg, beam = W.c5()
+
+    def weights(cfg, dtype):
+        if name == "c4":
+            k_lo, k_hi = W.C4_LOSS_SLICES
+            n = k_hi + 1
+            wts = torch.zeros(n - k_lo, cfg.ny + 1, cfg.nx + 1, dtype=dtype, device="cuda")
+            wts[:, cfg.ny // 2, cfg.nx // 2] = 1.0 / (n - k_lo)
+            return k_lo, n, wts
         k_lo, gz, gy, gx = W.witness_factors(cfg)
         n = k_lo + len(gz)
         dv = cfg.hx * cfg.hy * cfg.dzeta
         t = lambda a: torch.tensor(a, dtype=torch.float64, device="cuda")
-        wts = (t(gz * dv)[:, None, None] * t(gy)[None, :, None] * t(gx)[None, None, :]).to(box_dtype)
+        wts = (t(gz * dv)[:, None, None] * t(gy)[None, :, None] * t(gx)[None, None, :]).to(dtype)
+        return k_lo, n, wts
+
+    cfg, beam = W.c4() if name == "c4" else W.c5()
+    note(f"adjoint {name} {precision} K={ckpt_every}")
+    box_dtype = torch.float32 if precision == "fp32" else torch.float64
+    k_lo, n, wts = weights(cfg, box_dtype)
     box = qsp.Box(cfg, precision)
     box.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
     cot = {"ez": wts}
@@ -263,14 +335,29 @@ def adjoint_leg(name: str, precision: str, ckpt_every: int, reps: int = 2) -> di
         t_f, t_r, t_a = t_f + t1 - t0, t_r + t2 - t1, t_a + t3 - t2
     mem = box.stats()["device_bytes"]
     box.close()
-    return {"workload": f"{name}_{cfg.nx}x{cfg.ny}_{n}slices_{n_p}particles",
-            "precision": precision, "ckpt_every": ckpt_every,
-            "fwd_ms": t_f / reps * 1e3, "record_ms": t_r / reps * 1e3,
-            "reverse_ms": t_a / reps * 1e3,
-            "fwd_bwd_over_fwd": (t_r + t_a) / t_f,
-            "fwd_bwd_updates_per_s": n_p * n / ((t_r + t_a) / reps),
-            "device_bytes": mem, "loss": float(loss.cpu()[0]),
-            "grad_sigma": gs.cpu().tolist()}
+    out = {"workload": f"{name}_{cfg.nx}x{cfg.ny}_{n}slices_{n_p}particles",
+           "precision": precision, "ckpt_every": ckpt_every,
+           "fwd_ms": t_f / reps * 1e3, "record_ms": t_r / reps * 1e3,
+           "reverse_ms": t_a / reps * 1e3,
+           "fwd_bwd_over_fwd": (t_r + t_a) / t_f,
+           "fwd_bwd_updates_per_s": n_p * n / ((t_r + t_a) / reps),
+           "device_bytes": mem, "loss": float(loss.cpu()[0]),
+           "grad_sigma": gs.cpu().tolist()}
+    if fp64_check and precision == "fp32":
+        _, _, w64 = weights(cfg, torch.float64)
+        with qsp.Box(cfg, "fp64") as b64:
+            b64.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
+            b64.init_plasma()
+            b64.record(n, ckpt_every)
+            g64, s64, l64 = b64.adjoint(k_lo, {"ez": w64})
+            torch.cuda.synchronize()
+        g32, g64 = ga.cpu().numpy(), g64.cpu().numpy()
+        out["fp32_vs_fp64_grad"] = {
+            "amp_max_rel": float(np.abs(g32 - g64).max() / np.abs(g64).max()),
+            "sigma_rel": (np.abs(gs.cpu().numpy() - s64.cpu().numpy()) /
+                          np.abs(s64.cpu().numpy())).tolist(),
+            "loss_rel": abs(out["loss"] - float(l64.cpu()[0])) / abs(float(l64.cpu()[0]))}
+    return out
 
 
 def emittance_study(nsteps: int) -> dict:
@@ -278,14 +365,15 @@ def emittance_study(nsteps: int) -> dict:
     on a reduced reference setup (256^2 x 256 slices, driver + witness
     macro-particle beams, witness with zero initial emittance and a
     transverse centroid offset of one sigma_x).  Each time step runs the box
-    with a fresh plasma while the beams advance by dt = 6 in every slice."""
+    with a fresh plasma while the beams advance by dt = 6 in every slice.
+    A progress line goes to stderr every 50 steps."""
     import numpy as np
     import torch
     import workloads as W
     from paper_2109_10277_amd import qsp
     cfg, beam = W.emittance_study()
     w_wit = float(beam.w[-1])
-    every = max(1, nsteps // 20)
+    every = max(1, nsteps // 30)
     out = {}
     for prec in ("fp32", "fp64"):
         box = qsp.Box(cfg, prec)
@@ -300,7 +388,10 @@ def emittance_study(nsteps: int) -> dict:
                 x, ux = x - x.mean(), ux - ux.mean()
                 emit = torch.sqrt(torch.clamp((x * x).mean() * (ux * ux).mean() - (x * ux).mean() ** 2,
                                               min=0.0))
-                series.append((step, float(emit), float(b[0][m].mean())))
+                series.append((step, float(emit), float(b[0][m].mean()), int(m.sum())))
+            if step % 50 == 0:
+                print(f"emittance study {prec}: step {step}/{nsteps}, "
+                      f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
             if step < nsteps:
                 box.init_plasma()
                 box.run_box()
@@ -317,24 +408,29 @@ def emittance_study(nsteps: int) -> dict:
             "emittance_fp64": e64.tolist(), "emittance_fp32": e32.tolist(),
             "rel_error_fp32_final": float(rel[-1]), "rel_error_fp32_max_after_first": float(rel[1:].max()),
             "centroid_x_fp64": [s[2] for s in out["fp64"]["series"]],
+            "witness_particles_fp64": [s[3] for s in out["fp64"]["series"]],
+            "witness_particles_fp32": [s[3] for s in out["fp32"]["series"]],
             "seconds": {p: out[p]["seconds"] for p in out}}
 
 
 def cpu_baseline(cfg, beam, n_slices: int) -> dict:
     """The FP64 oracle on the host cores: the first n_slices slices of the
-    same box, from the unperturbed plasma."""
+    same box, from the unperturbed plasma (a macro-particle beam is
+    deposited and pushed in its slices as on the GPU)."""
+    import workloads as W
     from oracle import qsp_oracle as O
+    note(f"oracle on the first {n_slices} slices")
+    b = W.copy_beam(beam) if hasattr(beam, "zeta") else beam
     st = O.initial_state(cfg)
     c0, w0 = time.process_time(), time.perf_counter()
-    for _ in range(n_slices):
-        st, _ = O.advance_slice(cfg, st, beam)
+    _, st = O.run_box(cfg, b, keep=lambda k, r: None, state=st, k_end=n_slices)
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     return {"value": n_p * n_slices / wall, "unit": "particle-slice updates/s",
             "cores": max(1, round(cpu / wall)), "kind": "oracle",
             "sample": f"first {n_slices} of {cfg.nzeta} slices of the same box "
-                      f"({n_p} particles), FP64 NumPy/SciPy, {wall:.1f} s wall, "
+                      f"({n_p} plasma particles), FP64 NumPy/SciPy, {wall:.1f} s wall, "
                       f"{len(os.sched_getaffinity(0))} host cores visible"}
 
 
@@ -343,17 +439,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c1", "c5fwd"))
     ap.add_argument("--timing-every", type=int, default=4,
                     help="time the kernels of every n-th slice with HIP events")
-    ap.add_argument("--cpu-slices", type=int, default=60)
+    ap.add_argument("--cpu-slices", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (for profiler runs)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true",
-                    help="skip the FP32-against-FP64 field comparison of the timed box")
-    ap.add_argument("--no-c3", action="store_true",
-                    help="skip the paper-scale time step (1024^2 x 1024 with beams)")
+                    help="skip the FP32-against-FP64 field comparison (C2)")
     ap.add_argument("--shape-order", type=int, default=1, choices=(0, 1, 2, 3),
                     help="transverse particle shape of the timed workload (1: linear)")
     ap.add_argument("--solver", default="pc", choices=("pc", "explicit"),
@@ -375,8 +471,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import torch
     if args.copy_calibration:
-        import torch
         n = args.copy_calibration * (1 << 20) // 4
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
@@ -390,12 +486,13 @@ def main():
         print(json.dumps(emittance_study(args.emittance_study)))
         return
     if args.adjoint_only:
-        legs = [] if args.no_adjoint else [adjoint_leg("c4", "fp32", 32)]
+        legs = [] if args.no_adjoint else [adjoint_leg("c4", "fp32", 32, fp64_check=True)]
         legs += [adjoint_leg("c5", "fp32", int(K), reps=1)
                  for K in filter(None, args.adjoint_c5.split(","))]
         print(json.dumps({"adjoint": legs}))
         return
-    cfg, beam, wname = workload(args.workload)
+
+    cfg, beam, wname, key = workload(args.workload)
     if args.shape_order != 1:
         cfg.shape_order = args.shape_order
         wname += f"_order{args.shape_order}"
@@ -403,59 +500,69 @@ def main():
         cfg.bxby_solver = "explicit"
         cfg.pc_max_iter, cfg.pc_tol = 6, 1e-5
         wname += "_explicit"
+        key = ""
+    soa = None if hasattr(beam, "amp") else torch.tensor(beam.soa(), device="cuda")
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
-    box, dt, stats, kt = run_gpu(cfg, beam, "fp32", args.steps, args.warmup,
-                                 args.timing_every)
-    updates = n_p * cfg.nzeta * args.steps
-    value = updates / dt
-    solves = sum(s["dst_solves"] for s in stats)
-    dst_ms = sum(kt[c][0] for c in ("row_fwd", "col", "row_inv"))
-    push_ms, push_n = kt["push"]
-    push_avg_ms = push_ms / max(push_n, 1) if push_n else float("nan")
-    bytes_launch = push_bytes(cfg, 4)
-    achieved = bytes_launch / (push_avg_ms * 1e-3) / 1e9
-    standalone = standalone_solves(box, cfg)
-    box.close()
-
+    head = leg(cfg, beam, wname, key, "fp32", args.steps, args.warmup, args.timing_every, soa,
+               solves=True)
+    kms = head["kernel_ms_per_step"]
+    timed = {c: v for c, v in kms.items() if v is not None}
+    dominant = max(timed, key=timed.get) if timed else None
+    p = head["push"]
     out = {
-        "metric": METRIC, "value": value, "unit": "particle-slice updates/s",
+        "metric": METRIC, "value": head["value"], "unit": "particle-slice updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
+        "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wname, "nx": cfg.nx, "ny": cfg.ny,
                    "slices": cfg.nzeta, "particles": n_p,
+                   "beam_particles": None if soa is None else int(soa.shape[1]),
                    "bxby_iterations": f"<= {cfg.pc_max_iter}, tol {cfg.pc_tol}",
                    "shape_order": cfg.shape_order, "bxby_solver": cfg.bxby_solver,
                    "deposit_sums": "f64"},
-        "dst_solves_per_s": solves / dt,
-        "dst_solves_per_s_standalone_batch3": standalone,
-        "pc_iterations_per_slice": sum(s["pc_iterations"] for s in stats) / (cfg.nzeta * args.steps),
-        "kernel_ms_per_step": {c: kt[c][0] / args.steps * args.timing_every for c in kt},
-        "fwd_bwd_over_fwd": None,
-        "adjoint": None,
-        "roofline": {"bound": "hbm", "kernel": "gather+push+deposit (real push)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": push_traffic(wname),
-                     "bytes_per_launch": bytes_launch,
-                     "avg_launch_ms": push_avg_ms, "launches_timed": push_n},
+        "dst_solves_per_s": head["dst_solves_per_s"],
+        "dst_solves_per_s_standalone_batch3": head["dst_solves_per_s_standalone_batch3"],
+        "pc_iterations_per_slice": head["pc_iterations_per_slice"],
+        "kernel_ms_per_step": kms,
+        "kernel_timing": (f"device time of the launches of every {args.timing_every}-th slice "
+                          f"(HIP events on the library stream), scaled by {args.timing_every}; "
+                          "null: not timed (HIP graph replay times only the real push)"),
+        "time_dominant_kernel_class": None if dominant is None else {
+            "class": dominant, "ms_per_step": timed[dominant],
+            "share_of_step": timed[dominant] / head["ms_per_step"]},
+        "roofline": {"bound": "hbm", "kernel": "k_push real (gather + AB5 push + deposit)",
+                     "achieved": p["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": p["frac"], "traffic": p["traffic"],
+                     "bytes_per_launch": p["bytes_per_launch"],
+                     "avg_launch_ms": p["avg_launch_ms"], "launches_timed": p["launches_timed"]},
+        "fwd_bwd_over_fwd": None, "adjoint": None,
     }
-    if not args.no_fp64:
-        box64, dt64, _, _ = run_gpu(cfg, beam, "fp64", max(1, args.steps // 2), 1, 0)
-        box64.close()
-        v64 = n_p * cfg.nzeta * max(1, args.steps // 2) / dt64
-        out["fp64_value"] = v64
-        out["fp32_over_fp64"] = value / v64
+    if not args.no_extras:
+        extras = {}
+        if args.workload == "c3" and args.solver == "pc" and not args.no_fp64:
+            extras["c3_variants"] = c3_variants(cfg, beam, soa, 2)
+            out["fp64_value"] = extras["c3_variants"]["updates_per_s"]["fp64_pc"]
+            out["fp32_over_fp64"] = (extras["c3_variants"]["step_s"]["fp64_pc"] /
+                                     extras["c3_variants"]["step_s"]["fp32_pc"])
+        for wl in ("c2", "c5fwd"):
+            if wl == args.workload:
+                continue
+            c2cfg, c2beam, c2name, c2key = workload(wl)
+            extras[wl] = leg(c2cfg, c2beam, c2name, c2key, "fp32", 3 if wl == "c2" else 1, 1,
+                             args.timing_every)
+            if wl == "c2" and not args.no_fp64:
+                extras["c2_fp64"] = leg(c2cfg, c2beam, c2name, "", "fp64", 2, 1, 0)
         if not args.no_accuracy:
-            out["fp32_vs_fp64"] = fp32_vs_fp64(cfg, beam)
-    if not args.no_adjoint:
-        adj = adjoint_leg("c4", "fp32", 32)
-        out["fwd_bwd_over_fwd"] = adj["fwd_bwd_over_fwd"]
-        out["adjoint"] = [adj]
-        for K in filter(None, args.adjoint_c5.split(",")):
-            out["adjoint"].append(adjoint_leg("c5", "fp32", int(K), reps=1))
-    if not args.no_c3:
-        out["c3_paper_step"] = c3_leg()
+            c2cfg, c2beam, _, _ = workload("c2")
+            extras["c2_fp32_vs_fp64"] = fp32_vs_fp64(c2cfg, c2beam)
+        out["extras"] = extras
+        if not args.no_adjoint:
+            adj = adjoint_leg("c4", "fp32", 32, fp64_check=True)
+            out["fwd_bwd_over_fwd"] = adj["fwd_bwd_over_fwd"]
+            out["adjoint"] = [adj]
+            for K in filter(None, args.adjoint_c5.split(",")):
+                out["adjoint"].append(adjoint_leg("c5", "fp32", int(K), reps=1))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, beam, args.cpu_slices)
     print(json.dumps(out))

@@ -63,11 +63,21 @@ struct Lattice {
   int64_t np;
 };
 
-// Per-slice twiddle / transform tables of one axis (device pointers).
+// Sine transforms of FP32 rows of 256-1024 points use the recurrence-free
+// core (an FFT of the odd extension, twice the length); the others the
+// half-length transform with a prefix sum for the odd outputs.
+__host__ __device__ constexpr bool fast_core(int elem_size, int n) {
+  return elem_size == 4 && n >= 256 && n <= 1024;
+}
+
+// Per-axis transform tables (device pointers): for the half-length
+// transform tw[m] = e^{-2 pi i m / n} and pre[j] = sin(pi j / n); for the
+// FP32 core tw[k1 * 64 + l] = e^{-2 pi i l k1 / 2n} (2n entries) and pre
+// holds the complex table W_64^{la c1} at [la * 9 + c1].
 template <typename T>
 struct AxisTables {
-  const Cplx<T>* tw;     // e^{-2 pi i m / n}, m = 0..n-1
-  const T* pre;          // sin(pi j / n), j = 0..n-1
+  const Cplx<T>* tw;
+  const T* pre;
   const double* lam;     // Laplacian eigenvalue of sine mode p, p = 0..n-1 (0 unused)
 };
 

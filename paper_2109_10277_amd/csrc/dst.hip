@@ -19,10 +19,10 @@ k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int n = g.nx;
   const int R = g.rr;
-  const int ppitch = Pad<T>::pitch(n);
+  const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
-  stage_tables(tx, n, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
+  stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int j0 = blockIdx.x * R;
   const int fld = blockIdx.y;   // 0 psi, 1 Ez, 2 Bz
   const double ihx = 0.5 / g.hx, ihy = 0.5 / g.hy;
@@ -88,15 +88,15 @@ k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int n = g.nx;
   const int R = g.rr;
-  const int ppitch = Pad<T>::pitch(n);
+  const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
-  stage_tables(tx, n, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
+  stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int j0 = blockIdx.x * R;
   const int fld = blockIdx.y;
   const T* in = a.in[fld];
   const int lx = g.lx;
-  for_elems(R * n, [&](int e) {
+  for_elems<32>(R * n, [&](int e) {
     const int r = e >> lx, i = e & (n - 1);
     buf[Pad<T>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
   });
@@ -143,7 +143,7 @@ template <typename T>
 void launch_src_fwd_pez(const Geom& g, const SrcPEZ<T>& a, const AxisTables<T>& tx,
                         hipStream_t st) {
   const int R = g.rr;
-  const size_t lds = static_cast<size_t>(R / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
+  const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
     allow_lds(reinterpret_cast<const void*>(&k_src_fwd_pez<T, E>), lds);
@@ -156,7 +156,7 @@ template <typename T>
 void launch_src_fwd_bxby(const Geom& g, const SrcBxBy<T>& a, const AxisTables<T>& tx,
                          const DevCounters* ctr, hipStream_t st) {
   const int R = g.rr;
-  const size_t lds = static_cast<size_t>(R / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
+  const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
     allow_lds(reinterpret_cast<const void*>(&k_src_fwd_bxby<T, E>), lds);
@@ -172,8 +172,8 @@ void launch_col_solve(const Geom& g, const ColArgs<T>& a, int nfield, const Axis
   const int W = a.w;
   if (W < 2 || (W & (W - 1)) || g.nx % W || nfield < 1 || nfield > 4)
     throw std::invalid_argument("column pass: bad strip width or field count");
-  const size_t lds = static_cast<size_t>(W / 2) * Pad<T>::pitch(g.ny) * sizeof(T) + table_bytes<T>(g.ny) +
-                     static_cast<size_t>(g.ny) * sizeof(double);
+  const size_t lds = static_cast<size_t>(W / 2) * pair_pitch<T>(g.ny) * sizeof(T) + table_bytes<T>(g.ny) +
+                     static_cast<size_t>(g.ny + W) * sizeof(double);
   with_logn(g.ny, [&](auto e) {
     constexpr int E = decltype(e)::value;
     allow_lds(reinterpret_cast<const void*>(&k_col_solve<T, E>), lds);
@@ -187,7 +187,7 @@ template <typename T>
 void launch_row_inv(const Geom& g, const RowInvArgs<T>& a, int nfield, const AxisTables<T>& tx,
                     hipStream_t st) {
   const int R = g.rr;
-  const size_t lds = static_cast<size_t>(R / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
+  const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
     allow_lds(reinterpret_cast<const void*>(&k_row_inv<T, E>), lds);
@@ -200,7 +200,7 @@ template <typename T>
 void launch_row_inv_pc(const Geom& g, const PCArgs<T>& a, const AxisTables<T>& tx,
                        DevCounters* ctr, hipStream_t st) {
   const int R = g.rr;
-  const size_t lds = static_cast<size_t>(R / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
+  const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
     allow_lds(reinterpret_cast<const void*>(&k_row_inv_pc<T, E>), lds);

@@ -317,26 +317,199 @@ __device__ __forceinline__ void wave_dst(T* g, int npg, int ppitch, const Cplx<T
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// FP32 core for n = 256, 512, 1024 without a recurrence.  The odd outputs of
+// the half-length transform above come from a prefix sum, whose FP32
+// round-off grows like sqrt(n) and, through the centred differences taken of
+// the solved fields, reaches ~1e-4 of Ey+Bx at 512^2-1024^2.  Here the two
+// rows a, b of a pair are extended oddly to length N = 2n (z_j = a_j + i b_j,
+// z_{2n-j} = -z_j, z_0 = z_n = 0) and transformed by one complex FFT of
+// length N: with X = DFT_N(z), S^a_p = -Im X_p / 2 and S^b_p = Re X_p / 2.
+// Every output carries plain FFT round-off.
+//
+// One wave per pair, N = 64 P (P = 8, 16, 32 points per lane), as a 4-step
+// FFT with the index j = l + 64 m (lane l, register m) and k = k1 + P k2:
+//   A   each lane: DFT_P over m in registers, times W_N^{l k1};
+//   B1  DFT_64 over l split as 8 x 8 (l = la + 8 lb, k2 = c1 + 8 c2):
+//       DFT_8 over lb, times W_64^{la c1};
+//   B2  DFT_8 over la.
+// Two transposes through the pair's LDS region (rows of 72 complex per k1:
+// the transposes and the strided DFT_8 reads touch every bank once per two
+// rows), no workgroup barrier.
+// ---------------------------------------------------------------------------
+constexpr int kCorePitch = 72;   // complex entries per k1 row of the transposes
+
+// W_32^k = e^{-2 pi i k / 32} for k >= 0 (from cos(2 pi k / 32), k = 0..8;
+// W_32^{k+16} = -W_32^k).  Called with compile-time k only.
+__device__ __forceinline__ Cplx<float> w32(int k) {
+  constexpr double c32[9] = {1.0,
+                             0.98078528040323044913,
+                             0.92387953251128675613,
+                             0.83146961230254523708,
+                             0.70710678118654752440,
+                             0.55557023301960222474,
+                             0.38268343236508977173,
+                             0.19509032201612826785,
+                             0.0};
+  const double sg = (k & 16) ? -1.0 : 1.0;
+  k &= 15;
+  const double c = k <= 8 ? c32[k] : -c32[16 - k];
+  const double s = k <= 8 ? c32[8 - k] : c32[k - 8];
+  return {static_cast<float>(sg * c), static_cast<float>(-sg * s)};
+}
+
+// In-register forward DFT of length P = R1 * 8 (R1 = 1, 2, 4), in place with
+// j = j0 + 8 j1 and k = k0 + R1 k1: DFT_R1 over j1, twiddles W_P^{j0 k0},
+// DFT_8 over j0.  X_k ends at position dft_pos<P>(k) = 8 k0 + k1.
+template <int P>
+__host__ __device__ constexpr int dft_pos(int k) {
+  return 8 * (k % (P / 8)) + k / (P / 8);
+}
+
+template <int P>
+__device__ __forceinline__ void dft_reg(Cplx<float>* v) {
+  constexpr int R1 = P / 8;
+  if constexpr (R1 == 2) {
+#pragma unroll
+    for (int j0 = 0; j0 < 8; ++j0) {
+      const Cplx<float> a = v[j0], b = v[j0 + 8];
+      v[j0] = cadd(a, b);
+      v[j0 + 8] = csub(a, b);
+    }
+  } else if constexpr (R1 == 4) {
+#pragma unroll
+    for (int j0 = 0; j0 < 8; ++j0) dft4(v[j0], v[j0 + 8], v[j0 + 16], v[j0 + 24]);
+  }
+  if constexpr (R1 > 1) {
+#pragma unroll
+    for (int k0 = 1; k0 < R1; ++k0)
+#pragma unroll
+      for (int j0 = 1; j0 < 8; ++j0) v[8 * k0 + j0] = cmul(v[8 * k0 + j0], w32(j0 * k0 * (32 / P)));
+  }
+#pragma unroll
+  for (int k0 = 0; k0 < R1; ++k0) dft8(v + 8 * k0);
+}
+
+// DST-I of one pair (rows a at g, b at g + rlen(n), entry 0 = 0) by one
+// wave, in place; twa[k1 * 64 + l] = W_N^{l k1}, w64[la * 9 + c1] =
+// W_64^{la c1}.  The pair's region holds P rows of kCorePitch complex.
+template <int P>
+__device__ __forceinline__ void wave_dst_core(float* g, const Cplx<float>* __restrict__ twa,
+                                              const Cplx<float>* __restrict__ w64) {
+  using Pd = Pad<float>;
+  constexpr int n = 32 * P;
+  constexpr int NB = P / 8;
+  const int l = threadIdx.x & 63;
+  float* ra = g;
+  float* rb = g + Pd::rlen(n);
+  Cplx<float>* s = reinterpret_cast<Cplx<float>*>(g);
+  // A: z_{l + 64 m}; m >= P/2 from the mirror 2n - j = 64 (P - m) - l
+  Cplx<float> v[P];
+#pragma unroll
+  for (int m = 0; m < P / 2; ++m) {
+    const int j = Pd::ridx(l + 64 * m);
+    v[m] = {ra[j], rb[j]};
+  }
+#pragma unroll
+  for (int m = P / 2; m < P; ++m) {
+    const int jm = 64 * (P - m) - l;          // in [1, n], n only for l = 0, m = P/2
+    const int j = Pd::ridx(jm < n ? jm : 0);
+    const float fa = ra[j], fb = rb[j];
+    v[m] = {jm < n ? -fa : 0.f, jm < n ? -fb : 0.f};
+  }
+  wave_sync();
+  dft_reg<P>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) {
+    const Cplx<float> y = v[dft_pos<P>(k1)];
+    s[k1 * kCorePitch + l] = k1 ? cmul(y, twa[k1 * 64 + l]) : y;
+  }
+  wave_sync();
+  // B1: combos (k1, la) = (l >> 3 + 8 t, l & 7)
+  const int la = l & 7, kb = l >> 3;
+  Cplx<float> u[NB][8];
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    const Cplx<float>* r = s + (kb + 8 * t) * kCorePitch + la;
+#pragma unroll
+    for (int lb = 0; lb < 8; ++lb) u[t][lb] = r[8 * lb];
+  }
+  Cplx<float> wl[8];
+  wl[0] = {1.f, 0.f};
+#pragma unroll
+  for (int c1 = 1; c1 < 8; ++c1) wl[c1] = w64[la * 9 + c1];
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    dft8(u[t]);
+    Cplx<float>* r = s + (kb + 8 * t) * kCorePitch + la * 9;
+    r[0] = u[t][0];
+#pragma unroll
+    for (int c1 = 1; c1 < 8; ++c1) r[c1] = cmul(u[t][c1], wl[c1]);
+  }
+  wave_sync();
+  // B2: combos (k1, c1) = (l >> 3 + 8 t, l & 7); DFT_8 over la
+  const int c1 = l & 7;
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    const Cplx<float>* r = s + (kb + 8 * t) * kCorePitch + c1;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) u[t][a] = r[a * 9];
+  }
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < NB; ++t) {
+    dft8(u[t]);
+    const int k0 = kb + 8 * t + P * c1;       // k = k0 + 8 P c2, < n for c2 < 4
+#pragma unroll
+    for (int c2 = 0; c2 < 4; ++c2) {
+      const int k = k0 + 8 * P * c2;
+      const int j = Pd::ridx(k);
+      ra[j] = k ? -0.5f * u[t][c2].im : 0.f;
+      rb[j] = k ? 0.5f * u[t][c2].re : 0.f;
+    }
+  }
+  wave_sync();
+}
+
+// Floats per row pair in LDS: the two padded rows, or for the FP32 core the
+// P rows of its transposes.
+template <typename T>
+__host__ __device__ inline int pair_pitch(int n) {
+  if (fast_core(sizeof(T), n)) return (n / 32) * kCorePitch * 2 + 2;
+  return Pad<T>::pitch(n);
+}
+
 // Type-I sine transform of nrow rows (nrow even) of length n = 2^logn held
-// in LDS; pair f = rows (2f, 2f+1) occupies buf[f*ppitch .. f*ppitch + 2n)
-// (row 2f first).  Entry 0 of every input row must be 0; on output entry p
-// holds S_p (entry 0 = 0).  Groups of max(1, 512/n) pairs are handed to the
-// workgroup's waves in turn; ends with a workgroup barrier.
+// in LDS; pair f = rows (2f, 2f+1) occupies buf[f*ppitch ..) (row 2f first,
+// ppitch = pair_pitch(n)).  Entry 0 of every input row must be 0; on output
+// entry p holds S_p (entry 0 = 0).  FP32 rows of 256-1024 go to the
+// recurrence-free core, one pair per wave; otherwise groups of max(1, 512/n)
+// pairs are handed to the workgroup's waves in turn.  Ends with a workgroup
+// barrier.
 template <typename T, int LOGN>
 __device__ __forceinline__ void block_dst(T* buf, int logn, int nrow, int ppitch,
                                           const Cplx<T>* __restrict__ tw,
                                           const T* __restrict__ pre) {
   constexpr int n = 1 << LOGN;
-  constexpr int per = n >= 512 ? 1 : 512 / n;
-  constexpr int E = n <= 512 ? 8 : n / 64;
   (void)logn;
   const int npair = nrow >> 1;
-  const int ngroup = (npair + per - 1) / per;
   const int wave = threadIdx.x >> 6;
   const int nwave = blockDim.x >> 6;
-  for (int gi = wave; gi < ngroup; gi += nwave) {
-    const int npg = min(per, npair - gi * per);
-    wave_dst<T, E, LOGN>(buf + static_cast<size_t>(gi) * per * ppitch, npg, ppitch, tw, pre);
+  if constexpr (fast_core(sizeof(T), n)) {
+    // tw: W_N^{l k1} by [k1][lane]; pre: the W_64 table (complex)
+    const Cplx<float>* w64 = reinterpret_cast<const Cplx<float>*>(pre);
+    for (int f = wave; f < npair; f += nwave)
+      wave_dst_core<n / 32>(buf + static_cast<size_t>(f) * ppitch, tw, w64);
+  } else {
+    constexpr int per = n >= 512 ? 1 : 512 / n;
+    constexpr int E = n <= 512 ? 8 : n / 64;
+    const int ngroup = (npair + per - 1) / per;
+    for (int gi = wave; gi < ngroup; gi += nwave) {
+      const int npg = min(per, npair - gi * per);
+      wave_dst<T, E, LOGN>(buf + static_cast<size_t>(gi) * per * ppitch, npg, ppitch, tw, pre);
+    }
   }
   __syncthreads();
 }
@@ -358,8 +531,12 @@ void with_logn(int n, F&& f) {
   }
 }
 
+// Bytes of the per-axis tables a transform pass stages in LDS: twiddles and
+// pre-twiddles of the half-length transform, or for the FP32 core the
+// W_N^{l k1} table (2n complex) and the W_64 table (72 complex).
 template <typename T>
 __host__ __device__ inline size_t table_bytes(int n) {
+  if (fast_core(sizeof(T), n)) return static_cast<size_t>(2 * n + 72) * sizeof(Cplx<T>);
   return static_cast<size_t>(n) * (sizeof(Cplx<T>) + sizeof(T));
 }
 
@@ -376,8 +553,8 @@ inline int pass_waves(const char* env, int dflt) {
 
 template <typename T>
 inline size_t pass_lds(int rows, int n) {
-  return static_cast<size_t>(rows / 2) * Pad<T>::pitch(n) * sizeof(T) + table_bytes<T>(n) +
-         static_cast<size_t>(n) * sizeof(double);
+  return static_cast<size_t>(rows / 2) * pair_pitch<T>(n) * sizeof(T) + table_bytes<T>(n) +
+         static_cast<size_t>(n + rows) * sizeof(double);
 }
 
 // columns per column-pass workgroup (even, at most nx, within 80 KiB of LDS).
@@ -385,34 +562,89 @@ inline size_t pass_lds(int rows, int n) {
 // 256 rows (FP64); beyond, two, whose four-column strips halve the strided
 // row segments each workgroup reads (measured from HIP graphs: 8 % off a
 // 1024^2 time step in FP32, 2 % off the 512^2 box in FP64).
+// The FP32 core at 1024 rows: four busy waves (eight-column strips, 32-byte
+// row segments), one workgroup per CU.
 template <typename T>
 inline int col_strip(int nx, int ny, int nfield) {
   (void)nfield;
-  const int per = ny >= 512 ? 1 : 512 / ny;
-  const int waves = ny >= (sizeof(T) == 8 ? 512 : 1024) ? 2 : 1;
+  const bool core = fast_core(sizeof(T), ny);
+  const int per = ny >= 512 || core ? 1 : 512 / ny;
+  const int waves = core ? (ny >= 1024 ? 4 : 1) : (ny >= (sizeof(T) == 8 ? 512 : 1024) ? 2 : 1);
   int w = 2 * per * pass_waves("QSP_COL_WAVES", waves);
   if (const char* e = std::getenv("QSP_COL_W")) {   // tuning override
     const int v = std::atoi(e);
-    if (v >= 2 && (v & (v - 1)) == 0) w = v;
+    if (v >= 2 && v <= 64 && (v & (v - 1)) == 0) w = v;
   }
   if (w > nx) w = nx;
-  while (w > 2 && pass_lds<T>(w, ny) > 81920) w >>= 1;   // two workgroups per CU
+  const size_t cap = core && ny >= 1024 ? 163840 : 81920;   // one or two workgroups per CU
+  while (w > 2 && pass_lds<T>(w, ny) > cap) w >>= 1;
   return w;
 }
 
-// Copies an axis' twiddle and pre-twiddle tables into LDS right after the
-// workgroup's data region, so the FFT stages never wait on global memory.
-template <typename T>
-__device__ inline void stage_tables(const AxisTables<T>& t, int n, unsigned char* base,
+// Copies an axis' transform tables into LDS right after the workgroup's data
+// region, so the FFT stages never wait on global memory.  Every load of a
+// thread is issued before its first LDS store (one memory latency, not one
+// per loop trip).
+template <typename T, int LOGN>
+__device__ inline void stage_tables(const AxisTables<T>& t, unsigned char* base,
                                     const Cplx<T>*& tw, const T*& pre) {
+  constexpr int n = 1 << LOGN;
   Cplx<T>* stw = reinterpret_cast<Cplx<T>*>(base);
-  T* spre = reinterpret_cast<T*>(base + n * sizeof(Cplx<T>));
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    stw[i] = t.tw[i];
-    spre[i] = t.pre[i];
+  if constexpr (fast_core(sizeof(T), n)) {
+    // 2n entries W_N^{l k1} by [k1][lane], then 72 of W_64 (as complex);
+    // 2n is a multiple of the workgroup size here
+    constexpr int NT = 2 * n / kBlock;
+    static_assert(2 * n % kBlock == 0, "table staging assumes 2n divisible by kBlock");
+    Cplx<T>* sw = stw + 2 * n;
+    const Cplx<T>* gw = reinterpret_cast<const Cplx<T>*>(t.pre);
+    Cplx<T> v[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) v[u] = t.tw[threadIdx.x + u * kBlock];
+    const bool wt = threadIdx.x < 72;
+    const Cplx<T> w = gw[wt ? threadIdx.x : 0];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) stw[threadIdx.x + u * kBlock] = v[u];
+    if (wt) sw[threadIdx.x] = w;
+    tw = stw;
+    pre = reinterpret_cast<const T*>(sw);
+  } else {
+    T* spre = reinterpret_cast<T*>(base + n * sizeof(Cplx<T>));
+    if constexpr (n % kBlock == 0) {
+      constexpr int NT = n / kBlock;
+      Cplx<T> v[NT];
+      T q[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        v[u] = t.tw[threadIdx.x + u * kBlock];
+        q[u] = t.pre[threadIdx.x + u * kBlock];
+      }
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        stw[threadIdx.x + u * kBlock] = v[u];
+        spre[threadIdx.x + u * kBlock] = q[u];
+      }
+    } else if (threadIdx.x < n) {   // n < kBlock
+      stw[threadIdx.x] = t.tw[threadIdx.x];
+      spre[threadIdx.x] = t.pre[threadIdx.x];
+    }
+    tw = stw;
+    pre = spre;
   }
-  tw = stw;
-  pre = spre;
+}
+
+// dst[i] = src[i] for i < N, all of a thread's loads before its stores
+template <int N>
+__device__ inline void stage_doubles(double* dst, const double* __restrict__ src) {
+  if constexpr (N % kBlock == 0) {
+    constexpr int NT = N / kBlock;
+    double v[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) v[u] = src[threadIdx.x + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) dst[threadIdx.x + u * kBlock] = v[u];
+  } else if (threadIdx.x < N) {   // N < kBlock
+    dst[threadIdx.x] = src[threadIdx.x];
+  }
 }
 
 // clears the planes of z, workgroup `bid` of `nblk` taking every nblk-th
@@ -435,14 +667,28 @@ __device__ inline void guess_job(const GuessJob<T>& q, size_t n) {
     q.ctr->pc_iters = 0u;
     q.ctr->pc_resid = 0.0;
   }
-  for (size_t i = bid * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const T vx = T(2) * q.bx1[i] - q.bx2[i];
-    const T vy = T(2) * q.by1[i] - q.by2[i];
-    q.bx[i] = vx;
-    q.by[i] = vy;
-    if (q.tape_bx) {
-      q.tape_bx[i] = vx;
-      q.tape_by[i] = vy;
+  // rounds of 8 elements per thread with all their loads issued first
+  constexpr int U = 8;
+  for (size_t i0 = bid * blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+    T vx[U], vy[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = i0 + u * stride;
+      const size_t c = i < n ? i : 0;   // clamped: every load in bounds
+      vx[u] = T(2) * q.bx1[c] - q.bx2[c];
+      vy[u] = T(2) * q.by1[c] - q.by2[c];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t i = i0 + u * stride;
+      if (i < n) {
+        q.bx[i] = vx[u];
+        q.by[i] = vy[u];
+        if (q.tape_bx) {
+          q.tape_bx[i] = vx[u];
+          q.tape_by[i] = vy[u];
+        }
+      }
     }
   }
 }
@@ -460,15 +706,20 @@ __device__ inline int xcd_strip(int b, int nstrip) {
 // Workgroups per CU the transform kernels are compiled for: four (<= 128
 // VGPRs) while a lane holds at most 8 FP32 complex points, fewer for the
 // long FP64 transforms whose register arrays would otherwise spill.
+// The FP32 core holds P = 2n/64 complex points per lane: 1024 points run
+// one workgroup per CU (up to 512 registers per lane, VGPRs and AGPRs), 512
+// two, 256 four.
 constexpr int dst_blocks_per_cu(int logn, int tsize) {
+  if (fast_core(tsize, 1 << logn)) return logn >= 10 ? 1 : (logn == 9 ? 2 : 4);
   const int u = (logn <= 9 ? 8 : (1 << logn) / 64) * tsize / 4;
   return u <= 8 ? 4 : (u <= 16 ? 2 : 1);
 }
 
 // Calls f(e) for the workgroup's elements e = threadIdx.x + it*kBlock,
 // e < total.  The whole multiples of kBlock run as unrolled straight-line
-// chunks of up to 8, so with a branch-free f the global loads of a chunk are
-// in flight together instead of one load latency per element.
+// chunks of up to CH (8, 16 or 32), so with a branch-free f the global loads
+// of a chunk are in flight together instead of one load latency per element
+// (plain copies take 32, source assembly with several loads per element 8).
 template <int CH, typename F>
 __device__ __forceinline__ void elem_chunk(int& it, F& f) {
 #pragma unroll
@@ -476,10 +727,14 @@ __device__ __forceinline__ void elem_chunk(int& it, F& f) {
   it += CH;
 }
 
-template <typename F>
+template <int CH = 8, typename F>
 __device__ __forceinline__ void for_elems(int total, F&& f) {
   const int nit = total / kBlock;   // uniform across the workgroup
   int it = 0;
+  if constexpr (CH >= 32)
+    while (it + 32 <= nit) elem_chunk<32>(it, f);
+  if constexpr (CH >= 16)
+    while (it + 16 <= nit) elem_chunk<16>(it, f);
   while (it + 8 <= nit) elem_chunk<8>(it, f);
   if (nit & 4) elem_chunk<4>(it, f);
   if (nit & 2) elem_chunk<2>(it, f);
@@ -499,10 +754,10 @@ __device__ __forceinline__ void src_bxby_block(const Geom& g, const SrcBxBy<T>& 
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int n = g.nx;
   const int R = g.rr;
-  const int ppitch = Pad<T>::pitch(n);
+  const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
-  stage_tables(tx, n, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
+  stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int j0 = bxi * R;
   const double ihx = 0.5 / g.hx, ihy = 0.5 / g.hy;
   const double idz = 0.5 / a.dzeta;
@@ -555,18 +810,20 @@ __device__ __forceinline__ void col_block(const Geom& g, const ColArgs<T>& a,
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int ny = g.ny, nx = g.nx;
   const int W = a.w;
-  const int ppitch = Pad<T>::pitch(ny);
+  const int ppitch = pair_pitch<T>(ny);
   const int p0 = strip * W;
   unsigned char* tbase = smem_raw + static_cast<size_t>(W / 2) * ppitch * sizeof(T);
   const Cplx<T>* tw;
   const T* pre;
-  stage_tables(ty, ny, tbase, tw, pre);
+  stage_tables<T, LOGN>(ty, tbase, tw, pre);
   double* slam = reinterpret_cast<double*>(tbase + table_bytes<T>(ny));
-  for (int i = threadIdx.x; i < ny; i += blockDim.x) slam[i] = ty.lam[i];
+  stage_doubles<(1 << LOGN)>(slam, ty.lam);
+  double* slamx = slam + ny;   // the strip's x eigenvalues
+  if (static_cast<int>(threadIdx.x) < W) slamx[threadIdx.x] = lamx[strip * W + threadIdx.x];
   const size_t plane = static_cast<size_t>(nx) * ny;
   const T* in = a.in + fld * plane;
   const int lw = 31 - __clz(W), ly = g.ly;
-  for_elems(W * ny, [&](int e) {
+  for_elems<32>(W * ny, [&](int e) {
     const int c = e & (W - 1), j = e >> lw;
     buf[Pad<T>::rpos(ny, ppitch, c, j)] = in[j * nx + p0 + c];
   });
@@ -578,10 +835,11 @@ __device__ __forceinline__ void col_block(const Geom& g, const ColArgs<T>& a,
     const int c = e >> ly, q = e & (ny - 1);
     const int p = p0 + c;
     T* r = buf + Pad<T>::rpos(ny, ppitch, c, 0);
-    const double den = lamx[p] + slam[q] - shift;
     const int iq = Pad<T>::ridx(q);
-    const double v = static_cast<double>(r[iq]) * norm / den;
-    r[iq] = (p > 0 && q > 0) ? static_cast<T>(v) : T(0);
+    // the eigenvalue sum in FP64, the division in the field precision
+    const T den = static_cast<T>((slamx[c] + slam[q] - shift) / norm);
+    const T v = r[iq] / den;
+    r[iq] = (p > 0 && q > 0) ? v : T(0);
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.ly, W, ppitch, tw, pre);
@@ -613,14 +871,14 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int n = g.nx;
   const int R = g.rr;
-  const int ppitch = Pad<T>::pitch(n);
+  const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
-  stage_tables(tx, n, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
+  stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int j0 = bxi * R;
   const T* in = a.in + static_cast<size_t>(fld) * g.nx * g.ny;
   const int lx = g.lx;
-  for_elems(R * n, [&](int e) {
+  for_elems<32>(R * n, [&](int e) {
     const int r = e >> lx, i = e & (n - 1);
     buf[Pad<T>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
   });
@@ -629,7 +887,7 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
   T* b = fld == 0 ? a.bx : a.by;
   T* tp = fld == 0 ? a.tape_bx : a.tape_by;
   double dsum = 0.0, nsum = 0.0;
-  for_elems(R * n, [&](int e) {
+  for_elems<32>(R * n, [&](int e) {
     const int r = e >> lx, i = e & (n - 1);
     const int j = j0 + r;
     const T v = buf[Pad<T>::rpos(n, ppitch, r, i)];
@@ -650,11 +908,13 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
 // rows per row-pass workgroup (even, at most ny, within 144 KiB of LDS).
 // Up to 512 columns one busy wave per workgroup (more, smaller workgroups
 // fill the chip; measured best from HIP graphs at 64^2 and 512^2), above
-// two in FP32 and four in FP64 (measured at 1024^2).
+// two in FP32 with the half-length transform and four in FP64 (measured at
+// 1024^2), four with the FP32 core.
 template <typename T>
 int row_rows(int nx, int ny) {
-  const int per = nx >= 512 ? 1 : 512 / nx;
-  const int waves = nx <= 512 ? 1 : (sizeof(T) == 8 ? 4 : 2);
+  const bool core = fast_core(sizeof(T), nx);
+  const int per = nx >= 512 || core ? 1 : 512 / nx;
+  const int waves = nx <= 512 ? 1 : (sizeof(T) == 8 || core ? 4 : 2);
   int r = 2 * per * dst_detail::pass_waves("QSP_ROW_WAVES", waves);
   if (r > ny) r = ny;
   while (r > 2 && dst_detail::pass_lds<T>(r, nx) > 147456) r >>= 1;

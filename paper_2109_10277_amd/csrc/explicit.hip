@@ -66,10 +66,10 @@ k_expl_setup(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int n = g.nx, ny = g.ny;
   const int R = g.rr;
-  const int ppitch = Pad<T>::pitch(n);
+  const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
-  stage_tables(tx, n, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
+  stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int fld = blockIdx.y;
   const int j0 = blockIdx.x * R;
   const size_t plane = static_cast<size_t>(n) * ny;
@@ -161,16 +161,16 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   if (stop) return;
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  const int ppitch = Pad<T>::pitch(n);
+  const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
-  stage_tables(tx, n, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
+  stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int fld = blockIdx.y;
   const int j0 = blockIdx.x * R;
   const size_t plane = static_cast<size_t>(n) * ny;
   const T* in = a.col + fld * plane;
   const int lx = g.lx;
-  for_elems(R * n, [&](int e) {
+  for_elems<32>(R * n, [&](int e) {
     const int rw = e >> lx, i = e & (n - 1);
     buf[Pad<T>::rpos(n, ppitch, rw, i)] = in[(j0 + rw) * n + i];
   });
@@ -285,10 +285,10 @@ k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   }
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  const int ppitch = Pad<T>::pitch(n);
+  const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
-  stage_tables(tx, n, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
+  stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int j0 = blockIdx.x * R;
   const size_t plane = static_cast<size_t>(n) * ny;
   const double* p = a.p[it & 1] + fld * plane;
@@ -346,7 +346,7 @@ void allow_lds_e(const void* fn, size_t lds) {
 
 template <typename T>
 size_t row_lds(const Geom& g) {
-  return static_cast<size_t>(g.rr / 2) * Pad<T>::pitch(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
+  return static_cast<size_t>(g.rr / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
 }
 
 }  // namespace

@@ -1259,10 +1259,10 @@ class Box final : public BoxBase {
     p_.psi = alloc<T>(np);
     p_.w = alloc<T>(np);
     p_.hist = alloc<T>(20 * np);
-    twx_ = alloc<Cplx<T>>(cfg_.nx);
+    twx_ = alloc<Cplx<T>>(2 * cfg_.nx);
     prex_ = alloc<T>(cfg_.nx);
     lamx_ = alloc<double>(cfg_.nx);
-    twy_ = alloc<Cplx<T>>(cfg_.ny);
+    twy_ = alloc<Cplx<T>>(2 * cfg_.ny);
     prey_ = alloc<T>(cfg_.ny);
     lamy_ = alloc<double>(cfg_.ny);
     bgx_ = alloc<double>(cfg_.nx + 1);
@@ -1288,19 +1288,39 @@ class Box final : public BoxBase {
     if (cfg_.mem_cap_bytes > 0 && bytes_ > cfg_.mem_cap_bytes) throw std::bad_alloc();
   }
 
+  // Per-axis tables of the sine transform (tw holds 2n entries, pre n):
+  // the half-length transform's twiddles e^{-2 pi i m/n} and pre-twiddles
+  // sin(pi m/n), or for the FP32 core of 256-1024 points the twiddles
+  // W_2n^{l k1} at [k1 * 64 + l] and, in pre, the W_64^{la c1} table at
+  // [la * 9 + c1] (complex); and the Laplacian eigenvalues.
   void axis_tables(int n, double h, Cplx<T>* tw, T* pre, double* lam) {
-    std::vector<Cplx<T>> htw(n);
+    std::vector<Cplx<T>> htw(2 * n);
     std::vector<T> hpre(n);
     std::vector<double> hlam(n);
     const double pi = 3.14159265358979323846;
+    auto unit = [&](long q, long m) {   // e^{-2 pi i q / m}
+      const double a = -2.0 * pi * static_cast<double>(q % m) / static_cast<double>(m);
+      return Cplx<T>{static_cast<T>(std::cos(a)), static_cast<T>(std::sin(a))};
+    };
+    if (fast_core(sizeof(T), n)) {
+      const int P = 2 * n / 64;
+      for (int k1 = 0; k1 < P; ++k1)
+        for (int l = 0; l < 64; ++l) htw[k1 * 64 + l] = unit(static_cast<long>(l) * k1, 2 * n);
+      Cplx<T>* w = reinterpret_cast<Cplx<T>*>(hpre.data());
+      for (int i = 0; i < 72; ++i) w[i] = Cplx<T>{T(0), T(0)};
+      for (int la = 0; la < 8; ++la)
+        for (int c1 = 0; c1 < 8; ++c1) w[la * 9 + c1] = unit(la * c1, 64);
+    } else {
+      for (int m = 0; m < n; ++m) {
+        htw[m] = unit(m, n);
+        hpre[m] = static_cast<T>(std::sin(pi * m / n));
+      }
+    }
     for (int m = 0; m < n; ++m) {
-      htw[m].re = static_cast<T>(std::cos(-2.0 * pi * m / n));
-      htw[m].im = static_cast<T>(std::sin(-2.0 * pi * m / n));
-      hpre[m] = static_cast<T>(std::sin(pi * m / n));
       const double s = std::sin(pi * m / (2.0 * n));
       hlam[m] = -4.0 / (h * h) * s * s;
     }
-    QSP_HIP(hipMemcpy(tw, htw.data(), n * sizeof(Cplx<T>), hipMemcpyHostToDevice));
+    QSP_HIP(hipMemcpy(tw, htw.data(), 2 * n * sizeof(Cplx<T>), hipMemcpyHostToDevice));
     QSP_HIP(hipMemcpy(pre, hpre.data(), n * sizeof(T), hipMemcpyHostToDevice));
     QSP_HIP(hipMemcpy(lam, hlam.data(), n * sizeof(double), hipMemcpyHostToDevice));
   }

@@ -8,8 +8,11 @@ loudly otherwise - there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 from typing import Dict, Optional
 
 import numpy as np
@@ -190,6 +193,20 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+# Boxes still open are closed by an exit handler registered when the first
+# box is made, after torch has been imported: exit handlers run
+# last-registered first, so the contexts go before torch and the HIP runtime
+# are torn down, and none is destroyed from a late finaliser.
+_LIVE: "weakref.WeakSet[Box]" = weakref.WeakSet()
+_EXIT_HOOK = False
+_FINALIZING = sys.is_finalizing   # kept: module globals may be cleared at shutdown
+
+
+def _close_live_boxes():
+    for box in list(_LIVE):
+        box.close()
+
+
 class Box:
     """One simulation box on one GPU (a libqsp context).
 
@@ -215,14 +232,25 @@ class Box:
                               C.byref(h))
         _check(st, None)
         self._h = h
+        self.record_id = 0      # bumped by every record(); ties a backward to its forward
+        global _EXIT_HOOK
+        if not _EXIT_HOOK:
+            atexit.register(_close_live_boxes)
+            _EXIT_HOOK = True
+        _LIVE.add(self)
 
     # -- lifetime
     def close(self):
         if getattr(self, "_h", None):
             lib().qsp_destroy(self._h)
             self._h = None
+        _LIVE.discard(self)
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be finalised:
+        # leave the context to the process exit rather than call into it
+        if _FINALIZING is None or _FINALIZING():
+            return
         try:
             self.close()
         except Exception:
@@ -337,6 +365,7 @@ class Box:
         (outputs as in ``run_box``)."""
         bo = self._box_out(stack, stack_every, lineout, axis, pc_iters, pc_resid)
         st = Stats()
+        self.record_id += 1
         self._call("qsp_run_box_record", int(n_slices), int(ckpt_every), C.byref(bo),
                    C.byref(st))
         return st.as_dict()
@@ -431,7 +460,8 @@ def _wake_fn():
         (``Box.record``); returns [n_slices - k_lo, len(fields), ny+1, nx+1]
         in the box precision.  backward: ``Box.adjoint`` with the incoming
         gradient as cotangent.  One backward per forward (the record is
-        consumed)."""
+        consumed), before the box records anything else: a backward whose
+        forward's record has been replaced raises."""
 
         @staticmethod
         def forward(ctx, amp, sigma_x, sigma_y, box, n_slices, k_lo, fields, ckpt_every,
@@ -443,6 +473,7 @@ def _wake_fn():
             box.record(n_slices, ckpt_every, stack=stack)
             out = torch.stack([stack[q][k_lo:] for q in fields], dim=1)
             ctx.box, ctx.fields, ctx.k_lo = box, tuple(fields), k_lo
+            ctx.record_id = box.record_id
             ctx.amp_meta = (amp.dtype, amp.device)
             ctx.sig_meta = [(s.dtype, s.device) if torch.is_tensor(s) else None
                             for s in (sigma_x, sigma_y)]
@@ -450,6 +481,9 @@ def _wake_fn():
 
         @staticmethod
         def backward(ctx, g):
+            if ctx.box.record_id != ctx.record_id:
+                raise RuntimeError("wake_fields backward: the box has recorded another forward "
+                                   "pass since this one; its gradient is no longer available")
             cot = {q: g[:, i].contiguous().to(ctx.box.fdtype) for i, q in enumerate(ctx.fields)}
             ga, gs, _ = ctx.box.adjoint(ctx.k_lo, cot)
             dt, dev = ctx.amp_meta

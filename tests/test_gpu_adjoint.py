@@ -39,7 +39,20 @@ def rect_case():
     return cfg, beam
 
 
+def wide_case():
+    """256 x 32 lattice sites (128 x 32 cells, 2 x 1 per cell): four push
+    tiles across x, so the reverse pass's tile transposes meet tile edges
+    and their halo flush in x, with a driver strong enough to move the
+    plasma across them."""
+    cfg = W.BoxConfig(nx=128, ny=32, x_lo=-6.0, x_hi=6.0, y_lo=-3.0, y_hi=3.0,
+                      nzeta=12, zeta_hi=0.0, dzeta=4.0 / 12, ppc_x=2, ppc_y=1,
+                      pc_max_iter=2, pc_tol=0.0)
+    beam = W.GaussianBeam(W.gaussian_envelope(cfg, 1.5, -1.0, 0.7), 0.6, 0.5)
+    return cfg, beam
+
+
 CASES = {
+    "wide128x32_ppc2x1": wide_case,
     "n32_ppc1": lambda: W.small(n=32, nzeta=14, ppc=1, nb=0.9, sigma=0.8, pc_max_iter=3,
                                 pc_tol=0.0, extent=5.0),
     "n16_ppc2": lambda: W.small(n=16, nzeta=12, ppc=2, nb=1.5, sigma=0.9, pc_max_iter=2,
@@ -276,3 +289,73 @@ def test_adjoint_with_early_exit_matches_oracle(tol):
     err = np.abs(ga - ga_o).max() / np.abs(ga_o).max()
     assert err <= 1e-9, err
     assert np.all(np.abs(gs - gs_o) <= 1e-9 * np.abs(gs_o)), (gs, gs_o)
+
+
+def c4_axis_loss(box, cfg, amp, sx, sy, n_loss):
+    """C4 loss (mean on-axis Ez over slices k_lo..k_hi) of one forward box."""
+    k_lo, k_hi = W.C4_LOSS_SLICES
+    box.set_beam_gaussian(amp, sx, sy)
+    box.init_plasma()
+    ax = torch.zeros(cfg.nzeta, dtype=box.fdtype, device="cuda")
+    box.run_box(axis={"ez": ax})
+    torch.cuda.synchronize()
+    return float(ax[k_lo:k_hi + 1].double().mean())
+
+
+def c4_gradient(box, cfg, beam, ckpt_every=32):
+    k_lo, k_hi = W.C4_LOSS_SLICES
+    n = k_hi + 1
+    w = torch.zeros(n - k_lo, cfg.ny + 1, cfg.nx + 1, dtype=box.fdtype, device="cuda")
+    w[:, cfg.ny // 2, cfg.nx // 2] = 1.0 / (n - k_lo)
+    box.set_beam_gaussian(beam.amp, beam.sigma_x, beam.sigma_y)
+    box.init_plasma()
+    box.record(n, ckpt_every)
+    ga, gs, loss = box.adjoint(k_lo, {"ez": w})
+    torch.cuda.synchronize()
+    return ga.cpu().numpy(), gs.cpu().numpy(), float(loss.cpu()[0])
+
+
+def test_c4_gradient_matches_central_differences():
+    # the C4 workload at its own size: 256^2 nodes, the loss over slices
+    # 400-420, checkpoints every 32 slices; FP64 central differences with
+    # h = 1e-6 for sigma_r (sigma_x = sigma_y move together) and for
+    # amplitudes ahead of, inside and behind the loss window
+    cfg, beam = W.c4()
+    print("c4 gradient vs central differences", flush=True)
+    with Q().Box(cfg, "fp64") as box:
+        ga, gs, L = c4_gradient(box, cfg, beam)
+        L0 = c4_axis_loss(box, cfg, beam.amp, beam.sigma_x, beam.sigma_y, None)
+        print(f"  loss {L:.12e} forward {L0:.12e}", flush=True)
+        assert abs(L - L0) <= 1e-10 * abs(L0)
+        gmax = np.abs(ga).max()
+        h = 1e-6
+        for k in (100, 250, 380, 405, 410, 419):
+            ap, am = beam.amp.copy(), beam.amp.copy()
+            ap[k] += h
+            am[k] -= h
+            fd = (c4_axis_loss(box, cfg, ap, beam.sigma_x, beam.sigma_y, None) -
+                  c4_axis_loss(box, cfg, am, beam.sigma_x, beam.sigma_y, None)) / (2 * h)
+            print(f"  d/da_{k}: adjoint {ga[k]:.9e} differences {fd:.9e}", flush=True)
+            assert abs(ga[k] - fd) <= 1e-4 * max(abs(fd), 1e-3 * gmax), (k, ga[k], fd)
+        s = beam.sigma_x
+        fd = (c4_axis_loss(box, cfg, beam.amp, s + h, s + h, None) -
+              c4_axis_loss(box, cfg, beam.amp, s - h, s - h, None)) / (2 * h)
+        g_sr = gs[0] + gs[1]
+        print(f"  d/dsigma_r: adjoint {g_sr:.9e} differences {fd:.9e}", flush=True)
+        assert abs(g_sr - fd) <= 1e-4 * abs(fd), (g_sr, fd)
+        # nothing behind the last loss slice matters
+        assert np.all(ga[W.C4_LOSS_SLICES[1] + 1:] == 0.0)
+
+
+def test_c4_fp32_gradient_matches_fp64():
+    cfg, beam = W.c4()
+    print("c4 gradient FP32 vs FP64", flush=True)
+    with Q().Box(cfg, "fp64") as box:
+        g64, s64, L64 = c4_gradient(box, cfg, beam)
+    with Q().Box(cfg, "fp32") as box:
+        g32, s32, L32 = c4_gradient(box, cfg, beam)
+    err = np.abs(g32 - g64).max() / np.abs(g64).max()
+    print(f"  amplitudes max rel {err:.2e}, sigma {s32} vs {s64}, loss {L32} vs {L64}", flush=True)
+    assert err <= 1e-3, err
+    assert np.all(np.abs(s32 - s64) <= 1e-3 * np.abs(s64)), (s32, s64)
+    assert abs(L32 - L64) <= 1e-4 * abs(L64)

@@ -35,7 +35,7 @@ def to_np(t):
 # ------------------------------------------------------------------ DST solve
 
 @pytest.mark.parametrize("nx,ny", [(16, 16), (64, 32), (32, 128), (256, 256), (512, 512),
-                                   (2048, 2048)])
+                                   (1024, 1024), (1024, 512), (2048, 2048)])
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_poisson_solve_matches_oracle(nx, ny, prec):
     cfg = W.BoxConfig(nx=nx, ny=ny, x_lo=-3.0, x_hi=3.0, y_lo=-2.0, y_hi=2.5,
@@ -59,10 +59,19 @@ def test_poisson_solve_matches_oracle(nx, ny, prec):
             # of a white-noise source (its low modes carry ~1/n of its norm and
             # are divided by the smallest eigenvalues): tolerance eps_n n log2 n.
             n = max(nx, ny)
-            unit = (1e-15 if prec == "fp64" else 1e-7) * n * np.log2(n)
+            fast = prec == "fp32" and all(256 <= m <= 1024 for m in (nx, ny))
             for b in range(nb):
                 ref = O.poisson_solve(cfg, srcs[b], shift)
                 err = rel_l2(got[b], ref)
+                if fast and b != 1:
+                    # transforms without the prefix-sum recurrence: plain FFT
+                    # round-off (a float32 model of the solve gives 1.4e-7 to
+                    # 2.5e-7 for these sources, the recurrence 1.2e-6 to
+                    # 3.9e-6); the rapidly oscillating source 1 loses ~1e-5
+                    # in any float32 transform
+                    unit = 2e-6
+                else:
+                    unit = (1e-15 if prec == "fp64" else 1e-7) * n * np.log2(n)
                 print(f"  source {b} shift {shift}: rel-L2 {err:.2e} (tol {unit:.1e})")
                 assert err < unit, (b, shift, err)
                 assert np.all(got[b][0] == 0) and np.all(got[b][:, -1] == 0)

@@ -336,4 +336,126 @@ def small(n: int = 32, nzeta: int = 24, ppc: int = 1, nb: float = 0.5,
     return cfg, beam
 
 
+def blowout_slice_state(cfg: BoxConfig, seed: int = SEED, r_bubble: float = 1.2,
+                        n_floored: int = 64, n_leaving: int = 64, n_dead: int = 32,
+                        psi_floor: float = ONE_PLUS_PSI_FLOOR) -> dict:
+    """A seeded plasma slice shaped like the inside of a blowout, for
+    importing the same state into both implementations at full grid size
+    without running the box up to a nonlinear slice.
+
+    Particles keep their lattice order.  Each lattice site at radius r0 is
+    moved radially to r0 + (sqrt(r0^2 + r_bubble^2) - r0) exp(-r0^2/12.5)
+    (an electron-free column of radius ~r_bubble with a dense sheath), plus
+    a uniform jitter of +-0.3 cells; every position stays one cell inside
+    the box.  Momenta point outward with amplitude 0.6 exp(-(r0/1.5)^2)
+    plus N(0, 0.05) noise; Psi = -0.4 exp(-r^2/4.5) + N(0, 0.02).
+    Special particles, chosen at random without overlap:
+      n_floored  in the annulus 3 < r0 < 5 with 1 + Psi = 0.3 psi_floor
+                 (below the floor) and |u| <= 0.05;
+      n_leaving  on the lattice rows and columns next to the box edge, with
+                 an outward momentum of 3 (they leave the box in one slice);
+      n_dead     weight 0 (absorbed earlier).
+    History slots hold N(0, 0.05) values.  The macro weight of a live
+    particle is n0 hx hy / (ppc_x ppc_y).
+
+    Returns a dict of float64 arrays: x, y, ux, uy, psi, w [N];
+    hist [4, 5, N]; index arrays floored, leaving, dead."""
+    rng = np.random.default_rng(seed)
+    nX, nY = cfg.nx * cfg.ppc_x, cfg.ny * cfg.ppc_y
+    I, J = np.meshgrid(np.arange(nX), np.arange(nY))
+    I, J = I.ravel(), J.ravel()
+    x0 = cfg.x_lo + (I + 0.5) * cfg.hx / cfg.ppc_x
+    y0 = cfg.y_lo + (J + 0.5) * cfg.hy / cfg.ppc_y
+    n = x0.size
+    r0 = np.hypot(x0, y0)
+    push = (np.sqrt(r0 * r0 + r_bubble * r_bubble) - r0) * np.exp(-r0 * r0 / 12.5)
+    ang = np.arctan2(y0, x0)
+    cx, cy = np.cos(ang), np.sin(ang)
+    x = x0 + push * cx + rng.uniform(-0.3, 0.3, n) * cfg.hx
+    y = y0 + push * cy + rng.uniform(-0.3, 0.3, n) * cfg.hy
+    x = np.clip(x, cfg.x_lo + cfg.hx, cfg.x_hi - cfg.hx)
+    y = np.clip(y, cfg.y_lo + cfg.hy, cfg.y_hi - cfg.hy)
+    amp = 0.6 * np.exp(-(r0 / 1.5) ** 2)
+    ux = amp * cx + rng.normal(0.0, 0.05, n)
+    uy = amp * cy + rng.normal(0.0, 0.05, n)
+    r = np.hypot(x, y)
+    psi = -0.4 * np.exp(-r * r / 4.5) + rng.normal(0.0, 0.02, n)
+    w = np.full(n, cfg.n0 * cfg.hx * cfg.hy / (cfg.ppc_x * cfg.ppc_y))
+    hist = rng.normal(0.0, 0.05, (4, 5, n))
+
+    taken = np.zeros(n, dtype=bool)
+
+    def pick(mask, count):
+        cand = np.nonzero(mask & ~taken)[0]
+        sel = np.sort(rng.choice(cand, size=min(count, cand.size), replace=False))
+        taken[sel] = True
+        return sel
+
+    floored = pick((r0 > 3.0) & (r0 < 5.0), n_floored)
+    psi[floored] = -1.0 + 0.3 * psi_floor
+    ux[floored] = rng.uniform(-0.05, 0.05, floored.size)
+    uy[floored] = rng.uniform(-0.05, 0.05, floored.size)
+    edge = (I < cfg.ppc_x) | (I >= nX - cfg.ppc_x) | (J < cfg.ppc_y) | (J >= nY - cfg.ppc_y)
+    leaving = pick(edge, n_leaving)
+    x[leaving] = np.clip(x0[leaving], cfg.x_lo + 0.5 * cfg.hx, cfg.x_hi - 0.5 * cfg.hx)
+    y[leaving] = np.clip(y0[leaving], cfg.y_lo + 0.5 * cfg.hy, cfg.y_hi - 0.5 * cfg.hy)
+    out_x = np.where(I[leaving] < nX // 2, -1.0, 1.0)
+    out_y = np.where(J[leaving] < nY // 2, -1.0, 1.0)
+    on_x = (I[leaving] < cfg.ppc_x) | (I[leaving] >= nX - cfg.ppc_x)
+    ux[leaving] = np.where(on_x, 3.0 * out_x, 0.0)
+    uy[leaving] = np.where(on_x, 0.0, 3.0 * out_y)
+    psi[leaving] = 0.0
+    hist[:, :, leaving] = 0.0
+    dead = pick(np.ones(n, dtype=bool), n_dead)
+    w[dead] = 0.0
+    return {"x": x, "y": y, "ux": ux, "uy": uy, "psi": psi, "w": w, "hist": hist,
+            "floored": floored, "leaving": leaving, "dead": dead}
+
+
+def smooth_planes(cfg: BoxConfig, seed: int = SEED, scale: float = 0.2) -> dict:
+    """Seeded smooth node planes for the quantities a slice takes over from
+    the two slices before it (transverse currents of slice k-1, Bx and By of
+    slices k-1 and k-2): sums of a few random Gaussians of width 0.5-2 near
+    the axis, amplitude ~scale, zero on the boundary nodes."""
+    rng = np.random.default_rng(seed)
+    x = cfg.x_lo + cfg.hx * np.arange(cfg.nx + 1)
+    y = cfg.y_lo + cfg.hy * np.arange(cfg.ny + 1)
+    X, Y = np.meshgrid(x, y)
+    out = {}
+    for name in ("jx_prev", "jy_prev", "bx_prev1", "by_prev1", "bx_prev2", "by_prev2"):
+        f = np.zeros_like(X)
+        for _ in range(4):
+            a = rng.normal(0.0, scale)
+            xc, yc = rng.uniform(-1.5, 1.5, 2)
+            s = rng.uniform(0.5, 2.0)
+            f += a * np.exp(-((X - xc) ** 2 + (Y - yc) ** 2) / (2 * s * s))
+        f[0, :] = f[-1, :] = 0.0
+        f[:, 0] = f[:, -1] = 0.0
+        out[name] = f
+    return out
+
+
+def witness_slice_beam(cfg: BoxConfig, k: int, n: int, peak: float = C3_WITNESS["peak"],
+                       sigma_r: float = C3_WITNESS["sigma_r"],
+                       sigma_z: float = C3_WITNESS["sigma_z"], gamma: float = C3_GAMMA,
+                       dt: float = BEAM_DT, seed: int = SEED) -> ParticleBeam:
+    """n macro-particles of a Gaussian beam (peak n_b/n0 `peak`, transverse
+    sigma_r, longitudinal sigma_z) that all sit within slice k (|zeta -
+    zeta_k| < dzeta/4): the density of one slice at the peak of the C3
+    witness.  Weights carry the full beam's charge per slice (peak density x
+    2 pi sigma_r^2 x dzeta spread over n particles); values are float32
+    representable.  u_perp = 0 plus N(0, 0.01), u_z = sqrt(gamma^2 - 1)."""
+    rng = np.random.default_rng(seed)
+    zk = cfg.zeta_hi - k * cfg.dzeta
+    x = rng.normal(0.0, sigma_r, n)
+    y = rng.normal(0.0, sigma_r, n)
+    z = zk + rng.uniform(-0.25, 0.25, n) * cfg.dzeta
+    total = peak * 2.0 * math.pi * sigma_r * sigma_r * cfg.dzeta
+    uz = math.sqrt(gamma * gamma - 1.0)
+    f32 = lambda a: np.asarray(a, dtype=np.float32).astype(np.float64)
+    return ParticleBeam(x=f32(x), y=f32(y), zeta=f32(z), ux=f32(rng.normal(0.0, 0.01, n)),
+                        uy=f32(rng.normal(0.0, 0.01, n)), uz=f32(np.full(n, uz)),
+                        w=f32(np.full(n, total / n)), dt=dt)
+
+
 PRESETS = {"c1": c1, "c2": c2, "c4": c4, "c5": c5}
