@@ -289,6 +289,27 @@ qsp_status qsp_set_slice_state(qsp_ctx ctx, const qsp_slice_state* src);
 qsp_status qsp_solve_poisson(qsp_ctx ctx, int32_t nbatch, const void* src, void* dst,
                              double shift);
 
+/* The batched 2D Dirichlet solve of qsp_solve_poisson without a context and
+ * without allocating device memory, for callers that cannot allocate (code
+ * under stream capture, tight serving loops).  Only the grid fields of cfg
+ * are read: nx, ny (powers of two in [16, 2048]), x_lo, x_hi, y_lo, y_hi and
+ * precision.  Solves (lap_h - shift) u_b = src_b for b < nbatch on
+ * `device`, enqueued on `hip_stream` (a hipStream_t; NULL = the null
+ * stream); src, dst: device arrays [nbatch][ny+1][nx+1] in the given
+ * precision (boundary entries of src ignored, of dst written as 0);
+ * 1 <= nbatch <= 4; shift >= 0.  Intermediate planes and transform tables
+ * live in one static device array per GPU of 16 MiB + 256 KiB (held from
+ * the library's first use on that GPU until the process ends):
+ * nbatch * nx * ny values above 16 MiB -> QSP_ERR_INVALID_ARG.  Every call
+ * on one GPU uses that GPU's array, so calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller.
+ * Asynchronous; argument errors leave dst untouched.  HIP errors ->
+ * QSP_ERR_DEVICE (no context, nothing sticky).  qsp_last_error(NULL) gives
+ * the message. */
+qsp_status qsp_solve_poisson_noalloc(const qsp_config* cfg, int device, void* hip_stream,
+                                     int32_t nbatch, const void* src, void* dst,
+                                     double shift);
+
 /* Cotangent weights of a recorded run for qsp_run_box_adjoint: the loss is
  *   L = sum_{k = k_lo}^{n-1} sum_F < w_F[k - k_lo], F_k >
  * over the interior nodes, F in psi, Ex-By, Ey+Bx, Ez, Bx, By, Bz of slice

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
 SOURCES = ["dst.hip", "explicit.hip", "particles.hip", "fields.hip", "beam.hip", "adjoint.hip",
-           "runtime.cpp", "abi.cpp"]
+           "noalloc.hip", "runtime.cpp", "abi.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep the compiler from emitting packed FP32 arithmetic

@@ -290,6 +290,16 @@ qsp_status qsp_solve_poisson(qsp_ctx ctx, int32_t nbatch, const void* src, void*
   });
 }
 
+qsp_status qsp_solve_poisson_noalloc(const qsp_config* cfg, int device, void* hip_stream,
+                                     int32_t nbatch, const void* src, void* dst,
+                                     double shift) {
+  std::string err;
+  const qsp_status st =
+      qsp::solve_poisson_noalloc(cfg, device, hip_stream, nbatch, src, dst, shift, err);
+  if (st != QSP_OK) return fail(nullptr, st, err);
+  return QSP_OK;
+}
+
 qsp_status qsp_set_timing(qsp_ctx ctx, int32_t every) {
   return guarded(ctx, [&] {
     if (every < 0) return fail(ctx, QSP_ERR_INVALID_ARG, "every must be >= 0");

@@ -77,4 +77,9 @@ std::unique_ptr<BoxBase> make_box(const qsp_config& cfg, int device, hipStream_t
 // bytes a context of this configuration will hold on the device
 int64_t device_bytes_needed(const qsp_config& cfg);
 
+// qsp_solve_poisson_noalloc (static scratch, no allocation); err holds the
+// reason of a failure
+qsp_status solve_poisson_noalloc(const qsp_config* cfg, int device, void* stream, int nbatch,
+                                 const void* src, void* dst, double shift, std::string& err);
+
 }  // namespace qsp

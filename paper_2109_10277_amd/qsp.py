@@ -130,6 +130,7 @@ def lib() -> C.CDLL:
             "qsp_get_slice_state": [vp, C.POINTER(SliceState)],
             "qsp_set_slice_state": [vp, C.POINTER(SliceState)],
             "qsp_solve_poisson": [vp, i32, vp, vp, d],
+            "qsp_solve_poisson_noalloc": [C.POINTER(Config), C.c_int, vp, i32, vp, vp, d],
             "qsp_get_info": [vp, C.POINTER(i64), C.POINTER(i32)],
             "qsp_set_timing": [vp, i32],
             "qsp_get_kernel_times": [vp, C.POINTER(KernelTimes)],
@@ -442,6 +443,21 @@ class Box:
             raise ValueError(f"output {q}: expected trailing shape {shape}")
         if t.dtype != self.dtype_of(q) or t.device != self.device:
             raise ValueError(f"output {q}: wrong dtype/device")
+
+
+def solve_poisson_noalloc(cfg, src, dst, shift: float = 0.0, precision: str = "fp32",
+                          device: int = 0, stream=None):
+    """Batched Dirichlet solve without a context or device allocation
+    (qsp_solve_poisson_noalloc): src, dst contiguous device tensors
+    [nbatch, ny+1, nx+1] of the given precision."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(torch.device("cuda", device))
+    c = make_config(cfg, precision)
+    st = lib().qsp_solve_poisson_noalloc(C.byref(c), int(device), C.c_void_p(stream.cuda_stream),
+                                         int(src.shape[0]), C.c_void_p(_ptr(src)),
+                                         C.c_void_p(_ptr(dst)), float(shift))
+    _check(st, None)
 
 
 def status_string(s: int) -> str:
