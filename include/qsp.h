@@ -233,7 +233,9 @@ qsp_status qsp_set_beam_gaussian(qsp_ctx ctx, const double* amp, double sx,
  * solves and, once the slice's fields are final, advances them by one
  * time step dt (drift-kick-drift, Boris kick; dt = 0: no push).  n = 0
  * removes the particle beam.  Replaces any previous particle beam.  A beam
- * pushed during a box is sorted again by qsp_init_plasma.  Synchronises. */
+ * pushed during a box is sorted again by qsp_init_plasma.  Synchronises.
+ * Errors: n outside [0, 2^31), null soa with n > 0, non-finite dt, or a
+ * particle beam in a box of nzeta >= 16384 slices -> QSP_ERR_INVALID_ARG. */
 qsp_status qsp_set_beam_particles(qsp_ctx ctx, int64_t n, const float* soa,
                                   double dt);
 

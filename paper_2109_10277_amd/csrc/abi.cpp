@@ -130,6 +130,8 @@ qsp_status qsp_set_beam_particles(qsp_ctx ctx, int64_t n, const float* soa, doub
     if (n < 0 || n > 2147483647LL) return fail(ctx, QSP_ERR_INVALID_ARG, "n must be in [0, 2^31)");
     if (n > 0 && !soa) return fail(ctx, QSP_ERR_INVALID_ARG, "null particle array");
     if (!std::isfinite(dt)) return fail(ctx, QSP_ERR_INVALID_ARG, "dt must be finite");
+    if (n > 0 && ctx->box->config().nzeta + 1 > qsp::kMaxBeamKeys)
+      return fail(ctx, QSP_ERR_INVALID_ARG, "particle beams need nzeta < 16384");
     ctx->box->set_beam_particles(n, soa, dt);
     return QSP_OK;
   });

@@ -12,13 +12,13 @@ using namespace dst_detail;
 // ---------------------------------------------------------------------------
 
 // field ids of the psi / Ez / Bz batch
-template <typename T, int LOGN>
+template <typename T, int LOGN, int RC>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  const int n = g.nx;
-  const int R = g.rr;
+  constexpr int n = 1 << LOGN;   // = nx
+  const int R = RC > 0 ? RC : g.rr;
   const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
@@ -26,11 +26,10 @@ k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
   const int j0 = blockIdx.x * R;
   const int fld = blockIdx.y;   // 0 psi, 1 Ez, 2 Bz
   const double ihx = 0.5 / g.hx, ihy = 0.5 / g.hy;
-  const int lx = g.lx;
   // neighbour indices are clamped so that every load is in bounds; values
   // outside the interior are replaced by selects
-  for_elems(R * n, [&](int e) {
-    const int r = e >> lx, i = e & (n - 1);
+  for_row_elems<RC, LOGN>(R, [&](int e) {
+    const int r = e >> LOGN, i = e & (n - 1);
     const int j = j0 + r;
     const int o = j * n + i;
     double s;
@@ -50,25 +49,25 @@ k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.out + static_cast<size_t>(fld) * g.nx * g.ny;
-  for_elems(R * n, [&](int e) {
-    const int r = e >> lx, i = e & (n - 1);
+  for_row_elems<RC, LOGN>(R, [&](int e) {
+    const int r = e >> LOGN, i = e & (n - 1);
     out[(j0 + r) * n + i] = buf[Pad<T>::rpos(n, ppitch, r, i)];
   });
 }
 
-template <typename T, int LOGN>
+template <typename T, int LOGN, int RC>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_src_fwd_bxby(Geom g, SrcBxBy<T> a, AxisTables<T> tx, const DevCounters* ctr) {
   if (ctr->pc_done) return;
   extern __shared__ unsigned char smem_raw[];
-  src_bxby_block<T, LOGN>(g, a, tx, blockIdx.x, blockIdx.y, smem_raw);
+  src_bxby_block<T, LOGN, RC>(g, a, tx, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
 // P2: column strip solve
 // ---------------------------------------------------------------------------
 template <typename T, int LOGN>
-__global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
+__global__ void __launch_bounds__(kBlock, col_blocks_per_cu(LOGN, sizeof(T)))
 k_col_solve(Geom g, ColArgs<T> a, AxisTables<T> ty, const double* __restrict__ lamx,
             const DevCounters* ctr) {
   if (a.honor_done && ctr->pc_done) return;
@@ -81,13 +80,13 @@ k_col_solve(Geom g, ColArgs<T> a, AxisTables<T> ty, const double* __restrict__ l
 // ---------------------------------------------------------------------------
 // P3: inverse DST along x with epilogues
 // ---------------------------------------------------------------------------
-template <typename T, int LOGN>
+template <typename T, int LOGN, int RC>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   extern __shared__ unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
-  const int n = g.nx;
-  const int R = g.rr;
+  constexpr int n = 1 << LOGN;   // = nx
+  const int R = RC > 0 ? RC : g.rr;
   const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
@@ -95,9 +94,8 @@ k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   const int j0 = blockIdx.x * R;
   const int fld = blockIdx.y;
   const T* in = a.in[fld];
-  const int lx = g.lx;
-  for_elems<32>(R * n, [&](int e) {
-    const int r = e >> lx, i = e & (n - 1);
+  for_row_elems<RC, LOGN, 32>(R, [&](int e) {
+    const int r = e >> LOGN, i = e & (n - 1);
     buf[Pad<T>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
   });
   __syncthreads();
@@ -106,8 +104,8 @@ k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   T* out = a.out[fld];
   T* out_dx = a.out_dx[fld];
   const T mihx = static_cast<T>(-0.5 / g.hx);
-  for_elems(R * n, [&](int e) {
-    const int r = e >> lx, i = e & (n - 1);
+  for_row_elems<RC, LOGN>(R, [&](int e) {
+    const int r = e >> LOGN, i = e & (n - 1);
     const int j = j0 + r;
     const T* row = buf + Pad<T>::rpos(n, ppitch, r, 0);
     const T u = row[Pad<T>::ridx(i)];
@@ -120,12 +118,12 @@ k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   });
 }
 
-template <typename T, int LOGN>
+template <typename T, int LOGN, int RC>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_row_inv_pc(Geom g, PCArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   if (ctr->pc_done) return;
   extern __shared__ unsigned char smem_raw[];
-  row_inv_pc_block<T, LOGN>(g, a, tx, blockIdx.x, blockIdx.y, smem_raw);
+  row_inv_pc_block<T, LOGN, RC>(g, a, tx, blockIdx.x, blockIdx.y, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -139,15 +137,28 @@ static void allow_lds(const void* fn, size_t lds) {
                                 static_cast<int>(lds)));
 }
 
+// Each wave transforms one group of row pairs (one pair for the FP32 core,
+// max(1, 512/n) otherwise): a pass must not give a workgroup more rows.
+template <typename T>
+static void check_rows(int n, int rows) {
+  const int per = fast_core(sizeof(T), n) || n >= 512 ? 1 : 512 / n;
+  if (rows > 2 * per * (kBlock / 64))
+    throw std::invalid_argument("transform pass: more row pairs than its waves take");
+}
+
 template <typename T>
 void launch_src_fwd_pez(const Geom& g, const SrcPEZ<T>& a, const AxisTables<T>& tx,
                         hipStream_t st) {
   const int R = g.rr;
+  check_rows<T>(g.nx, R);
   const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
-    allow_lds(reinterpret_cast<const void*>(&k_src_fwd_pez<T, E>), lds);
-    hipLaunchKernelGGL((k_src_fwd_pez<T, E>), dim3(g.ny / R, 3), dim3(kBlock), lds, st, g, a, tx);
+    with_rows<T, E>(R, [&](auto rc) {
+      constexpr int RC = decltype(rc)::value;
+      allow_lds(reinterpret_cast<const void*>(&k_src_fwd_pez<T, E, RC>), lds);
+      hipLaunchKernelGGL((k_src_fwd_pez<T, E, RC>), dim3(g.ny / R, 3), dim3(kBlock), lds, st, g, a, tx);
+    });
   });
   QSP_LAUNCH_CHECK();
 }
@@ -156,12 +167,16 @@ template <typename T>
 void launch_src_fwd_bxby(const Geom& g, const SrcBxBy<T>& a, const AxisTables<T>& tx,
                          const DevCounters* ctr, hipStream_t st) {
   const int R = g.rr;
+  check_rows<T>(g.nx, R);
   const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
-    allow_lds(reinterpret_cast<const void*>(&k_src_fwd_bxby<T, E>), lds);
-    hipLaunchKernelGGL((k_src_fwd_bxby<T, E>), dim3(g.ny / R, 2), dim3(kBlock), lds, st, g, a, tx,
-                       ctr);
+    with_rows<T, E>(R, [&](auto rc) {
+      constexpr int RC = decltype(rc)::value;
+      allow_lds(reinterpret_cast<const void*>(&k_src_fwd_bxby<T, E, RC>), lds);
+      hipLaunchKernelGGL((k_src_fwd_bxby<T, E, RC>), dim3(g.ny / R, 2), dim3(kBlock), lds, st, g, a, tx,
+                         ctr);
+    });
   });
   QSP_LAUNCH_CHECK();
 }
@@ -172,8 +187,9 @@ void launch_col_solve(const Geom& g, const ColArgs<T>& a, int nfield, const Axis
   const int W = a.w;
   if (W < 2 || (W & (W - 1)) || g.nx % W || nfield < 1 || nfield > 4)
     throw std::invalid_argument("column pass: bad strip width or field count");
+  check_rows<T>(g.ny, W);
   const size_t lds = static_cast<size_t>(W / 2) * pair_pitch<T>(g.ny) * sizeof(T) + table_bytes<T>(g.ny) +
-                     static_cast<size_t>(g.ny + W) * sizeof(double);
+                     lam_bytes<T>(g.ny, W);
   with_logn(g.ny, [&](auto e) {
     constexpr int E = decltype(e)::value;
     allow_lds(reinterpret_cast<const void*>(&k_col_solve<T, E>), lds);
@@ -187,11 +203,15 @@ template <typename T>
 void launch_row_inv(const Geom& g, const RowInvArgs<T>& a, int nfield, const AxisTables<T>& tx,
                     hipStream_t st) {
   const int R = g.rr;
+  check_rows<T>(g.nx, R);
   const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
-    allow_lds(reinterpret_cast<const void*>(&k_row_inv<T, E>), lds);
-    hipLaunchKernelGGL((k_row_inv<T, E>), dim3(g.ny / R, nfield), dim3(kBlock), lds, st, g, a, tx);
+    with_rows<T, E>(R, [&](auto rc) {
+      constexpr int RC = decltype(rc)::value;
+      allow_lds(reinterpret_cast<const void*>(&k_row_inv<T, E, RC>), lds);
+      hipLaunchKernelGGL((k_row_inv<T, E, RC>), dim3(g.ny / R, nfield), dim3(kBlock), lds, st, g, a, tx);
+    });
   });
   QSP_LAUNCH_CHECK();
 }
@@ -200,12 +220,16 @@ template <typename T>
 void launch_row_inv_pc(const Geom& g, const PCArgs<T>& a, const AxisTables<T>& tx,
                        DevCounters* ctr, hipStream_t st) {
   const int R = g.rr;
+  check_rows<T>(g.nx, R);
   const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
-    allow_lds(reinterpret_cast<const void*>(&k_row_inv_pc<T, E>), lds);
-    hipLaunchKernelGGL((k_row_inv_pc<T, E>), dim3(g.ny / R, 2), dim3(kBlock), lds, st, g, a, tx,
-                       ctr);
+    with_rows<T, E>(R, [&](auto rc) {
+      constexpr int RC = decltype(rc)::value;
+      allow_lds(reinterpret_cast<const void*>(&k_row_inv_pc<T, E, RC>), lds);
+      hipLaunchKernelGGL((k_row_inv_pc<T, E, RC>), dim3(g.ny / R, 2), dim3(kBlock), lds, st, g, a, tx,
+                         ctr);
+    });
   });
   QSP_LAUNCH_CHECK();
 }

@@ -392,11 +392,43 @@ __device__ __forceinline__ void dft_reg(Cplx<float>* v) {
 }
 
 // DST-I of one pair (rows a at g, b at g + rlen(n), entry 0 = 0) by one
-// wave, in place; twa[k1 * 64 + l] = W_N^{l k1}, w64[la * 9 + c1] =
-// W_64^{la c1}.  The pair's region holds P rows of kCorePitch complex.
+// wave, in place; twa[k1 * 64 + l] = W_N^{l k1} (global memory), w64[la * 9
+// + c1] = W_64^{la c1} (LDS).  The pair's region holds P rows of kCorePitch
+// complex.
+// Output scaling of the core: none (plain transform).
+struct NoScale {
+  __device__ void operator()(int, int, float&, float&) const {}
+};
+
+// Output scaling of the core in the column pass: S_k of the pair's columns
+// p_a, p_b divided by (lambda_x(p) + lambda_y(k) - shift) nx ny / 4, the
+// eigenvalue of the shifted Laplacian times the two transforms'
+// normalisation; column p = 0 (a boundary node line) is zero.  ry holds
+// (lambda_y(k) - shift) nx ny / 4 for the lane's 4 NB outputs k (see the
+// core's B2 stage), xa / xb lambda_x(p) nx ny / 4.
+template <int NB>
+struct EigenScale {
+  float ry[NB][4];
+  float xa, xb;
+  bool za;
+  __device__ void operator()(int t, int c2, float& oa, float& ob) const {
+    const float ra = __builtin_amdgcn_rcpf(xa + ry[t][c2]);
+    const float rb = __builtin_amdgcn_rcpf(xb + ry[t][c2]);
+    oa = za ? 0.f : oa * ra;
+    ob *= rb;
+  }
+};
+
+// The output index k of the core's register (t, c2) in lane l.
 template <int P>
+__device__ __forceinline__ int core_out_k(int l, int t, int c2) {
+  return (l >> 3) + 8 * t + P * (l & 7) + 8 * P * c2;
+}
+
+template <int P, typename Epi = NoScale>
 __device__ __forceinline__ void wave_dst_core(float* g, const Cplx<float>* __restrict__ twa,
-                                              const Cplx<float>* __restrict__ w64) {
+                                              const Cplx<float>* __restrict__ w64,
+                                              const Epi& epi = Epi{}) {
   using Pd = Pad<float>;
   constexpr int n = 32 * P;
   constexpr int NB = P / 8;
@@ -466,8 +498,10 @@ __device__ __forceinline__ void wave_dst_core(float* g, const Cplx<float>* __res
     for (int c2 = 0; c2 < 4; ++c2) {
       const int k = k0 + 8 * P * c2;
       const int j = Pd::ridx(k);
-      ra[j] = k ? -0.5f * u[t][c2].im : 0.f;
-      rb[j] = k ? 0.5f * u[t][c2].re : 0.f;
+      float oa = -0.5f * u[t][c2].im, ob = 0.5f * u[t][c2].re;
+      epi(t, c2, oa, ob);
+      ra[j] = k ? oa : 0.f;
+      rb[j] = k ? ob : 0.f;
     }
   }
   wave_sync();
@@ -496,19 +530,20 @@ __device__ __forceinline__ void block_dst(T* buf, int logn, int nrow, int ppitch
   (void)logn;
   const int npair = nrow >> 1;
   const int wave = threadIdx.x >> 6;
-  const int nwave = blockDim.x >> 6;
   if constexpr (fast_core(sizeof(T), n)) {
     // tw: W_N^{l k1} by [k1][lane]; pre: the W_64 table (complex)
+    // one pair per wave (the launchers keep nrow <= 2 * waves): no loop,
+    // whose invariant hoisting would keep the core's per-lane addresses live
     const Cplx<float>* w64 = reinterpret_cast<const Cplx<float>*>(pre);
-    for (int f = wave; f < npair; f += nwave)
-      wave_dst_core<n / 32>(buf + static_cast<size_t>(f) * ppitch, tw, w64);
+    if (wave < npair) wave_dst_core<n / 32>(buf + static_cast<size_t>(wave) * ppitch, tw, w64);
   } else {
     constexpr int per = n >= 512 ? 1 : 512 / n;
     constexpr int E = n <= 512 ? 8 : n / 64;
+    // at most one group per wave (the launchers keep nrow <= 2 * per * waves)
     const int ngroup = (npair + per - 1) / per;
-    for (int gi = wave; gi < ngroup; gi += nwave) {
-      const int npg = min(per, npair - gi * per);
-      wave_dst<T, E, LOGN>(buf + static_cast<size_t>(gi) * per * ppitch, npg, ppitch, tw, pre);
+    if (wave < ngroup) {
+      const int npg = min(per, npair - wave * per);
+      wave_dst<T, E, LOGN>(buf + static_cast<size_t>(wave) * per * ppitch, npg, ppitch, tw, pre);
     }
   }
   __syncthreads();
@@ -532,11 +567,11 @@ void with_logn(int n, F&& f) {
 }
 
 // Bytes of the per-axis tables a transform pass stages in LDS: twiddles and
-// pre-twiddles of the half-length transform, or for the FP32 core the
-// W_N^{l k1} table (2n complex) and the W_64 table (72 complex).
+// pre-twiddles of the half-length transform, or for the FP32 core the W_64
+// table (72 complex; its W_N^{l k1} table is read from global memory).
 template <typename T>
 __host__ __device__ inline size_t table_bytes(int n) {
-  if (fast_core(sizeof(T), n)) return static_cast<size_t>(2 * n + 72) * sizeof(Cplx<T>);
+  if (fast_core(sizeof(T), n)) return static_cast<size_t>(72) * sizeof(Cplx<T>);
   return static_cast<size_t>(n) * (sizeof(Cplx<T>) + sizeof(T));
 }
 
@@ -551,10 +586,18 @@ inline int pass_waves(const char* env, int dflt) {
   return dflt;
 }
 
+// Eigenvalue bytes the column pass stages after the tables: the strip's W
+// x eigenvalues, and the n y eigenvalues except with the FP32 core (which
+// reads them from global memory so that two workgroups fit a CU at 1024).
+template <typename T>
+__host__ __device__ inline size_t lam_bytes(int n, int w) {
+  return static_cast<size_t>((fast_core(sizeof(T), n) ? 0 : n) + w) * sizeof(double);
+}
+
 template <typename T>
 inline size_t pass_lds(int rows, int n) {
   return static_cast<size_t>(rows / 2) * pair_pitch<T>(n) * sizeof(T) + table_bytes<T>(n) +
-         static_cast<size_t>(n + rows) * sizeof(double);
+         lam_bytes<T>(n, rows);
 }
 
 // columns per column-pass workgroup (even, at most nx, within 80 KiB of LDS).
@@ -563,7 +606,7 @@ inline size_t pass_lds(int rows, int n) {
 // row segments each workgroup reads (measured from HIP graphs: 8 % off a
 // 1024^2 time step in FP32, 2 % off the 512^2 box in FP64).
 // The FP32 core at 1024 rows: four busy waves (eight-column strips, 32-byte
-// row segments), one workgroup per CU.
+// row segments), two workgroups per CU.
 template <typename T>
 inline int col_strip(int nx, int ny, int nfield) {
   (void)nfield;
@@ -576,7 +619,8 @@ inline int col_strip(int nx, int ny, int nfield) {
     if (v >= 2 && v <= 64 && (v & (v - 1)) == 0) w = v;
   }
   if (w > nx) w = nx;
-  const size_t cap = core && ny >= 1024 ? 163840 : 81920;   // one or two workgroups per CU
+  if (w > 2 * per * (kBlock / 64)) w = 2 * per * (kBlock / 64);   // one pair group per wave
+  const size_t cap = 81920;   // two workgroups per CU
   while (w > 2 && pass_lds<T>(w, ny) > cap) w >>= 1;
   return w;
 }
@@ -591,21 +635,13 @@ __device__ inline void stage_tables(const AxisTables<T>& t, unsigned char* base,
   constexpr int n = 1 << LOGN;
   Cplx<T>* stw = reinterpret_cast<Cplx<T>*>(base);
   if constexpr (fast_core(sizeof(T), n)) {
-    // 2n entries W_N^{l k1} by [k1][lane], then 72 of W_64 (as complex);
-    // 2n is a multiple of the workgroup size here
-    constexpr int NT = 2 * n / kBlock;
-    static_assert(2 * n % kBlock == 0, "table staging assumes 2n divisible by kBlock");
-    Cplx<T>* sw = stw + 2 * n;
+    // the W_N^{l k1} table (2n entries by [k1][lane]) stays in global
+    // memory, where each wave reads it coalesced (L1/L2 resident); the 72
+    // entries of W_64 go to LDS
+    Cplx<T>* sw = stw;
     const Cplx<T>* gw = reinterpret_cast<const Cplx<T>*>(t.pre);
-    Cplx<T> v[NT];
-#pragma unroll
-    for (int u = 0; u < NT; ++u) v[u] = t.tw[threadIdx.x + u * kBlock];
-    const bool wt = threadIdx.x < 72;
-    const Cplx<T> w = gw[wt ? threadIdx.x : 0];
-#pragma unroll
-    for (int u = 0; u < NT; ++u) stw[threadIdx.x + u * kBlock] = v[u];
-    if (wt) sw[threadIdx.x] = w;
-    tw = stw;
+    if (threadIdx.x < 72) sw[threadIdx.x] = gw[threadIdx.x];
+    tw = t.tw;
     pre = reinterpret_cast<const T*>(sw);
   } else {
     T* spre = reinterpret_cast<T*>(base + n * sizeof(Cplx<T>));
@@ -706,11 +742,20 @@ __device__ inline int xcd_strip(int b, int nstrip) {
 // Workgroups per CU the transform kernels are compiled for: four (<= 128
 // VGPRs) while a lane holds at most 8 FP32 complex points, fewer for the
 // long FP64 transforms whose register arrays would otherwise spill.
-// The FP32 core holds P = 2n/64 complex points per lane: 1024 points run
-// one workgroup per CU (up to 512 registers per lane, VGPRs and AGPRs), 512
-// two, 256 four.
+// The FP32 core holds P = 2n/64 complex points per lane (one pair per wave,
+// up to ~140 VGPRs at 1024 points): two workgroups per CU at 1024, four
+// below.
 constexpr int dst_blocks_per_cu(int logn, int tsize) {
-  if (fast_core(tsize, 1 << logn)) return logn >= 10 ? 1 : (logn == 9 ? 2 : 4);
+  if (fast_core(tsize, 1 << logn)) return logn >= 10 ? 2 : 4;
+  const int u = (logn <= 9 ? 8 : (1 << logn) / 64) * tsize / 4;
+  return u <= 8 ? 4 : (u <= 16 ? 2 : 1);
+}
+
+// The column pass with the FP32 core keeps its eigenvalue divisors and a
+// strip load in flight beside the core's registers: two workgroups per CU
+// (its grids hold at most two per CU at 512 and 1024 rows).
+constexpr int col_blocks_per_cu(int logn, int tsize) {
+  if (fast_core(tsize, 1 << logn)) return 2;
   const int u = (logn <= 9 ? 8 : (1 << logn) / 64) * tsize / 4;
   return u <= 8 ? 4 : (u <= 16 ? 2 : 1);
 }
@@ -744,16 +789,54 @@ __device__ __forceinline__ void for_elems(int total, F&& f) {
 
 
 
+// Calls f(e) for e = t + u kBlock, u = 0 .. TOTAL / kBlock - 1 (TOTAL a
+// multiple of kBlock known at compile time), fully unrolled: with the row
+// length a compile-time power of two, the row and column of e and their LDS
+// offsets fold to per-thread constants plus immediates.
+template <int TOTAL, typename F>
+__device__ __forceinline__ void for_elems_ct(F&& f) {
+  static_assert(TOTAL % kBlock == 0, "whole multiples of the workgroup");
+  const int t = static_cast<int>(threadIdx.x) & (kBlock - 1);
+#pragma unroll
+  for (int u = 0; u < TOTAL / kBlock; ++u) f(t + u * kBlock);
+}
+
+// The elements of a block of rows of n = 2^LOGN: RC rows when RC > 0 (a
+// compile-time row count), else R rows in chunks of CH (see for_elems).
+template <int RC, int LOGN, int CH = 8, typename F>
+__device__ __forceinline__ void for_row_elems(int R, F&& f) {
+  if constexpr (RC > 0)
+    for_elems_ct<(RC << LOGN)>(f);
+  else
+    for_elems<CH>(R << LOGN, f);
+}
+
+// Runs f(std::integral_constant<int, RC>) with RC = R (2, 4 or 8) for row
+// passes of the FP32 core, RC = 0 (rows at run time) otherwise.
+template <typename T, int LOGN, typename F>
+void with_rows(int R, F&& f) {
+  if constexpr (fast_core(sizeof(T), 1 << LOGN)) {
+    switch (R) {
+      case 2: f(std::integral_constant<int, 2>{}); break;
+      case 4: f(std::integral_constant<int, 4>{}); break;
+      case 8: f(std::integral_constant<int, 8>{}); break;
+      default: throw std::invalid_argument("row pass: rows per workgroup must be 2, 4 or 8");
+    }
+  } else {
+    f(std::integral_constant<int, 0>{});
+  }
+}
+
 // Source assembly (FP64) + forward DST along x of row block bxi of field
 // fld (0 Bx, 1 By) of the Bx/By predictor-corrector.
-template <typename T, int LOGN>
+template <typename T, int LOGN, int RC>
 __device__ __forceinline__ void src_bxby_block(const Geom& g, const SrcBxBy<T>& a,
                                                const AxisTables<T>& tx, int bxi, int fld,
                                                unsigned char* smem_raw) {
   __syncthreads();   // the workgroup's previous use of LDS is complete
   T* buf = reinterpret_cast<T*>(smem_raw);
-  const int n = g.nx;
-  const int R = g.rr;
+  constexpr int n = 1 << LOGN;   // = nx
+  const int R = RC > 0 ? RC : g.rr;
   const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
@@ -761,10 +844,9 @@ __device__ __forceinline__ void src_bxby_block(const Geom& g, const SrcBxBy<T>& 
   const int j0 = bxi * R;
   const double ihx = 0.5 / g.hx, ihy = 0.5 / g.hy;
   const double idz = 0.5 / a.dzeta;
-  const int lx = g.lx;
   const double amp = a.beam_amp;
-  for_elems(R * n, [&](int e) {
-    const int r = e >> lx, i = e & (n - 1);
+  for_row_elems<RC, LOGN>(R, [&](int e) {
+    const int r = e >> LOGN, i = e & (n - 1);
     const int j = j0 + r;
     const int o = j * n + i;
     double s;
@@ -794,10 +876,109 @@ __device__ __forceinline__ void src_bxby_block(const Geom& g, const SrcBxBy<T>& 
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.out + static_cast<size_t>(fld) * g.nx * g.ny;
-  for_elems(R * n, [&](int e) {
-    const int r = e >> lx, i = e & (n - 1);
+  for_row_elems<RC, LOGN>(R, [&](int e) {
+    const int r = e >> LOGN, i = e & (n - 1);
     out[(j0 + r) * n + i] = buf[Pad<T>::rpos(n, ppitch, r, i)];
   });
+}
+
+// Calls f(it) for it = 0 .. NIT-1 in unrolled chunks of up to 32 (NIT a
+// compile-time count), so that element addresses are affine in it.
+template <int NIT, typename F>
+__device__ __forceinline__ void for_iters(F&& f) {
+#pragma unroll
+  for (int i0 = 0; i0 < NIT; i0 += 32) {
+#pragma unroll
+    for (int u = 0; u < (NIT - i0 < 32 ? NIT - i0 : 32); ++u) f(i0 + u);
+  }
+}
+
+// Column pass with the FP32 core (n = ny = 256..1024, W = 2, 4 or 8
+// columns): strip load, forward core whose output stage divides by the
+// eigenvalues, inverse core, store.  Thread t handles column c = t mod W and
+// rows j = t / W + it (256 / W); the row step is a multiple of 32, so the
+// padded LDS index ridx(j) = j + j / 32 is affine in it as well.
+template <int LOGN, int W>
+__device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<float>& a,
+                                               const AxisTables<float>& ty,
+                                               const double* __restrict__ lamx, int strip, int fld,
+                                               unsigned char* smem_raw) {
+  using Pd = Pad<float>;
+  constexpr int n = 1 << LOGN;
+  constexpr int P = n / 32, NB = P / 8;
+  constexpr int LW = W == 2 ? 1 : (W == 4 ? 2 : 3);
+  constexpr int JS = kBlock / W;              // row step of a thread
+  constexpr int NIT = n / JS;                 // rows per thread
+  constexpr int LS = JS + JS / 32;            // LDS step of ridx
+  static_assert(JS % 32 == 0, "row step must keep the LDS padding affine");
+  __syncthreads();   // the workgroup's previous use of LDS is complete
+  float* buf = reinterpret_cast<float*>(smem_raw);
+  const int nx = g.nx;
+  const int ppitch = pair_pitch<float>(n);
+  const int p0 = strip * W;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int wave = tid >> 6, l = tid & 63;
+  const bool busy = wave < W / 2;
+  Cplx<float>* w64 = reinterpret_cast<Cplx<float>*>(smem_raw + static_cast<size_t>(W / 2) * ppitch * sizeof(float));
+  if (tid < 72) w64[tid] = reinterpret_cast<const Cplx<float>*>(ty.pre)[tid];
+  // the y eigenvalues of the lane's core outputs, fetched under the strip load
+  double ly[NB][4];
+  double lxa = 0.0, lxb = 0.0;
+  if (busy) {
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+#pragma unroll
+      for (int c2 = 0; c2 < 4; ++c2) ly[t][c2] = ty.lam[core_out_k<P>(l, t, c2)];
+    lxa = lamx[p0 + 2 * wave];
+    lxb = lamx[p0 + 2 * wave + 1];
+  }
+  const size_t plane = static_cast<size_t>(nx) * n;
+  const int c = tid & (W - 1), j0 = tid >> LW;
+  const int lcol = (c >> 1) * ppitch + (c & 1) * Pd::rlen(n) + Pd::ridx(j0);
+  {
+    const float* in = a.in + fld * plane + p0 + c + static_cast<size_t>(j0) * nx;
+    float* d = buf + lcol;
+    for_iters<NIT>([&](int it) { d[it * LS] = in[static_cast<size_t>(it) * JS * nx]; });
+  }
+  __syncthreads();
+  if (busy) {
+    const double shift = a.shift[fld];
+    const double inorm = 0.25 * static_cast<double>(nx) * n;
+    EigenScale<NB> sc;
+#pragma unroll
+    for (int t = 0; t < NB; ++t)
+#pragma unroll
+      for (int c2 = 0; c2 < 4; ++c2) sc.ry[t][c2] = static_cast<float>((ly[t][c2] - shift) * inorm);
+    sc.xa = static_cast<float>(lxa * inorm);
+    sc.xb = static_cast<float>(lxb * inorm);
+    sc.za = p0 + 2 * wave == 0;
+    float* pr = buf + static_cast<size_t>(wave) * ppitch;
+    wave_dst_core<P>(pr, ty.tw, w64, sc);
+    wave_dst_core<P>(pr, ty.tw, w64);
+  }
+  __syncthreads();
+  float* out = a.out + fld * plane + p0 + c + static_cast<size_t>(j0) * nx;
+  const float* r = buf + lcol;
+  if (fld == 0 && a.out_dy) {
+    // -d_y by central differences, zero on the boundary rows j = 0 and the
+    // clamped neighbour beyond j = ny - 1; j + 1 (j - 1) crosses a padding
+    // gap exactly when j0 + 1 (j0) is a multiple of 32
+    float* dy = a.out_dy + p0 + c + static_cast<size_t>(j0) * nx;
+    const float mihy = static_cast<float>(-0.5 / g.hy);
+    const int up = 1 + ((j0 + 1) % 32 == 0), dn = -1 - (j0 % 32 == 0);
+    for_iters<NIT>([&](int it) {
+      const float* q = r + it * LS;
+      const int j = j0 + it * JS;
+      // the neighbour reads stay inside the strip (clamped at the two ends)
+      const float v = q[0];
+      const float vu = j + 1 < n ? q[it == NIT - 1 && j0 == JS - 1 ? 0 : up] : 0.f;
+      const float vd = j > 0 ? q[it == 0 && j0 == 0 ? 0 : dn] : 0.f;
+      out[static_cast<size_t>(it) * JS * nx] = v;
+      dy[static_cast<size_t>(it) * JS * nx] = j > 0 ? mihy * (vu - vd) : 0.f;
+    });
+  } else {
+    for_iters<NIT>([&](int it) { out[static_cast<size_t>(it) * JS * nx] = r[it * LS]; });
+  }
 }
 
 // DST along y, eigenvalue division, inverse DST along y (and -d_y for
@@ -806,6 +987,15 @@ template <typename T, int LOGN>
 __device__ __forceinline__ void col_block(const Geom& g, const ColArgs<T>& a,
                                           const AxisTables<T>& ty, const double* __restrict__ lamx,
                                           int strip, int fld, unsigned char* smem_raw) {
+  if constexpr (fast_core(sizeof(T), 1 << LOGN)) {
+    if (a.w == 8)
+      col_block_core<LOGN, 8>(g, a, ty, lamx, strip, fld, smem_raw);
+    else if (a.w == 4)
+      col_block_core<LOGN, 4>(g, a, ty, lamx, strip, fld, smem_raw);
+    else
+      col_block_core<LOGN, 2>(g, a, ty, lamx, strip, fld, smem_raw);
+    return;
+  }
   __syncthreads();   // the workgroup's previous use of LDS is complete
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int ny = g.ny, nx = g.nx;
@@ -816,9 +1006,13 @@ __device__ __forceinline__ void col_block(const Geom& g, const ColArgs<T>& a,
   const Cplx<T>* tw;
   const T* pre;
   stage_tables<T, LOGN>(ty, tbase, tw, pre);
-  double* slam = reinterpret_cast<double*>(tbase + table_bytes<T>(ny));
-  stage_doubles<(1 << LOGN)>(slam, ty.lam);
-  double* slamx = slam + ny;   // the strip's x eigenvalues
+  double* slamx = reinterpret_cast<double*>(tbase + table_bytes<T>(ny));   // the strip's
+  const double* slam = ty.lam;                                              // x, y eigenvalues
+  if constexpr (!fast_core(sizeof(T), 1 << LOGN)) {
+    stage_doubles<(1 << LOGN)>(slamx, ty.lam);
+    slam = slamx;
+    slamx += ny;
+  }
   if (static_cast<int>(threadIdx.x) < W) slamx[threadIdx.x] = lamx[strip * W + threadIdx.x];
   const size_t plane = static_cast<size_t>(nx) * ny;
   const T* in = a.in + fld * plane;
@@ -830,14 +1024,15 @@ __device__ __forceinline__ void col_block(const Geom& g, const ColArgs<T>& a,
   __syncthreads();
   block_dst<T, LOGN>(buf, g.ly, W, ppitch, tw, pre);
   const double shift = a.shift[fld];
-  const double norm = 4.0 / (static_cast<double>(nx) * ny);
+  // 1 / normalisation (nx ny / 4, exact): the eigenvalue sum in FP64 without
+  // a division, the one division in the field precision
+  const double inorm = 0.25 * static_cast<double>(nx) * ny;
   for_elems(W * ny, [&](int e) {
     const int c = e >> ly, q = e & (ny - 1);
     const int p = p0 + c;
     T* r = buf + Pad<T>::rpos(ny, ppitch, c, 0);
     const int iq = Pad<T>::ridx(q);
-    // the eigenvalue sum in FP64, the division in the field precision
-    const T den = static_cast<T>((slamx[c] + slam[q] - shift) / norm);
+    const T den = static_cast<T>((slamx[c] + slam[q] - shift) * inorm);
     const T v = r[iq] / den;
     r[iq] = (p > 0 && q > 0) ? v : T(0);
   });
@@ -863,23 +1058,22 @@ __device__ __forceinline__ void col_block(const Geom& g, const ColArgs<T>& a,
 // Each workgroup leaves its two sums in a.partial; the next trial push (or
 // the real push after the last iteration) forms the relative change and
 // decides convergence.
-template <typename T, int LOGN>
+template <typename T, int LOGN, int RC>
 __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>& a,
                                                  const AxisTables<T>& tx, int bxi, int fld,
                                                  unsigned char* smem_raw) {
   __syncthreads();   // the workgroup's previous use of LDS is complete
   T* buf = reinterpret_cast<T*>(smem_raw);
-  const int n = g.nx;
-  const int R = g.rr;
+  constexpr int n = 1 << LOGN;   // = nx
+  const int R = RC > 0 ? RC : g.rr;
   const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
   const T* pre;
   stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int j0 = bxi * R;
   const T* in = a.in + static_cast<size_t>(fld) * g.nx * g.ny;
-  const int lx = g.lx;
-  for_elems<32>(R * n, [&](int e) {
-    const int r = e >> lx, i = e & (n - 1);
+  for_row_elems<RC, LOGN, 32>(R, [&](int e) {
+    const int r = e >> LOGN, i = e & (n - 1);
     buf[Pad<T>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
   });
   __syncthreads();
@@ -887,8 +1081,8 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
   T* b = fld == 0 ? a.bx : a.by;
   T* tp = fld == 0 ? a.tape_bx : a.tape_by;
   double dsum = 0.0, nsum = 0.0;
-  for_elems<32>(R * n, [&](int e) {
-    const int r = e >> lx, i = e & (n - 1);
+  for_row_elems<RC, LOGN, 32>(R, [&](int e) {
+    const int r = e >> LOGN, i = e & (n - 1);
     const int j = j0 + r;
     const T v = buf[Pad<T>::rpos(n, ppitch, r, i)];
     const T u = j > 0 ? v : T(0);
@@ -917,6 +1111,7 @@ int row_rows(int nx, int ny) {
   const int waves = nx <= 512 ? 1 : (sizeof(T) == 8 || core ? 4 : 2);
   int r = 2 * per * dst_detail::pass_waves("QSP_ROW_WAVES", waves);
   if (r > ny) r = ny;
+  if (r > 2 * per * (kBlock / 64)) r = 2 * per * (kBlock / 64);   // one pair group per wave
   while (r > 2 && dst_detail::pass_lds<T>(r, nx) > 147456) r >>= 1;
   return r;
 }

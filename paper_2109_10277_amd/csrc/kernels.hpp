@@ -280,21 +280,22 @@ void launch_to_nodes_t(const Geom&, const T* src, T* dst, hipStream_t);
 
 // ---------------------------------------------------------------- beams
 struct BeamScratch {
-  int* keys_in;
-  int* keys_out;
-  int* idx_in;
-  int* idx_out;
-  int* counts;          // nzeta + 1
-  void* temp;           // radix-sort scratch
-  size_t temp_bytes;
+  int* hist;            // [nchunk][nzeta + 1] per-chunk key counts, then their prefixes
+  int* total;           // [nzeta + 1] particles per key
+  int64_t* off;         // [nzeta + 2] first particle of each key, then n
+  int nchunk;           // chunks the scratch holds
 };
+
+// Largest key count (nzeta + 1) of the slice sort: its per-chunk counters
+// live in 64 KiB of LDS.
+constexpr int kMaxBeamKeys = 16384;
 
 // Stable sort of a [7][n] float SoA beam by nearest slice; offsets[k] is the
 // first sorted particle of slice k (offsets[nzeta] = particles inside the
 // box, offsets[nzeta+1] = n).  Synchronises the stream.
 void beam_sort(const float* in, float* out, int64_t n, double zeta_hi, double dzeta, int nzeta,
                BeamScratch& s, std::vector<int64_t>& offsets, hipStream_t st);
-size_t beam_sort_temp_bytes(int64_t n, int nzeta);
+int beam_sort_chunks(int64_t n);
 void launch_beam_deposit(const Geom&, const float* soa, int64_t n, int64_t start, int64_t count,
                          double dzeta, double* rho_mjz, double* jz, double* rho, hipStream_t);
 template <typename T>

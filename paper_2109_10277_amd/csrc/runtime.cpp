@@ -315,18 +315,17 @@ class Box final : public BoxBase {
     free_beam();
     if (n == 0) return;
     const int nz = cfg_.nzeta;
-    const size_t temp = beam_sort_temp_bytes(n, nz);
-    const int64_t need = n * (14 * 4 + 16) + (nz + 1) * 4 + static_cast<int64_t>(temp);
+    if (nz + 1 > kMaxBeamKeys) throw std::invalid_argument("particle beams need nzeta < 16384");
+    const int nchunk = beam_sort_chunks(n);
+    const int64_t need = n * (14 * 4) + static_cast<int64_t>(nchunk + 1) * (nz + 1) * 4 +
+                         static_cast<int64_t>(nz + 2) * 8;
     if (cfg_.mem_cap_bytes > 0 && bytes_ + need > cfg_.mem_cap_bytes) throw std::bad_alloc();
     beam_soa_ = beam_alloc<float>(7 * n);
     beam_tmp_ = beam_alloc<float>(7 * n);
-    bs_.keys_in = beam_alloc<int>(n);
-    bs_.keys_out = beam_alloc<int>(n);
-    bs_.idx_in = beam_alloc<int>(n);
-    bs_.idx_out = beam_alloc<int>(n);
-    bs_.counts = beam_alloc<int>(nz + 1);
-    bs_.temp = beam_alloc<unsigned char>(temp);
-    bs_.temp_bytes = temp;
+    bs_.hist = beam_alloc<int>(static_cast<size_t>(nchunk) * (nz + 1));
+    bs_.total = beam_alloc<int>(nz + 1);
+    bs_.off = beam_alloc<int64_t>(nz + 2);
+    bs_.nchunk = nchunk;
     beam_n_ = n;
     beam_dt_ = dt;
     moving_beam_ = dt != 0.0;

@@ -247,6 +247,28 @@ def test_particle_beam_box_matches_oracle(prec):
         assert d <= (2e-6 if prec == "fp64" else 2e-4) * scale + 1e-12, (name, d, scale)
 
 
+@pytest.mark.parametrize("n", [1, 4095, 4096, 5 * 4096 + 123])
+def test_beam_sort_stable_across_chunks(n):
+    """The slice sort over several 4096-particle chunks with a ragged tail,
+    keys spread over every slice, particles ahead of and behind the box and
+    runs of equal keys: the sorted beam must be the stable argsort of the
+    nearest-slice keys (particles outside the box last)."""
+    cfg, _ = W.small_particle_beam(n=16, nzeta=300)
+    rng = np.random.default_rng(1234 + n)
+    zeta = rng.uniform(cfg.zeta_hi - (cfg.nzeta + 20) * cfg.dzeta, cfg.zeta_hi + 10 * cfg.dzeta, n)
+    zeta[: n // 3] = cfg.zeta_hi - 7 * cfg.dzeta     # a long run of one key
+    soa = np.stack([np.arange(n, dtype=np.float64)] + [rng.normal(size=n) for _ in range(6)])
+    soa[2] = zeta
+    soa = soa.astype(np.float32)
+    with Q().Box(cfg, "fp32") as box:
+        box.set_beam_particles(torch.tensor(soa, device="cuda"), 0.0)
+        got = box.get_beam_particles().cpu().numpy()
+    keys = O.beam_slice_index(cfg, soa[2].astype(np.float64))
+    keys = np.where((keys >= 0) & (keys < cfg.nzeta), keys, cfg.nzeta)
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(got, soa[:, order])
+
+
 def test_beam_sort_and_counts():
     cfg, beam = W.small_particle_beam()
     with Q().Box(cfg, "fp32") as box:
