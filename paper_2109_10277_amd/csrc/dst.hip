@@ -44,14 +44,14 @@ k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
       const double jx_n = j + 1 < g.ny ? xn : 0.0, jy_n = j + 1 < g.ny ? yn : 0.0;
       s = fld == 1 ? (jx_e - xw) * ihx + (jy_n - ys) * ihy : (jx_n - xs) * ihy - (jy_e - yw) * ihx;
     }
-    buf[Pad<T>::rpos(n, ppitch, r, i)] = static_cast<T>((i > 0 && j > 0) ? s : 0.0);
+    buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)] = static_cast<T>((i > 0 && j > 0) ? s : 0.0);
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.out + static_cast<size_t>(fld) * g.nx * g.ny;
   for_row_elems<RC, LOGN>(R, [&](int e) {
     const int r = e >> LOGN, i = e & (n - 1);
-    out[(j0 + r) * n + i] = buf[Pad<T>::rpos(n, ppitch, r, i)];
+    out[(j0 + r) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)];
   });
 }
 
@@ -71,10 +71,12 @@ __global__ void __launch_bounds__(kBlock, col_blocks_per_cu(LOGN, sizeof(T)))
 k_col_solve(Geom g, ColArgs<T> a, AxisTables<T> ty, const double* __restrict__ lamx,
             const DevCounters* ctr) {
   if (a.honor_done && ctr->pc_done) return;
-  zero_job(a.zero, static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x,
-           static_cast<size_t>(gridDim.x) * gridDim.y);
   extern __shared__ unsigned char smem_raw[];
   col_block<T, LOGN>(g, a, ty, lamx, xcd_strip(blockIdx.x, gridDim.x), blockIdx.y, smem_raw);
+  // the side job's stores come last: the memory counter the strip load waits
+  // on also counts stores
+  zero_job(a.zero, static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x,
+           static_cast<size_t>(gridDim.x) * gridDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -96,7 +98,7 @@ k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   const T* in = a.in[fld];
   for_row_elems<RC, LOGN, 32>(R, [&](int e) {
     const int r = e >> LOGN, i = e & (n - 1);
-    buf[Pad<T>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
+    buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
@@ -107,11 +109,11 @@ k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   for_row_elems<RC, LOGN>(R, [&](int e) {
     const int r = e >> LOGN, i = e & (n - 1);
     const int j = j0 + r;
-    const T* row = buf + Pad<T>::rpos(n, ppitch, r, 0);
-    const T u = row[Pad<T>::ridx(i)];
+    const T* row = buf + RowLay<T, LOGN>::rpos(n, ppitch, r, 0);
+    const T u = row[RowLay<T, LOGN>::ridx(i)];
     out[j * n + i] = j > 0 ? u : T(0);
     if (out_dx) {
-      const T ue = row[Pad<T>::ridx(i + 1 < n ? i + 1 : i)], uw = row[Pad<T>::ridx(i > 0 ? i - 1 : 0)];
+      const T ue = row[RowLay<T, LOGN>::ridx(i + 1 < n ? i + 1 : i)], uw = row[RowLay<T, LOGN>::ridx(i > 0 ? i - 1 : 0)];
       const T d = mihx * ((i + 1 < n ? ue : T(0)) - uw);
       out_dx[j * n + i] = (i > 0 && j > 0) ? d : T(0);
     }

@@ -340,6 +340,23 @@ __device__ __forceinline__ void wave_dst(T* g, int npg, int ppitch, const Cplx<T
 // ---------------------------------------------------------------------------
 constexpr int kCorePitch = 72;   // complex entries per k1 row of the transposes
 
+// Row layout in LDS around the FP32 core (gfx950 serves LDS as 32 banks of 4
+// bytes, half a wave at a time): 4 padding words after every 32, row b of a
+// pair at an offset = 4 (mod 32), pairs 8 (mod 32) apart.  Then the core's
+// last-stage writes (k = kb + P c1 + const over the lanes kb < 4, c1 < 8 of
+// a half-wave) land on 32 distinct banks, and so do the column pass's strip
+// accesses (8 columns = 4 pairs x 2 rows, 4 consecutive rows each); runs of
+// 32 consecutive entries (row passes, the core's first stage) stay
+// contiguous.
+struct CoreLay {
+  __host__ __device__ static constexpr int ridx(int i) { return i + 4 * (i >> 5); }
+  // offset of row b in the pair (named as in Pad)
+  __host__ __device__ static constexpr int rlen(int n) { return ((ridx(n) + 31) & ~31) + 4; }
+  __host__ __device__ static constexpr int rpos(int n, int pitch, int r, int i) {
+    return (r >> 1) * pitch + (r & 1) * rlen(n) + ridx(i);
+  }
+};
+
 // W_32^k = e^{-2 pi i k / 32} for k >= 0 (from cos(2 pi k / 32), k = 0..8;
 // W_32^{k+16} = -W_32^k).  Called with compile-time k only.
 __device__ __forceinline__ Cplx<float> w32(int k) {
@@ -429,7 +446,7 @@ template <int P, typename Epi = NoScale>
 __device__ __forceinline__ void wave_dst_core(float* g, const Cplx<float>* __restrict__ twa,
                                               const Cplx<float>* __restrict__ w64,
                                               const Epi& epi = Epi{}) {
-  using Pd = Pad<float>;
+  using Pd = CoreLay;
   constexpr int n = 32 * P;
   constexpr int NB = P / 8;
   const int l = threadIdx.x & 63;
@@ -511,9 +528,13 @@ __device__ __forceinline__ void wave_dst_core(float* g, const Cplx<float>* __res
 // P rows of its transposes.
 template <typename T>
 __host__ __device__ inline int pair_pitch(int n) {
-  if (fast_core(sizeof(T), n)) return (n / 32) * kCorePitch * 2 + 2;
+  if (fast_core(sizeof(T), n)) return (n / 32) * kCorePitch * 2 + 8;   // = 8 (mod 32)
   return Pad<T>::pitch(n);
 }
+
+// The LDS row layout of a pass over rows of 2^LOGN values.
+template <typename T, int LOGN>
+using RowLay = std::conditional_t<fast_core(sizeof(T), 1 << LOGN), CoreLay, Pad<T>>;
 
 // Type-I sine transform of nrow rows (nrow even) of length n = 2^logn held
 // in LDS; pair f = rows (2f, 2f+1) occupies buf[f*ppitch ..) (row 2f first,
@@ -871,14 +892,14 @@ __device__ __forceinline__ void src_bxby_block(const Geom& g, const SrcBxBy<T>& 
       const double jz_e = i + 1 < n ? ze - amp * ge * gy : 0.0;
       s = (jz_e - jz_w) * ihx - (xp - xt) * idz - a.shift * bo;
     }
-    buf[Pad<T>::rpos(n, ppitch, r, i)] = static_cast<T>((i > 0 && j > 0) ? s : 0.0);
+    buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)] = static_cast<T>((i > 0 && j > 0) ? s : 0.0);
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.out + static_cast<size_t>(fld) * g.nx * g.ny;
   for_row_elems<RC, LOGN>(R, [&](int e) {
     const int r = e >> LOGN, i = e & (n - 1);
-    out[(j0 + r) * n + i] = buf[Pad<T>::rpos(n, ppitch, r, i)];
+    out[(j0 + r) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)];
   });
 }
 
@@ -897,19 +918,19 @@ __device__ __forceinline__ void for_iters(F&& f) {
 // columns): strip load, forward core whose output stage divides by the
 // eigenvalues, inverse core, store.  Thread t handles column c = t mod W and
 // rows j = t / W + it (256 / W); the row step is a multiple of 32, so the
-// padded LDS index ridx(j) = j + j / 32 is affine in it as well.
+// padded LDS index ridx(j) = j + 4 (j / 32) is affine in it as well.
 template <int LOGN, int W>
 __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<float>& a,
                                                const AxisTables<float>& ty,
                                                const double* __restrict__ lamx, int strip, int fld,
                                                unsigned char* smem_raw) {
-  using Pd = Pad<float>;
+  using Pd = CoreLay;
   constexpr int n = 1 << LOGN;
   constexpr int P = n / 32, NB = P / 8;
   constexpr int LW = W == 2 ? 1 : (W == 4 ? 2 : 3);
   constexpr int JS = kBlock / W;              // row step of a thread
   constexpr int NIT = n / JS;                 // rows per thread
-  constexpr int LS = JS + JS / 32;            // LDS step of ridx
+  constexpr int LS = Pd::ridx(JS);            // LDS step of ridx
   static_assert(JS % 32 == 0, "row step must keep the LDS padding affine");
   __syncthreads();   // the workgroup's previous use of LDS is complete
   float* buf = reinterpret_cast<float*>(smem_raw);
@@ -962,10 +983,10 @@ __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<floa
   if (fld == 0 && a.out_dy) {
     // -d_y by central differences, zero on the boundary rows j = 0 and the
     // clamped neighbour beyond j = ny - 1; j + 1 (j - 1) crosses a padding
-    // gap exactly when j0 + 1 (j0) is a multiple of 32
+    // gap (4 words) exactly when j0 + 1 (j0) is a multiple of 32
     float* dy = a.out_dy + p0 + c + static_cast<size_t>(j0) * nx;
     const float mihy = static_cast<float>(-0.5 / g.hy);
-    const int up = 1 + ((j0 + 1) % 32 == 0), dn = -1 - (j0 % 32 == 0);
+    const int up = Pd::ridx(j0 + 1) - Pd::ridx(j0), dn = Pd::ridx(j0 - 1) - Pd::ridx(j0);
     for_iters<NIT>([&](int it) {
       const float* q = r + it * LS;
       const int j = j0 + it * JS;
@@ -1074,7 +1095,7 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
   const T* in = a.in + static_cast<size_t>(fld) * g.nx * g.ny;
   for_row_elems<RC, LOGN, 32>(R, [&](int e) {
     const int r = e >> LOGN, i = e & (n - 1);
-    buf[Pad<T>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
+    buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
@@ -1084,7 +1105,7 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
   for_row_elems<RC, LOGN, 32>(R, [&](int e) {
     const int r = e >> LOGN, i = e & (n - 1);
     const int j = j0 + r;
-    const T v = buf[Pad<T>::rpos(n, ppitch, r, i)];
+    const T v = buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)];
     const T u = j > 0 ? v : T(0);
     const double old = static_cast<double>(b[j * n + i]);
     const double d = static_cast<double>(u) - old;

@@ -117,14 +117,14 @@ k_expl_setup(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     r[o] = r0;
     bn += b * b;
     rn += r0 * r0;
-    buf[Pad<T>::rpos(n, ppitch, rr, i)] = static_cast<T>(-r0);
+    buf[RowLay<T, LOGN>::rpos(n, ppitch, rr, i)] = static_cast<T>(-r0);
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.fwd + fld * plane;
   for_elems(R * n, [&](int e) {
     const int rr = e >> lx, i = e & (n - 1);
-    out[(j0 + rr) * n + i] = buf[Pad<T>::rpos(n, ppitch, rr, i)];
+    out[(j0 + rr) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, rr, i)];
   });
   double v[2] = {bn, rn};
   partials::store<2>(v, a.part_s, fld * (ny / R) + blockIdx.x);
@@ -172,7 +172,7 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   const int lx = g.lx;
   for_elems<32>(R * n, [&](int e) {
     const int rw = e >> lx, i = e & (n - 1);
-    buf[Pad<T>::rpos(n, ppitch, rw, i)] = in[(j0 + rw) * n + i];
+    buf[RowLay<T, LOGN>::rpos(n, ppitch, rw, i)] = in[(j0 + rw) * n + i];
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
@@ -185,7 +185,7 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     const int rw = e >> lx, i = e & (n - 1);
     const int j = j0 + rw;
     const int o = j * n + i;
-    const T u = buf[Pad<T>::rpos(n, ppitch, rw, i)];
+    const T u = buf[RowLay<T, LOGN>::rpos(n, ppitch, rw, i)];
     const T zv = (i > 0 && j > 0) ? u : T(0);
     z[o] = zv;
     zr += static_cast<double>(zv) * r[o];
@@ -309,14 +309,14 @@ k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     r[o] = rv;
     B[o] = static_cast<T>(xv);
     rn += rv * rv;
-    buf[Pad<T>::rpos(n, ppitch, rw, i)] = static_cast<T>(-rv);
+    buf[RowLay<T, LOGN>::rpos(n, ppitch, rw, i)] = static_cast<T>(-rv);
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* out = a.fwd + fld * plane;
   for_elems(R * n, [&](int e) {
     const int rw = e >> lx, i = e & (n - 1);
-    out[(j0 + rw) * n + i] = buf[Pad<T>::rpos(n, ppitch, rw, i)];
+    out[(j0 + rw) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, rw, i)];
   });
   double v[1] = {rn};
   partials::store<1>(v, a.part_u, fld * (ny / R) + blockIdx.x);
