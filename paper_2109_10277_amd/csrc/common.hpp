@@ -70,10 +70,17 @@ __host__ __device__ constexpr bool fast_core(int elem_size, int n) {
   return elem_size == 4 && n >= 256 && n <= 1024;
 }
 
+// Lanes that transform one row pair with the FP32 core: two waves (128) at
+// 1024 points, one wave (64) at 256 and 512.
+__host__ __device__ constexpr int core_lanes(int elem_size, int n) {
+  return fast_core(elem_size, n) && n >= 1024 ? 128 : 64;
+}
+
 // Per-axis transform tables (device pointers): for the half-length
 // transform tw[m] = e^{-2 pi i m / n} and pre[j] = sin(pi j / n); for the
-// FP32 core tw[k1 * 64 + l] = e^{-2 pi i l k1 / 2n} (2n entries) and pre
-// holds the complex table W_64^{la c1} at [la * 9 + c1].
+// FP32 core with NL = core_lanes lanes per pair tw[k1 * NL + l] =
+// e^{-2 pi i l k1 / 2n} (2n entries) and pre holds the complex table
+// W_NL^{la c1} at [la * 9 + c1] (la < NL / 8, c1 < 8, entry 8 of a row 0).
 template <typename T>
 struct AxisTables {
   const Cplx<T>* tw;

@@ -140,9 +140,14 @@ static void allow_lds(const void* fn, size_t lds) {
 }
 
 // Each wave transforms one group of row pairs (one pair for the FP32 core,
-// max(1, 512/n) otherwise): a pass must not give a workgroup more rows.
+// max(1, 512/n) otherwise; two waves per pair at 1024 with the FP32 core,
+// exactly two pairs): a pass must not give a workgroup more rows.
 template <typename T>
 static void check_rows(int n, int rows) {
+  if (core_lanes(sizeof(T), n) == 128) {   // the two-wave core needs all four waves busy
+    if (rows != 4) throw std::invalid_argument("transform pass: the two-wave core takes 4 rows");
+    return;
+  }
   const int per = fast_core(sizeof(T), n) || n >= 512 ? 1 : 512 / n;
   if (rows > 2 * per * (kBlock / 64))
     throw std::invalid_argument("transform pass: more row pairs than its waves take");

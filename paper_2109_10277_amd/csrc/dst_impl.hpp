@@ -342,16 +342,19 @@ constexpr int kCorePitch = 72;   // complex entries per k1 row of the transposes
 
 // Row layout in LDS around the FP32 core (gfx950 serves LDS as 32 banks of 4
 // bytes, half a wave at a time): 4 padding words after every 32, row b of a
-// pair at an offset = 4 (mod 32), pairs 8 (mod 32) apart.  Then the core's
-// last-stage writes (k = kb + P c1 + const over the lanes kb < 4, c1 < 8 of
-// a half-wave) land on 32 distinct banks, and so do the column pass's strip
-// accesses (8 columns = 4 pairs x 2 rows, 4 consecutive rows each); runs of
-// 32 consecutive entries (row passes, the core's first stage) stay
-// contiguous.
+// pair at an offset = 4 (mod 32), pairs 8 (mod 32) apart (at 1024 points: 8
+// and 16).  Then the core's last-stage writes (k = kb + P c1 + const over
+// the lanes kb < 4, c1 < 8 of a half-wave) land on 32 distinct banks, and
+// so do the column pass's strip accesses (8 columns = 4 pairs x 2 rows, 4
+// consecutive rows each; at 1024 points 4 columns, 8 rows each); runs of 32
+// consecutive entries (row passes, the core's first stage) stay contiguous.
 struct CoreLay {
   __host__ __device__ static constexpr int ridx(int i) { return i + 4 * (i >> 5); }
-  // offset of row b in the pair (named as in Pad)
-  __host__ __device__ static constexpr int rlen(int n) { return ((ridx(n) + 31) & ~31) + 4; }
+  // offset of row b in the pair (named as in Pad): = 4 (mod 32), or = 8 at
+  // 1024 points, whose column strips are 4 columns (2 pairs) wide
+  __host__ __device__ static constexpr int rlen(int n) {
+    return ((ridx(n) + 31) & ~31) + (n >= 1024 ? 8 : 4);
+  }
   __host__ __device__ static constexpr int rpos(int n, int pitch, int r, int i) {
     return (r >> 1) * pitch + (r & 1) * rlen(n) + ridx(i);
   }
@@ -412,34 +415,41 @@ __device__ __forceinline__ void dft_reg(Cplx<float>* v) {
 // wave, in place; twa[k1 * 64 + l] = W_N^{l k1} (global memory), w64[la * 9
 // + c1] = W_64^{la c1} (LDS).  The pair's region holds P rows of kCorePitch
 // complex.
-// Output scaling of the core: none (plain transform).
+// Output scaling of the core: none (plain transform).  The cores call
+// epi(q, oa, ob) for their q-th output slot of the lane.
 struct NoScale {
-  __device__ void operator()(int, int, float&, float&) const {}
+  __device__ void operator()(int, float&, float&) const {}
 };
 
 // Output scaling of the core in the column pass: S_k of the pair's columns
 // p_a, p_b divided by (lambda_x(p) + lambda_y(k) - shift) nx ny / 4, the
 // eigenvalue of the shifted Laplacian times the two transforms'
 // normalisation; column p = 0 (a boundary node line) is zero.  ry holds
-// (lambda_y(k) - shift) nx ny / 4 for the lane's 4 NB outputs k (see the
-// core's B2 stage), xa / xb lambda_x(p) nx ny / 4.
-template <int NB>
+// (lambda_y(k) - shift) nx ny / 4 for the lane's NK output slots k (see
+// core_out_k), xa / xb lambda_x(p) nx ny / 4.
+template <int NK>
 struct EigenScale {
-  float ry[NB][4];
+  float ry[NK];
   float xa, xb;
   bool za;
-  __device__ void operator()(int t, int c2, float& oa, float& ob) const {
-    const float ra = __builtin_amdgcn_rcpf(xa + ry[t][c2]);
-    const float rb = __builtin_amdgcn_rcpf(xb + ry[t][c2]);
+  __device__ void operator()(int q, float& oa, float& ob) const {
+    const float ra = __builtin_amdgcn_rcpf(xa + ry[q]);
+    const float rb = __builtin_amdgcn_rcpf(xb + ry[q]);
     oa = za ? 0.f : oa * ra;
     ob *= rb;
   }
 };
 
-// The output index k of the core's register (t, c2) in lane l.
+// Output slots of a lane: the one-wave core (P points per lane, lane l)
+// writes k = (l >> 3) + 8 t + P (l & 7) + 8 P c2 in slot q = 4 t + c2; the
+// two-wave core (n = 1024, lane L of 128) k = k1 + 16 c1 + 128 q with
+// k1 = 8 (L >> 6) + ((L & 63) >> 3), c1 = L & 7.
 template <int P>
-__device__ __forceinline__ int core_out_k(int l, int t, int c2) {
-  return (l >> 3) + 8 * t + P * (l & 7) + 8 * P * c2;
+__device__ __forceinline__ int core_out_k(int l, int q) {
+  return (l >> 3) + 8 * (q >> 2) + P * (l & 7) + 8 * P * (q & 3);
+}
+__device__ __forceinline__ int core2_out_k(int L, int q) {
+  return 8 * (L >> 6) + ((L & 63) >> 3) + 16 * (L & 7) + 128 * q;
 }
 
 template <int P, typename Epi = NoScale>
@@ -516,7 +526,7 @@ __device__ __forceinline__ void wave_dst_core(float* g, const Cplx<float>* __res
       const int k = k0 + 8 * P * c2;
       const int j = Pd::ridx(k);
       float oa = -0.5f * u[t][c2].im, ob = 0.5f * u[t][c2].re;
-      epi(t, c2, oa, ob);
+      epi(4 * t + c2, oa, ob);
       ra[j] = k ? oa : 0.f;
       rb[j] = k ? ob : 0.f;
     }
@@ -524,10 +534,110 @@ __device__ __forceinline__ void wave_dst_core(float* g, const Cplx<float>* __res
   wave_sync();
 }
 
+// ---------------------------------------------------------------------------
+// Two-wave FP32 core for rows of n = 1024 points: the pair's 128 lanes share
+// the N = 2048-point FFT, 16 points per lane, so that twice as many waves
+// (two per SIMD on a full grid) hide each other's latencies:
+//   A   lane L: DFT_16 over m of z_{L + 128 m}, times W_N^{L k1} (k = k1 +
+//       16 k2), into row k1 of the transpose region; one workgroup barrier;
+//   B1  DFT_128 over L split as 16 x 8 (L = la + 16 lb, k2 = c1 + 8 c2):
+//       DFT_8 over lb, times W_128^{la c1}; wave w of the pair owns rows
+//       k1 = 8 w .. 8 w + 7 from here on (no more barriers);
+//   B2  DFT_16 over la, outputs k = k1 + 16 c1 + 128 c2 for c2 < 8.
+// The transposes use a region of their own after the rows (rows of 152
+// complex: the strided reads and writes of B1 and B2 meet every bank once
+// per 16 lanes), so the first stage reads its rows without a barrier before
+// its writes.  Every thread of the workgroup must call it (its barrier);
+// the caller synchronises the workgroup before the rows are read again.
+// ---------------------------------------------------------------------------
+constexpr int kCore2Pitch = 152;   // complex entries per k1 row of the transposes
+
+__host__ __device__ constexpr int core2_soff(int n) {   // floats before the transposes
+  return (CoreLay::rlen(n) + CoreLay::ridx(n) + 31) & ~31;
+}
+
+template <typename Epi = NoScale>
+__device__ __forceinline__ void pair2_dst_core(float* g, int L, const Cplx<float>* __restrict__ twa,
+                                               const Cplx<float>* __restrict__ w128,
+                                               const Epi& epi = Epi{}) {
+  using Pd = CoreLay;
+  constexpr int n = 1024, P = 16;
+  float* ra = g;
+  float* rb = g + Pd::rlen(n);
+  Cplx<float>* s = reinterpret_cast<Cplx<float>*>(g + core2_soff(n));
+  // A: z_{L + 128 m}; m >= 8 from the mirror 2n - j = 128 (16 - m) - L
+  Cplx<float> v[P];
+#pragma unroll
+  for (int m = 0; m < P / 2; ++m) {
+    const int j = Pd::ridx(L + 128 * m);
+    v[m] = {ra[j], rb[j]};
+  }
+#pragma unroll
+  for (int m = P / 2; m < P; ++m) {
+    const int jm = 128 * (P - m) - L;         // in [1, n], n only for L = 0, m = 8
+    const int j = Pd::ridx(jm < n ? jm : 0);
+    const float fa = ra[j], fb = rb[j];
+    v[m] = {jm < n ? -fa : 0.f, jm < n ? -fb : 0.f};
+  }
+  dft_reg<P>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < P; ++k1) {
+    const Cplx<float> y = v[dft_pos<P>(k1)];
+    s[k1 * kCore2Pitch + L] = k1 ? cmul(y, twa[k1 * 128 + L]) : y;
+  }
+  __syncthreads();
+  // B1: lane (la, kb) of wave w handles rows k1 = 8 w + kb + 4 t
+  const int l6 = L & 63, w = L >> 6;
+  const int la = l6 & 15, kb = l6 >> 4;
+  Cplx<float> u[2][8];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const Cplx<float>* r = s + (8 * w + kb + 4 * t) * kCore2Pitch + la;
+#pragma unroll
+    for (int lb = 0; lb < 8; ++lb) u[t][lb] = r[16 * lb];
+  }
+  Cplx<float> wl[8];
+  wl[0] = {1.f, 0.f};
+#pragma unroll
+  for (int c1 = 1; c1 < 8; ++c1) wl[c1] = w128[la * 9 + c1];
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    dft8(u[t]);
+    Cplx<float>* r = s + (8 * w + kb + 4 * t) * kCore2Pitch + la * 9;
+    r[0] = u[t][0];
+#pragma unroll
+    for (int c1 = 1; c1 < 8; ++c1) r[c1] = cmul(u[t][c1], wl[c1]);
+  }
+  wave_sync();
+  // B2: lane (k1, c1) = (8 w + l6 >> 3, l6 & 7); DFT_16 over la
+  const int k1 = 8 * w + (l6 >> 3), c1 = l6 & 7;
+  Cplx<float> x[P];
+  {
+    const Cplx<float>* r = s + k1 * kCore2Pitch + c1;
+#pragma unroll
+    for (int a = 0; a < P; ++a) x[a] = r[9 * a];
+  }
+  dft_reg<P>(x);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const Cplx<float> y = x[dft_pos<P>(q)];
+    const int k = k1 + 16 * c1 + 128 * q;
+    const int j = Pd::ridx(k);
+    float oa = -0.5f * y.im, ob = 0.5f * y.re;
+    epi(q, oa, ob);
+    ra[j] = k ? oa : 0.f;
+    rb[j] = k ? ob : 0.f;
+  }
+}
+
 // Floats per row pair in LDS: the two padded rows, or for the FP32 core the
-// P rows of its transposes.
+// P rows of its transposes (which the one-wave core lays over the rows), or
+// for the two-wave core the rows followed by its transposes.
 template <typename T>
 __host__ __device__ inline int pair_pitch(int n) {
+  if (fast_core(sizeof(T), n) && core_lanes(sizeof(T), n) == 128)   // rows, transposes; = 16 (mod 32)
+    return core2_soff(n) + (n / 64) * kCore2Pitch * 2 + 16;
   if (fast_core(sizeof(T), n)) return (n / 32) * kCorePitch * 2 + 8;   // = 8 (mod 32)
   return Pad<T>::pitch(n);
 }
@@ -552,11 +662,17 @@ __device__ __forceinline__ void block_dst(T* buf, int logn, int nrow, int ppitch
   const int npair = nrow >> 1;
   const int wave = threadIdx.x >> 6;
   if constexpr (fast_core(sizeof(T), n)) {
-    // tw: W_N^{l k1} by [k1][lane]; pre: the W_64 table (complex)
-    // one pair per wave (the launchers keep nrow <= 2 * waves): no loop,
-    // whose invariant hoisting would keep the core's per-lane addresses live
-    const Cplx<float>* w64 = reinterpret_cast<const Cplx<float>*>(pre);
-    if (wave < npair) wave_dst_core<n / 32>(buf + static_cast<size_t>(wave) * ppitch, tw, w64);
+    // tw: W_N^{l k1} by [k1][lane]; pre: the W_64 (W_128) table (complex)
+    const Cplx<float>* wt = reinterpret_cast<const Cplx<float>*>(pre);
+    if constexpr (core_lanes(sizeof(T), n) == 128) {
+      // two waves per pair, every thread (the launchers give 4 rows: 2 pairs)
+      const int pr = threadIdx.x >> 7;
+      pair2_dst_core(buf + static_cast<size_t>(pr) * ppitch, threadIdx.x & 127, tw, wt);
+    } else {
+      // one pair per wave (the launchers keep nrow <= 2 * waves): no loop,
+      // whose invariant hoisting would keep the core's per-lane addresses live
+      if (wave < npair) wave_dst_core<n / 32>(buf + static_cast<size_t>(wave) * ppitch, tw, wt);
+    }
   } else {
     constexpr int per = n >= 512 ? 1 : 512 / n;
     constexpr int E = n <= 512 ? 8 : n / 64;
@@ -589,10 +705,11 @@ void with_logn(int n, F&& f) {
 
 // Bytes of the per-axis tables a transform pass stages in LDS: twiddles and
 // pre-twiddles of the half-length transform, or for the FP32 core the W_64
-// table (72 complex; its W_N^{l k1} table is read from global memory).
+// or W_128 table (72 or 144 complex; its W_N^{l k1} table is read from
+// global memory).
 template <typename T>
 __host__ __device__ inline size_t table_bytes(int n) {
-  if (fast_core(sizeof(T), n)) return static_cast<size_t>(72) * sizeof(Cplx<T>);
+  if (fast_core(sizeof(T), n)) return static_cast<size_t>(core_lanes(sizeof(T), n) / 8 * 9) * sizeof(Cplx<T>);
   return static_cast<size_t>(n) * (sizeof(Cplx<T>) + sizeof(T));
 }
 
@@ -626,11 +743,12 @@ inline size_t pass_lds(int rows, int n) {
 // 256 rows (FP64); beyond, two, whose four-column strips halve the strided
 // row segments each workgroup reads (measured from HIP graphs: 8 % off a
 // 1024^2 time step in FP32, 2 % off the 512^2 box in FP64).
-// The FP32 core at 1024 rows: four busy waves (eight-column strips, 32-byte
-// row segments), two workgroups per CU.
+// The FP32 core at 1024 rows: two pairs of two waves (four-column strips),
+// two workgroups per CU.
 template <typename T>
 inline int col_strip(int nx, int ny, int nfield) {
   (void)nfield;
+  if (core_lanes(sizeof(T), ny) == 128) return 4;   // two-wave core: two pairs per workgroup
   const bool core = fast_core(sizeof(T), ny);
   const int per = ny >= 512 || core ? 1 : 512 / ny;
   const int waves = core ? (ny >= 1024 ? 4 : 1) : (ny >= (sizeof(T) == 8 ? 512 : 1024) ? 2 : 1);
@@ -658,10 +776,10 @@ __device__ inline void stage_tables(const AxisTables<T>& t, unsigned char* base,
   if constexpr (fast_core(sizeof(T), n)) {
     // the W_N^{l k1} table (2n entries by [k1][lane]) stays in global
     // memory, where each wave reads it coalesced (L1/L2 resident); the 72
-    // entries of W_64 go to LDS
+    // (144) entries of W_64 (W_128) go to LDS
     Cplx<T>* sw = stw;
     const Cplx<T>* gw = reinterpret_cast<const Cplx<T>*>(t.pre);
-    if (threadIdx.x < 72) sw[threadIdx.x] = gw[threadIdx.x];
+    if (threadIdx.x < core_lanes(sizeof(T), n) / 8 * 9) sw[threadIdx.x] = gw[threadIdx.x];
     tw = t.tw;
     pre = reinterpret_cast<const T*>(sw);
   } else {
@@ -832,11 +950,15 @@ __device__ __forceinline__ void for_row_elems(int R, F&& f) {
     for_elems<CH>(R << LOGN, f);
 }
 
-// Runs f(std::integral_constant<int, RC>) with RC = R (2, 4 or 8) for row
-// passes of the FP32 core, RC = 0 (rows at run time) otherwise.
+// Runs f(std::integral_constant<int, RC>) with RC = R (2, 4 or 8; 4 for
+// the two-wave core) for row passes of the FP32 core, RC = 0 (rows at run
+// time) otherwise.
 template <typename T, int LOGN, typename F>
 void with_rows(int R, F&& f) {
-  if constexpr (fast_core(sizeof(T), 1 << LOGN)) {
+  if constexpr (core_lanes(sizeof(T), 1 << LOGN) == 128) {   // the two-wave core: 4 rows only
+    if (R != 4) throw std::invalid_argument("row pass: the two-wave core takes 4 rows");
+    f(std::integral_constant<int, 4>{});
+  } else if constexpr (fast_core(sizeof(T), 1 << LOGN)) {
     switch (R) {
       case 2: f(std::integral_constant<int, 2>{}); break;
       case 4: f(std::integral_constant<int, 4>{}); break;
@@ -915,8 +1037,8 @@ __device__ __forceinline__ void for_iters(F&& f) {
 }
 
 // Column pass with the FP32 core (n = ny = 256..1024, W = 2, 4 or 8
-// columns): strip load, forward core whose output stage divides by the
-// eigenvalues, inverse core, store.  Thread t handles column c = t mod W and
+// columns; at 1024 the two-wave core on 4 columns): strip load, forward
+// core whose output stage divides by the eigenvalues, inverse core, store.  Thread t handles column c = t mod W and
 // rows j = t / W + it (256 / W); the row step is a multiple of 32, so the
 // padded LDS index ridx(j) = j + 4 (j / 32) is affine in it as well.
 template <int LOGN, int W>
@@ -926,32 +1048,35 @@ __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<floa
                                                unsigned char* smem_raw) {
   using Pd = CoreLay;
   constexpr int n = 1 << LOGN;
+  constexpr bool two = core_lanes(4, n) == 128;   // two waves per pair (W = 4)
   constexpr int P = n / 32, NB = P / 8;
+  constexpr int NK = two ? 8 : 4 * NB;            // output slots per lane
   constexpr int LW = W == 2 ? 1 : (W == 4 ? 2 : 3);
   constexpr int JS = kBlock / W;              // row step of a thread
   constexpr int NIT = n / JS;                 // rows per thread
   constexpr int LS = Pd::ridx(JS);            // LDS step of ridx
   static_assert(JS % 32 == 0, "row step must keep the LDS padding affine");
+  static_assert(!two || W == 4, "the two-wave core takes four-column strips");
   __syncthreads();   // the workgroup's previous use of LDS is complete
   float* buf = reinterpret_cast<float*>(smem_raw);
   const int nx = g.nx;
   const int ppitch = pair_pitch<float>(n);
   const int p0 = strip * W;
   const int tid = static_cast<int>(threadIdx.x);
-  const int wave = tid >> 6, l = tid & 63;
-  const bool busy = wave < W / 2;
-  Cplx<float>* w64 = reinterpret_cast<Cplx<float>*>(smem_raw + static_cast<size_t>(W / 2) * ppitch * sizeof(float));
-  if (tid < 72) w64[tid] = reinterpret_cast<const Cplx<float>*>(ty.pre)[tid];
+  const int pr = two ? tid >> 7 : tid >> 6;     // the thread's pair
+  const int l = two ? tid & 127 : tid & 63;     // its lane in the pair
+  const bool busy = two || pr < W / 2;
+  constexpr int NWT = core_lanes(4, n) / 8 * 9;
+  Cplx<float>* wt = reinterpret_cast<Cplx<float>*>(smem_raw + static_cast<size_t>(W / 2) * ppitch * sizeof(float));
+  if (tid < NWT) wt[tid] = reinterpret_cast<const Cplx<float>*>(ty.pre)[tid];
   // the y eigenvalues of the lane's core outputs, fetched under the strip load
-  double ly[NB][4];
+  double ly[NK];
   double lxa = 0.0, lxb = 0.0;
   if (busy) {
 #pragma unroll
-    for (int t = 0; t < NB; ++t)
-#pragma unroll
-      for (int c2 = 0; c2 < 4; ++c2) ly[t][c2] = ty.lam[core_out_k<P>(l, t, c2)];
-    lxa = lamx[p0 + 2 * wave];
-    lxb = lamx[p0 + 2 * wave + 1];
+    for (int q = 0; q < NK; ++q) ly[q] = ty.lam[two ? core2_out_k(l, q) : core_out_k<P>(l, q)];
+    lxa = lamx[p0 + 2 * pr];
+    lxb = lamx[p0 + 2 * pr + 1];
   }
   const size_t plane = static_cast<size_t>(nx) * n;
   const int c = tid & (W - 1), j0 = tid >> LW;
@@ -965,17 +1090,21 @@ __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<floa
   if (busy) {
     const double shift = a.shift[fld];
     const double inorm = 0.25 * static_cast<double>(nx) * n;
-    EigenScale<NB> sc;
+    EigenScale<NK> sc;
 #pragma unroll
-    for (int t = 0; t < NB; ++t)
-#pragma unroll
-      for (int c2 = 0; c2 < 4; ++c2) sc.ry[t][c2] = static_cast<float>((ly[t][c2] - shift) * inorm);
+    for (int q = 0; q < NK; ++q) sc.ry[q] = static_cast<float>((ly[q] - shift) * inorm);
     sc.xa = static_cast<float>(lxa * inorm);
     sc.xb = static_cast<float>(lxb * inorm);
-    sc.za = p0 + 2 * wave == 0;
-    float* pr = buf + static_cast<size_t>(wave) * ppitch;
-    wave_dst_core<P>(pr, ty.tw, w64, sc);
-    wave_dst_core<P>(pr, ty.tw, w64);
+    sc.za = p0 + 2 * pr == 0;
+    float* g2 = buf + static_cast<size_t>(pr) * ppitch;
+    if constexpr (two) {
+      pair2_dst_core(g2, l, ty.tw, wt, sc);
+      __syncthreads();   // both waves' outputs are the next transform's input
+      pair2_dst_core(g2, l, ty.tw, wt);
+    } else {
+      wave_dst_core<P>(g2, ty.tw, wt, sc);
+      wave_dst_core<P>(g2, ty.tw, wt);
+    }
   }
   __syncthreads();
   float* out = a.out + fld * plane + p0 + c + static_cast<size_t>(j0) * nx;
@@ -1008,7 +1137,10 @@ template <typename T, int LOGN>
 __device__ __forceinline__ void col_block(const Geom& g, const ColArgs<T>& a,
                                           const AxisTables<T>& ty, const double* __restrict__ lamx,
                                           int strip, int fld, unsigned char* smem_raw) {
-  if constexpr (fast_core(sizeof(T), 1 << LOGN)) {
+  if constexpr (fast_core(sizeof(T), 1 << LOGN) && core_lanes(sizeof(T), 1 << LOGN) == 128) {
+    col_block_core<LOGN, 4>(g, a, ty, lamx, strip, fld, smem_raw);   // the launcher checks w = 4
+    return;
+  } else if constexpr (fast_core(sizeof(T), 1 << LOGN)) {
     if (a.w == 8)
       col_block_core<LOGN, 8>(g, a, ty, lamx, strip, fld, smem_raw);
     else if (a.w == 4)
@@ -1124,9 +1256,10 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
 // Up to 512 columns one busy wave per workgroup (more, smaller workgroups
 // fill the chip; measured best from HIP graphs at 64^2 and 512^2), above
 // two in FP32 with the half-length transform and four in FP64 (measured at
-// 1024^2), four with the FP32 core.
+// 1024^2), four with the FP32 core (two pairs of two waves at 1024).
 template <typename T>
 int row_rows(int nx, int ny) {
+  if (core_lanes(sizeof(T), nx) == 128) return 4;   // two-wave core: two pairs per workgroup
   const bool core = fast_core(sizeof(T), nx);
   const int per = nx >= 512 || core ? 1 : 512 / nx;
   const int waves = nx <= 512 ? 1 : (sizeof(T) == 8 || core ? 4 : 2);

@@ -47,13 +47,14 @@ __global__ void k_axis_tables(int n, double h, qsp::Cplx<T>* tw, T* pre, double*
   if (m >= 2 * n) return;
   double s, c;
   if (qsp::fast_core(sizeof(T), n)) {
-    const int k1 = m >> 6, l = m & 63;
+    const int NL = qsp::core_lanes(sizeof(T), n);
+    const int k1 = m / NL, l = m % NL;
     sincospi(-2.0 * static_cast<double>((l * k1) % (2 * n)) / (2 * n), &s, &c);
     tw[m] = {static_cast<T>(c), static_cast<T>(s)};
-    if (m < 72) {
+    if (m < NL / 8 * 9) {
       auto* w = reinterpret_cast<qsp::Cplx<T>*>(pre);
       const int la = m / 9, c1 = m % 9;
-      sincospi(-2.0 * (la * c1) / 64.0, &s, &c);
+      sincospi(-2.0 * (la * c1) / static_cast<double>(NL), &s, &c);
       w[m] = c1 < 8 ? qsp::Cplx<T>{static_cast<T>(c), static_cast<T>(s)}
                     : qsp::Cplx<T>{T(0), T(0)};
     }

@@ -1173,11 +1173,12 @@ class Box final : public BoxBase {
   }
 
   // Lattice rows per push workgroup (64 sites wide): as many rows as keep
-  // >= 1024 workgroups per launch, between 4 and 16.
+  // >= 2048 workgroups per launch, between 4 and 16 (at 1024^2 sites, 8 rows
+  // take the real push from 86 to 74 us against 16; at 512^2, 4).
   int default_tile_rows() const {
     const int tx = lat_.nX < 64 ? lat_.nX : 64;
     int r = 16;
-    while (r > 4 && r * tx > kBlock && lat_.np / (static_cast<int64_t>(tx) * r) < 1024) r >>= 1;
+    while (r > 4 && r * tx > kBlock && lat_.np / (static_cast<int64_t>(tx) * r) < 2048) r >>= 1;
     if (const char* e = std::getenv("QSP_TILE_ROWS")) {   // tuning override
       const int v = std::atoi(e);
       if (v >= 1 && v <= 16 && (v & (v - 1)) == 0 && v * tx >= kBlock) r = v;
@@ -1302,13 +1303,13 @@ class Box final : public BoxBase {
       return Cplx<T>{static_cast<T>(std::cos(a)), static_cast<T>(std::sin(a))};
     };
     if (fast_core(sizeof(T), n)) {
-      const int P = 2 * n / 64;
+      const int NL = core_lanes(sizeof(T), n), P = 2 * n / NL;
       for (int k1 = 0; k1 < P; ++k1)
-        for (int l = 0; l < 64; ++l) htw[k1 * 64 + l] = unit(static_cast<long>(l) * k1, 2 * n);
+        for (int l = 0; l < NL; ++l) htw[k1 * NL + l] = unit(static_cast<long>(l) * k1, 2 * n);
       Cplx<T>* w = reinterpret_cast<Cplx<T>*>(hpre.data());
-      for (int i = 0; i < 72; ++i) w[i] = Cplx<T>{T(0), T(0)};
-      for (int la = 0; la < 8; ++la)
-        for (int c1 = 0; c1 < 8; ++c1) w[la * 9 + c1] = unit(la * c1, 64);
+      for (int i = 0; i < NL / 8 * 9; ++i) w[i] = Cplx<T>{T(0), T(0)};
+      for (int la = 0; la < NL / 8; ++la)
+        for (int c1 = 0; c1 < 8; ++c1) w[la * 9 + c1] = unit(la * c1, NL);
     } else {
       for (int m = 0; m < n; ++m) {
         htw[m] = unit(m, n);
