@@ -55,7 +55,18 @@ struct Geom {
   double x_lo, y_lo, hx, hy;
   int rr;                // rows per workgroup of the transform row passes
   int order;             // transverse particle shape order, 0..3
+  // 1: the planes between the row and column passes of a solve are stored
+  // in strips of 4 columns, element (j, i) at ((i / 4) ny + j) 4 + i % 4
+  // (FP32 with 1024 rows: the column pass reads and writes one contiguous
+  // block per strip, the row passes 64-byte blocks of 4 rows x 4 columns);
+  // 0: row-major
+  int strip;
 };
+
+// Offset of element (j, i) of a strip-ordered intermediate plane.
+__host__ __device__ inline size_t strip_at(int j, int i, int ny) {
+  return (static_cast<size_t>(i >> 2) * ny + j) * 4 + (i & 3);
+}
 
 // Plasma lattice: (nx*ppc_x) x (ny*ppc_y) sites, particle p = I + J*nX.
 struct Lattice {

@@ -23,7 +23,9 @@ k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
   const Cplx<T>* tw;
   const T* pre;
   stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
-  const int j0 = blockIdx.x * R;
+  // neighbouring row blocks share the 128-byte lines of strip-ordered
+  // planes: keep them on one XCD (one L2)
+  const int j0 = xcd_strip(blockIdx.x, gridDim.x) * R;
   const int fld = blockIdx.y;   // 0 psi, 1 Ez, 2 Bz
   const double ihx = 0.5 / g.hx, ihy = 0.5 / g.hy;
   // neighbour indices are clamped so that every load is in bounds; values
@@ -48,11 +50,7 @@ k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
-  T* out = a.out + static_cast<size_t>(fld) * g.nx * g.ny;
-  for_row_elems<RC, LOGN>(R, [&](int e) {
-    const int r = e >> LOGN, i = e & (n - 1);
-    out[(j0 + r) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)];
-  });
+  rows_to_plane<T, RC, LOGN>(g, R, j0, buf, ppitch, a.out + static_cast<size_t>(fld) * g.nx * g.ny);
 }
 
 template <typename T, int LOGN, int RC>
@@ -60,7 +58,7 @@ __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_src_fwd_bxby(Geom g, SrcBxBy<T> a, AxisTables<T> tx, const DevCounters* ctr) {
   if (ctr->pc_done) return;
   extern __shared__ unsigned char smem_raw[];
-  src_bxby_block<T, LOGN, RC>(g, a, tx, blockIdx.x, blockIdx.y, smem_raw);
+  src_bxby_block<T, LOGN, RC>(g, a, tx, xcd_strip(blockIdx.x, gridDim.x), blockIdx.y, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -73,10 +71,12 @@ k_col_solve(Geom g, ColArgs<T> a, AxisTables<T> ty, const double* __restrict__ l
   if (a.honor_done && ctr->pc_done) return;
   extern __shared__ unsigned char smem_raw[];
   col_block<T, LOGN>(g, a, ty, lamx, xcd_strip(blockIdx.x, gridDim.x), blockIdx.y, smem_raw);
-  // the side job's stores come last: the memory counter the strip load waits
-  // on also counts stores
-  zero_job(a.zero, static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x,
-           static_cast<size_t>(gridDim.x) * gridDim.y);
+  // the side job's stores come last (the memory counter the strip load waits
+  // on also counts stores); the two-wave core's pass issues them itself,
+  // before its transforms
+  if constexpr (core_lanes(sizeof(T), 1 << LOGN) != 128)
+    zero_job(a.zero, static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x,
+             static_cast<size_t>(gridDim.x) * gridDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -93,18 +93,24 @@ k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
   const Cplx<T>* tw;
   const T* pre;
   stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
-  const int j0 = blockIdx.x * R;
+  const int j0 = xcd_strip(blockIdx.x, gridDim.x) * R;   // neighbours on one XCD
   const int fld = blockIdx.y;
-  const T* in = a.in[fld];
-  for_row_elems<RC, LOGN, 32>(R, [&](int e) {
-    const int r = e >> LOGN, i = e & (n - 1);
-    buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
-  });
+  {
+    Geom gi = g;
+    gi.strip = a.in_strip;
+    plane_to_rows<T, RC, LOGN>(gi, R, j0, a.in[fld], buf, ppitch);
+  }
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   guess_job(a.guess, static_cast<size_t>(g.nx) * g.ny);
   T* out = a.out[fld];
   T* out_dx = a.out_dx[fld];
+  if (a.out_strip) {   // an intermediate plane (no -d_x)
+    Geom go = g;
+    go.strip = 1;
+    rows_to_plane<T, RC, LOGN>(go, R, j0, buf, ppitch, out);
+    return;
+  }
   const T mihx = static_cast<T>(-0.5 / g.hx);
   for_row_elems<RC, LOGN>(R, [&](int e) {
     const int r = e >> LOGN, i = e & (n - 1);
@@ -125,7 +131,7 @@ __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_row_inv_pc(Geom g, PCArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   if (ctr->pc_done) return;
   extern __shared__ unsigned char smem_raw[];
-  row_inv_pc_block<T, LOGN, RC>(g, a, tx, blockIdx.x, blockIdx.y, smem_raw);
+  row_inv_pc_block<T, LOGN, RC>(g, a, tx, xcd_strip(blockIdx.x, gridDim.x), blockIdx.y, smem_raw);
 }
 
 // ---------------------------------------------------------------------------
@@ -142,6 +148,13 @@ static void allow_lds(const void* fn, size_t lds) {
 // Each wave transforms one group of row pairs (one pair for the FP32 core,
 // max(1, 512/n) otherwise; two waves per pair at 1024 with the FP32 core,
 // exactly two pairs): a pass must not give a workgroup more rows.
+// The strip order of the intermediate planes moves 4 rows x 4 columns at a
+// time: it needs 4-row row blocks and 4-column column strips.
+static void check_strip(const Geom& g, int rows_or_cols) {
+  if (g.strip && rows_or_cols != 4)
+    throw std::invalid_argument("transform pass: strip-ordered planes need blocks of 4 rows or columns");
+}
+
 template <typename T>
 static void check_rows(int n, int rows) {
   if (core_lanes(sizeof(T), n) == 128) {   // the two-wave core needs all four waves busy
@@ -158,6 +171,7 @@ void launch_src_fwd_pez(const Geom& g, const SrcPEZ<T>& a, const AxisTables<T>& 
                         hipStream_t st) {
   const int R = g.rr;
   check_rows<T>(g.nx, R);
+  check_strip(g, R);
   const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
@@ -175,6 +189,7 @@ void launch_src_fwd_bxby(const Geom& g, const SrcBxBy<T>& a, const AxisTables<T>
                          const DevCounters* ctr, hipStream_t st) {
   const int R = g.rr;
   check_rows<T>(g.nx, R);
+  check_strip(g, R);
   const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
@@ -195,6 +210,7 @@ void launch_col_solve(const Geom& g, const ColArgs<T>& a, int nfield, const Axis
   if (W < 2 || (W & (W - 1)) || g.nx % W || nfield < 1 || nfield > 4)
     throw std::invalid_argument("column pass: bad strip width or field count");
   check_rows<T>(g.ny, W);
+  check_strip(g, W);
   const size_t lds = static_cast<size_t>(W / 2) * pair_pitch<T>(g.ny) * sizeof(T) + table_bytes<T>(g.ny) +
                      lam_bytes<T>(g.ny, W);
   with_logn(g.ny, [&](auto e) {
@@ -211,6 +227,7 @@ void launch_row_inv(const Geom& g, const RowInvArgs<T>& a, int nfield, const Axi
                     hipStream_t st) {
   const int R = g.rr;
   check_rows<T>(g.nx, R);
+  check_strip(g, R);
   const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;
@@ -228,6 +245,7 @@ void launch_row_inv_pc(const Geom& g, const PCArgs<T>& a, const AxisTables<T>& t
                        DevCounters* ctr, hipStream_t st) {
   const int R = g.rr;
   check_rows<T>(g.nx, R);
+  check_strip(g, R);
   const size_t lds = static_cast<size_t>(R / 2) * pair_pitch<T>(g.nx) * sizeof(T) + table_bytes<T>(g.nx);
   with_logn(g.nx, [&](auto e) {
     constexpr int E = decltype(e)::value;

@@ -704,11 +704,14 @@ void with_logn(int n, F&& f) {
 }
 
 // Bytes of the per-axis tables a transform pass stages in LDS: twiddles and
-// pre-twiddles of the half-length transform, or for the FP32 core the W_64
-// or W_128 table (72 or 144 complex; its W_N^{l k1} table is read from
-// global memory).
+// pre-twiddles of the half-length transform; for the one-wave FP32 core the
+// W_64 table (72 complex; its W_N^{l k1} table is read from global memory);
+// for the two-wave core both (2n + 144 complex), so that its transforms
+// issue no global loads (a wait on a load also waits on earlier stores).
 template <typename T>
 __host__ __device__ inline size_t table_bytes(int n) {
+  if (fast_core(sizeof(T), n) && core_lanes(sizeof(T), n) == 128)   // W_N and W_128 tables
+    return static_cast<size_t>(2 * n + 144) * sizeof(Cplx<T>);
   if (fast_core(sizeof(T), n)) return static_cast<size_t>(core_lanes(sizeof(T), n) / 8 * 9) * sizeof(Cplx<T>);
   return static_cast<size_t>(n) * (sizeof(Cplx<T>) + sizeof(T));
 }
@@ -779,9 +782,23 @@ __device__ inline void stage_tables(const AxisTables<T>& t, unsigned char* base,
     // (144) entries of W_64 (W_128) go to LDS
     Cplx<T>* sw = stw;
     const Cplx<T>* gw = reinterpret_cast<const Cplx<T>*>(t.pre);
-    if (threadIdx.x < core_lanes(sizeof(T), n) / 8 * 9) sw[threadIdx.x] = gw[threadIdx.x];
-    tw = t.tw;
-    pre = reinterpret_cast<const T*>(sw);
+    if constexpr (core_lanes(sizeof(T), n) == 128) {
+      // W_N^{L k1} (2n entries) then W_128 (144) in LDS
+      constexpr int NT = 2 * n / kBlock;
+      Cplx<T> v[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) v[u] = t.tw[threadIdx.x + u * kBlock];
+      const Cplx<T> wv = threadIdx.x < 144 ? gw[threadIdx.x] : Cplx<T>{T(0), T(0)};
+#pragma unroll
+      for (int u = 0; u < NT; ++u) sw[threadIdx.x + u * kBlock] = v[u];
+      if (threadIdx.x < 144) sw[2 * n + threadIdx.x] = wv;
+      tw = sw;
+      pre = reinterpret_cast<const T*>(sw + 2 * n);
+    } else {
+      if (threadIdx.x < core_lanes(sizeof(T), n) / 8 * 9) sw[threadIdx.x] = gw[threadIdx.x];
+      tw = t.tw;
+      pre = reinterpret_cast<const T*>(sw);
+    }
   } else {
     T* spre = reinterpret_cast<T*>(base + n * sizeof(Cplx<T>));
     if constexpr (n % kBlock == 0) {
@@ -950,6 +967,56 @@ __device__ __forceinline__ void for_row_elems(int R, F&& f) {
     for_elems<CH>(R << LOGN, f);
 }
 
+// Element e of a block of 4 rows in the strip order (Geom::strip): e = 16 s
+// + 4 r + c is row r, column 4 s + c, stored at offset (s ny + j0 + r) 4 + c
+// of the plane, so 16 consecutive elements are one 64-byte block.
+__device__ __forceinline__ void strip_elem(int e, int& r, int& i) {
+  const int w = e & 15;
+  r = w >> 2;
+  i = ((e >> 4) << 2) | (w & 3);
+}
+__device__ __forceinline__ size_t strip_off(int e, int j0, int ny) {
+  return static_cast<size_t>(e >> 4) * (static_cast<size_t>(ny) << 2) + (static_cast<size_t>(j0) << 2) +
+         (e & 15);
+}
+
+// The R rows j0.. of a row block between LDS and an intermediate plane of a
+// solve: row-major, or in the strip order (Geom::strip, R = 4).
+template <typename T, int RC, int LOGN, int CH = 8>
+__device__ __forceinline__ void rows_to_plane(const Geom& g, int R, int j0, const T* buf, int ppitch,
+                                              T* __restrict__ out) {
+  constexpr int n = 1 << LOGN;
+  if (g.strip) {
+    for_row_elems<RC, LOGN, CH>(R, [&](int e) {
+      int r, i;
+      strip_elem(e, r, i);
+      out[strip_off(e, j0, g.ny)] = buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)];
+    });
+  } else {
+    for_row_elems<RC, LOGN, CH>(R, [&](int e) {
+      const int r = e >> LOGN, i = e & (n - 1);
+      out[(j0 + r) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)];
+    });
+  }
+}
+template <typename T, int RC, int LOGN, int CH = 32>
+__device__ __forceinline__ void plane_to_rows(const Geom& g, int R, int j0, const T* __restrict__ in,
+                                              T* buf, int ppitch) {
+  constexpr int n = 1 << LOGN;
+  if (g.strip) {
+    for_row_elems<RC, LOGN, CH>(R, [&](int e) {
+      int r, i;
+      strip_elem(e, r, i);
+      buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)] = in[strip_off(e, j0, g.ny)];
+    });
+  } else {
+    for_row_elems<RC, LOGN, CH>(R, [&](int e) {
+      const int r = e >> LOGN, i = e & (n - 1);
+      buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
+    });
+  }
+}
+
 // Runs f(std::integral_constant<int, RC>) with RC = R (2, 4 or 8; 4 for
 // the two-wave core) for row passes of the FP32 core, RC = 0 (rows at run
 // time) otherwise.
@@ -1018,11 +1085,7 @@ __device__ __forceinline__ void src_bxby_block(const Geom& g, const SrcBxBy<T>& 
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
-  T* out = a.out + static_cast<size_t>(fld) * g.nx * g.ny;
-  for_row_elems<RC, LOGN>(R, [&](int e) {
-    const int r = e >> LOGN, i = e & (n - 1);
-    out[(j0 + r) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)];
-  });
+  rows_to_plane<T, RC, LOGN>(g, R, j0, buf, ppitch, a.out + static_cast<size_t>(fld) * g.nx * g.ny);
 }
 
 // Calls f(it) for it = 0 .. NIT-1 in unrolled chunks of up to 32 (NIT a
@@ -1066,9 +1129,10 @@ __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<floa
   const int pr = two ? tid >> 7 : tid >> 6;     // the thread's pair
   const int l = two ? tid & 127 : tid & 63;     // its lane in the pair
   const bool busy = two || pr < W / 2;
-  constexpr int NWT = core_lanes(4, n) / 8 * 9;
-  Cplx<float>* wt = reinterpret_cast<Cplx<float>*>(smem_raw + static_cast<size_t>(W / 2) * ppitch * sizeof(float));
-  if (tid < NWT) wt[tid] = reinterpret_cast<const Cplx<float>*>(ty.pre)[tid];
+  const Cplx<float>* tw;   // W_N^{l k1}: LDS for the two-wave core, else global
+  const float* wpre;
+  stage_tables<float, LOGN>(ty, smem_raw + static_cast<size_t>(W / 2) * ppitch * sizeof(float), tw, wpre);
+  const Cplx<float>* wt = reinterpret_cast<const Cplx<float>*>(wpre);
   // the y eigenvalues of the lane's core outputs, fetched under the strip load
   double ly[NK];
   double lxa = 0.0, lxb = 0.0;
@@ -1081,7 +1145,25 @@ __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<floa
   const size_t plane = static_cast<size_t>(nx) * n;
   const int c = tid & (W - 1), j0 = tid >> LW;
   const int lcol = (c >> 1) * ppitch + (c & 1) * Pd::rlen(n) + Pd::ridx(j0);
-  {
+  // strip-ordered planes (Geom::strip): the strip is one contiguous block of
+  // n rows x 4 columns, read and written as one float4 per row
+  const bool cont = two && g.strip != 0;
+  constexpr int NQ = n / kBlock;
+  const int rl = Pd::rlen(n);
+  if (cont) {
+    const float4* src = reinterpret_cast<const float4*>(a.in + fld * plane + static_cast<size_t>(strip) * 4 * n);
+    float4 v[NQ];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) v[u] = src[tid + u * kBlock];
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      float* d = buf + Pd::ridx(tid) + Pd::ridx(u * kBlock);
+      d[0] = v[u].x;
+      d[rl] = v[u].y;
+      d[ppitch] = v[u].z;
+      d[ppitch + rl] = v[u].w;
+    }
+  } else {
     const float* in = a.in + fld * plane + p0 + c + static_cast<size_t>(j0) * nx;
     float* d = buf + lcol;
     for_iters<NIT>([&](int it) { d[it * LS] = in[static_cast<size_t>(it) * JS * nx]; });
@@ -1098,15 +1180,46 @@ __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<floa
     sc.za = p0 + 2 * pr == 0;
     float* g2 = buf + static_cast<size_t>(pr) * ppitch;
     if constexpr (two) {
-      pair2_dst_core(g2, l, ty.tw, wt, sc);
+      // the side job's stores drain under the transforms (which issue no
+      // global loads here: a wait on a load also waits on earlier stores)
+      zero_job(a.zero, static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x,
+               static_cast<size_t>(gridDim.x) * gridDim.y);
+      pair2_dst_core(g2, l, tw, wt, sc);
       __syncthreads();   // both waves' outputs are the next transform's input
-      pair2_dst_core(g2, l, ty.tw, wt);
+      pair2_dst_core(g2, l, tw, wt);
     } else {
-      wave_dst_core<P>(g2, ty.tw, wt, sc);
-      wave_dst_core<P>(g2, ty.tw, wt);
+      wave_dst_core<P>(g2, tw, wt, sc);
+      wave_dst_core<P>(g2, tw, wt);
     }
   }
   __syncthreads();
+  if (cont) {
+    const size_t sb = fld * plane + static_cast<size_t>(strip) * 4 * n;
+    float4* dst = reinterpret_cast<float4*>(a.out + sb);
+    float4* dy = fld == 0 && a.out_dy ? reinterpret_cast<float4*>(a.out_dy + static_cast<size_t>(strip) * 4 * n)
+                                      : nullptr;
+    const float mihy = static_cast<float>(-0.5 / g.hy);
+#pragma unroll
+    for (int u = 0; u < NQ; ++u) {
+      const int j = tid + u * kBlock;
+      const float* q = buf + Pd::ridx(j);
+      dst[j] = float4{q[0], q[rl], q[ppitch], q[ppitch + rl]};
+      if (dy) {
+        // -d_y by central differences, zero on row 0 and beyond row n - 1
+        // (neighbour indices clamped into the strip)
+        const float* qu = buf + Pd::ridx(j + 1 < n ? j + 1 : j);
+        const float* qd = buf + Pd::ridx(j > 0 ? j - 1 : 0);
+        const bool hu = j + 1 < n, in = j > 0;
+        float4 d4;
+        d4.x = in ? mihy * ((hu ? qu[0] : 0.f) - qd[0]) : 0.f;
+        d4.y = in ? mihy * ((hu ? qu[rl] : 0.f) - qd[rl]) : 0.f;
+        d4.z = in ? mihy * ((hu ? qu[ppitch] : 0.f) - qd[ppitch]) : 0.f;
+        d4.w = in ? mihy * ((hu ? qu[ppitch + rl] : 0.f) - qd[ppitch + rl]) : 0.f;
+        dy[j] = d4;
+      }
+    }
+    return;
+  }
   float* out = a.out + fld * plane + p0 + c + static_cast<size_t>(j0) * nx;
   const float* r = buf + lcol;
   if (fld == 0 && a.out_dy) {
@@ -1224,11 +1337,7 @@ __device__ __forceinline__ void row_inv_pc_block(const Geom& g, const PCArgs<T>&
   const T* pre;
   stage_tables<T, LOGN>(tx, smem_raw + static_cast<size_t>(R / 2) * ppitch * sizeof(T), tw, pre);
   const int j0 = bxi * R;
-  const T* in = a.in + static_cast<size_t>(fld) * g.nx * g.ny;
-  for_row_elems<RC, LOGN, 32>(R, [&](int e) {
-    const int r = e >> LOGN, i = e & (n - 1);
-    buf[RowLay<T, LOGN>::rpos(n, ppitch, r, i)] = in[(j0 + r) * n + i];
-  });
+  plane_to_rows<T, RC, LOGN>(g, R, j0, a.in + static_cast<size_t>(fld) * g.nx * g.ny, buf, ppitch);
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* b = fld == 0 ? a.bx : a.by;

@@ -121,11 +121,7 @@ k_expl_setup(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
-  T* out = a.fwd + fld * plane;
-  for_elems(R * n, [&](int e) {
-    const int rr = e >> lx, i = e & (n - 1);
-    out[(j0 + rr) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, rr, i)];
-  });
+  rows_to_plane<T, 0, LOGN>(g, R, j0, buf, ppitch, a.fwd + fld * plane);
   double v[2] = {bn, rn};
   partials::store<2>(v, a.part_s, fld * (ny / R) + blockIdx.x);
 }
@@ -168,12 +164,8 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   const int fld = blockIdx.y;
   const int j0 = blockIdx.x * R;
   const size_t plane = static_cast<size_t>(n) * ny;
-  const T* in = a.col + fld * plane;
   const int lx = g.lx;
-  for_elems<32>(R * n, [&](int e) {
-    const int rw = e >> lx, i = e & (n - 1);
-    buf[RowLay<T, LOGN>::rpos(n, ppitch, rw, i)] = in[(j0 + rw) * n + i];
-  });
+  plane_to_rows<T, 0, LOGN>(g, R, j0, a.col + fld * plane, buf, ppitch);
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
   T* z = a.z + fld * plane;
@@ -313,11 +305,7 @@ k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   });
   __syncthreads();
   block_dst<T, LOGN>(buf, g.lx, R, ppitch, tw, pre);
-  T* out = a.fwd + fld * plane;
-  for_elems(R * n, [&](int e) {
-    const int rw = e >> lx, i = e & (n - 1);
-    out[(j0 + rw) * n + i] = buf[RowLay<T, LOGN>::rpos(n, ppitch, rw, i)];
-  });
+  rows_to_plane<T, 0, LOGN>(g, R, j0, buf, ppitch, a.fwd + fld * plane);
   double v[1] = {rn};
   partials::store<1>(v, a.part_u, fld * (ny / R) + blockIdx.x);
 }

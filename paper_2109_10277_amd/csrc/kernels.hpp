@@ -76,6 +76,7 @@ struct RowInvArgs {
   T* out[4];
   T* out_dx[4];             // optional -d_x of the result
   GuessJob<T> guess;
+  int in_strip, out_strip;  // in / out planes in the strip order of Geom::strip
 };
 
 template <typename T>

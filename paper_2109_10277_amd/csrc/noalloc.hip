@@ -98,6 +98,7 @@ void solve(const qsp_config& c, unsigned char* ptr, int nb, const T* src, T* dst
   g.hy = (c.y_hi - c.y_lo) / c.ny;
   g.rr = row_rows<T>(c.nx, c.ny);
   g.order = 1;
+  g.strip = 0;   // the passes run in place: the planes stay row-major
   const size_t pl = static_cast<size_t>(c.nx) * c.ny;
   const size_t nn = static_cast<size_t>(c.nx + 1) * (c.ny + 1);
   T* planes = reinterpret_cast<T*>(ptr);

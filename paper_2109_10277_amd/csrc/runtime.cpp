@@ -197,6 +197,8 @@ class Box final : public BoxBase {
     geom_.hy = (cfg.y_hi - cfg.y_lo) / cfg.ny;
     geom_.rr = row_rows<T>(cfg.nx, cfg.ny);
     geom_.order = cfg.shape_order;
+    // both axes on the two-wave core: strip-ordered intermediate planes
+    geom_.strip = core_lanes(sizeof(T), cfg.nx) == 128 && core_lanes(sizeof(T), cfg.ny) == 128;
     lat_.ppc_x = cfg.ppc_x;
     lat_.ppc_y = cfg.ppc_y;
     lat_.nX = cfg.nx * cfg.ppc_x;
@@ -513,6 +515,7 @@ class Box final : public BoxBase {
       r.in[b] = t2_ + b * pl;
       r.out[b] = t1_ + b * pl;
     }
+    r.out_strip = geom_.strip;
     launch_row_inv<T>(geom_, r, nb, tx(), st_);
     ColArgs<T> c{};
     c.in = t1_;
@@ -524,6 +527,8 @@ class Box final : public BoxBase {
       r.in[b] = t2_ + b * pl;
       r.out[b] = t1_ + b * pl;
     }
+    r.in_strip = geom_.strip;
+    r.out_strip = 0;
     launch_row_inv<T>(geom_, r, nb, tx(), st_);
     for (int b = 0; b < nb; ++b) launch_to_nodes_t<T>(geom_, t1_ + b * pl, d + b * nn, st_);
   }
@@ -988,6 +993,7 @@ class Box final : public BoxBase {
       r.in[b] = t2_ + b * pl;
       r.out[b] = t1_ + b * pl;
     }
+    r.out_strip = geom_.strip;
     launch_row_inv<T>(geom_, r, nb, tx(), st_);
     ColArgs<T> c{};
     c.in = t1_;
@@ -996,6 +1002,8 @@ class Box final : public BoxBase {
     c.honor_done = 0;
     c.w = col_width<T>(geom_, nb);
     launch_col_solve<T>(geom_, c, nb, ty(), lamx_, ctr_, st_);
+    r.in_strip = geom_.strip;
+    r.out_strip = 0;
     launch_row_inv<T>(geom_, r, nb, tx(), st_);
   }
 
@@ -1438,6 +1446,7 @@ class Box final : public BoxBase {
       r.out[2] = ez_;
       r.in[3] = t2_ + 2 * pl;
       r.out[3] = bz_;
+      r.in_strip = geom_.strip;
       // Bx/By initial guess of the predictor-corrector rides along
       r.guess = {bxk, byk, b_[i1_][0], b_[i1_][1], b_[i2_][0], b_[i2_][1], ctr_,
                  tape_slot_ ? tape_b(*tape_slot_, 0, 0) : nullptr,
@@ -1587,29 +1596,32 @@ class Box final : public BoxBase {
     a.part_u = ex_partial_ + 8 * np;
     a.s = ex_s_;
     a.tol = cfg_.pc_tol;
+    // the solver's planes between its row and column passes stay row-major
+    Geom ge = geom_;
+    ge.strip = 0;
     ColArgs<T> c{};
     c.in = t1_;
     c.out = t2_;
     c.out_dy = nullptr;
     c.shift[0] = c.shift[1] = shift_;
     c.honor_done = 1;
-    c.w = col_width<T>(geom_, 2);
+    c.w = col_width<T>(ge, 2);
     auto precondition = [&](int it) {
       a.it = it;
-      timed(QSP_K_COL, [&] { launch_col_solve<T>(geom_, c, 2, ty(), lamx_, ctr_, st_); });
-      timed(QSP_K_ROW_INV, [&] { launch_explicit<T>(geom_, a, kExplRowInv, tx(), ctr_, st_); });
+      timed(QSP_K_COL, [&] { launch_col_solve<T>(ge, c, 2, ty(), lamx_, ctr_, st_); });
+      timed(QSP_K_ROW_INV, [&] { launch_explicit<T>(ge, a, kExplRowInv, tx(), ctr_, st_); });
     };
     a.it = 0;
-    timed(QSP_K_ROW_FWD, [&] { launch_explicit<T>(geom_, a, kExplSetup, tx(), ctr_, st_); });
+    timed(QSP_K_ROW_FWD, [&] { launch_explicit<T>(ge, a, kExplSetup, tx(), ctr_, st_); });
     precondition(0);
     for (int m = 1; m <= cfg_.pc_max_iter; ++m) {
       a.it = m;
-      timed(QSP_K_OTHER, [&] { launch_explicit<T>(geom_, a, kExplMatvec, tx(), ctr_, st_); });
-      timed(QSP_K_ROW_FWD, [&] { launch_explicit<T>(geom_, a, kExplUpdate, tx(), ctr_, st_); });
+      timed(QSP_K_OTHER, [&] { launch_explicit<T>(ge, a, kExplMatvec, tx(), ctr_, st_); });
+      timed(QSP_K_ROW_FWD, [&] { launch_explicit<T>(ge, a, kExplUpdate, tx(), ctr_, st_); });
       if (m < cfg_.pc_max_iter) precondition(m);
     }
     a.it = cfg_.pc_max_iter;
-    timed(QSP_K_OTHER, [&] { launch_explicit<T>(geom_, a, kExplClose, tx(), ctr_, st_); });
+    timed(QSP_K_OTHER, [&] { launch_explicit<T>(ge, a, kExplClose, tx(), ctr_, st_); });
     dst_solves_ += 2 * (cfg_.pc_max_iter);
   }
 
