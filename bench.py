@@ -360,18 +360,20 @@ def adjoint_leg(name: str, precision: str, ckpt_every: int, reps: int = 2,
     return out
 
 
-def emittance_study(nsteps: int) -> dict:
+def emittance_study(nsteps: int, solver: str = "pc") -> dict:
     """FP32 versus FP64 drift of the witness emittance over nsteps time steps
     on a reduced reference setup (256^2 x 256 slices, driver + witness
     macro-particle beams, witness with zero initial emittance and a
-    transverse centroid offset of one sigma_x).  Each time step runs the box
-    with a fresh plasma while the beams advance by dt = 6 in every slice.
-    A progress line goes to stderr every 50 steps."""
+    transverse centroid offset of one sigma_x), with the predictor-corrector
+    or the explicit Bx/By solver (the two solvers of Fig. 7).  Each time
+    step runs the box with a fresh plasma while the beams advance by dt = 6
+    in every slice.  A progress line goes to stderr every 50 steps."""
     import numpy as np
     import torch
     import workloads as W
     from paper_2109_10277_amd import qsp
     cfg, beam = W.emittance_study()
+    cfg.bxby_solver = solver
     w_wit = float(beam.w[-1])
     every = max(1, nsteps // 30)
     out = {}
@@ -401,7 +403,7 @@ def emittance_study(nsteps: int) -> dict:
     e32 = np.array([s[1] for s in out["fp32"]["series"]])
     e64 = np.array([s[1] for s in out["fp64"]["series"]])
     rel = np.abs(e32 - e64) / np.maximum(e64, 1e-300)
-    return {"study": "witness emittance, FP32 vs FP64", "steps": nsteps, "dt": beam.dt,
+    return {"study": "witness emittance, FP32 vs FP64", "bxby_solver": solver, "steps": nsteps, "dt": beam.dt,
             "config": {"nx": cfg.nx, "ny": cfg.ny, "slices": cfg.nzeta,
                        "beam_particles": int(beam.x.size)},
             "steps_sampled": [s[0] for s in out["fp64"]["series"]],
@@ -483,7 +485,7 @@ def main():
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
         return
     if args.emittance_study:
-        print(json.dumps(emittance_study(args.emittance_study)))
+        print(json.dumps(emittance_study(args.emittance_study, args.solver)))
         return
     if args.adjoint_only:
         legs = [] if args.no_adjoint else [adjoint_leg("c4", "fp32", 32, fp64_check=True)]
