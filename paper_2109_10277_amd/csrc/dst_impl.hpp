@@ -442,14 +442,16 @@ struct EigenScale {
 
 // Output slots of a lane: the one-wave core (P points per lane, lane l)
 // writes k = (l >> 3) + 8 t + P (l & 7) + 8 P c2 in slot q = 4 t + c2; the
-// two-wave core (n = 1024, lane L of 128) k = k1 + 16 c1 + 128 q with
-// k1 = 8 (L >> 6) + ((L & 63) >> 3), c1 = L & 7.
+// two-wave core (P points per lane, lane L of 128) k = k1 + P c1 + 8 P q with
+// k1 = (L >> 6) P / 2 + ((L & 63) >> 3), c1 = L & 7 (lanes whose k1 falls
+// outside their wave's rows write nothing; their k is wrapped into [0, n)).
 template <int P>
 __device__ __forceinline__ int core_out_k(int l, int q) {
   return (l >> 3) + 8 * (q >> 2) + P * (l & 7) + 8 * P * (q & 3);
 }
+template <int P>
 __device__ __forceinline__ int core2_out_k(int L, int q) {
-  return 8 * (L >> 6) + ((L & 63) >> 3) + 16 * (L & 7) + 128 * q;
+  return ((L >> 6) * (P / 2) + ((L & 63) >> 3) + P * (L & 7) + 8 * P * q) & (64 * P - 1);
 }
 
 template <int P, typename Epi = NoScale>
@@ -535,15 +537,17 @@ __device__ __forceinline__ void wave_dst_core(float* g, const Cplx<float>* __res
 }
 
 // ---------------------------------------------------------------------------
-// Two-wave FP32 core for rows of n = 1024 points: the pair's 128 lanes share
-// the N = 2048-point FFT, 16 points per lane, so that twice as many waves
-// (two per SIMD on a full grid) hide each other's latencies:
-//   A   lane L: DFT_16 over m of z_{L + 128 m}, times W_N^{L k1} (k = k1 +
-//       16 k2), into row k1 of the transpose region; one workgroup barrier;
+// Two-wave FP32 core for rows of n = 64 P points (used with P = 16, n = 1024):
+// the pair's 128 lanes share the N = 128 P-point FFT, P points per lane, so
+// that twice as many waves (two per SIMD on a full grid) hide each other's
+// latencies:
+//   A   lane L: DFT_P over m of z_{L + 128 m}, times W_N^{L k1} (k = k1 +
+//       P k2), into row k1 of the transpose region; one workgroup barrier;
 //   B1  DFT_128 over L split as 16 x 8 (L = la + 16 lb, k2 = c1 + 8 c2):
 //       DFT_8 over lb, times W_128^{la c1}; wave w of the pair owns rows
-//       k1 = 8 w .. 8 w + 7 from here on (no more barriers);
-//   B2  DFT_16 over la, outputs k = k1 + 16 c1 + 128 c2 for c2 < 8.
+//       k1 = w P/2 .. (w + 1) P/2 - 1 from here on (no more barriers);
+//   B2  DFT_16 over la (4 P of a wave's 64 lanes), outputs k = k1 + P c1 +
+//       8 P c2 for c2 < 8.
 // The transposes use a region of their own after the rows (rows of 152
 // complex: the strided reads and writes of B1 and B2 meet every bank once
 // per 16 lanes), so the first stage reads its rows without a barrier before
@@ -556,16 +560,17 @@ __host__ __device__ constexpr int core2_soff(int n) {   // floats before the tra
   return (CoreLay::rlen(n) + CoreLay::ridx(n) + 31) & ~31;
 }
 
-template <typename Epi = NoScale>
+template <int P, typename Epi = NoScale>
 __device__ __forceinline__ void pair2_dst_core(float* g, int L, const Cplx<float>* __restrict__ twa,
                                                const Cplx<float>* __restrict__ w128,
                                                const Epi& epi = Epi{}) {
   using Pd = CoreLay;
-  constexpr int n = 1024, P = 16;
+  constexpr int n = 64 * P;
+  constexpr int HR = P / 2;   // transpose rows per wave
   float* ra = g;
   float* rb = g + Pd::rlen(n);
   Cplx<float>* s = reinterpret_cast<Cplx<float>*>(g + core2_soff(n));
-  // A: z_{L + 128 m}; m >= 8 from the mirror 2n - j = 128 (16 - m) - L
+  // A: z_{L + 128 m}; m >= P/2 from the mirror 2n - j = 128 (P - m) - L
   Cplx<float> v[P];
 #pragma unroll
   for (int m = 0; m < P / 2; ++m) {
@@ -574,7 +579,7 @@ __device__ __forceinline__ void pair2_dst_core(float* g, int L, const Cplx<float
   }
 #pragma unroll
   for (int m = P / 2; m < P; ++m) {
-    const int jm = 128 * (P - m) - L;         // in [1, n], n only for L = 0, m = 8
+    const int jm = 128 * (P - m) - L;         // in [1, n], n only for L = 0, m = P/2
     const int j = Pd::ridx(jm < n ? jm : 0);
     const float fa = ra[j], fb = rb[j];
     v[m] = {jm < n ? -fa : 0.f, jm < n ? -fb : 0.f};
@@ -586,13 +591,14 @@ __device__ __forceinline__ void pair2_dst_core(float* g, int L, const Cplx<float
     s[k1 * kCore2Pitch + L] = k1 ? cmul(y, twa[k1 * 128 + L]) : y;
   }
   __syncthreads();
-  // B1: lane (la, kb) of wave w handles rows k1 = 8 w + kb + 4 t
+  // B1: lane (la, kb) of wave w handles rows k1 = w HR + kb + 4 t
   const int l6 = L & 63, w = L >> 6;
   const int la = l6 & 15, kb = l6 >> 4;
-  Cplx<float> u[2][8];
+  constexpr int NT = HR / 4;
+  Cplx<float> u[NT][8];
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const Cplx<float>* r = s + (8 * w + kb + 4 * t) * kCore2Pitch + la;
+  for (int t = 0; t < NT; ++t) {
+    const Cplx<float>* r = s + (w * HR + kb + 4 * t) * kCore2Pitch + la;
 #pragma unroll
     for (int lb = 0; lb < 8; ++lb) u[t][lb] = r[16 * lb];
   }
@@ -602,32 +608,32 @@ __device__ __forceinline__ void pair2_dst_core(float* g, int L, const Cplx<float
   for (int c1 = 1; c1 < 8; ++c1) wl[c1] = w128[la * 9 + c1];
   wave_sync();
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < NT; ++t) {
     dft8(u[t]);
-    Cplx<float>* r = s + (8 * w + kb + 4 * t) * kCore2Pitch + la * 9;
+    Cplx<float>* r = s + (w * HR + kb + 4 * t) * kCore2Pitch + la * 9;
     r[0] = u[t][0];
 #pragma unroll
     for (int c1 = 1; c1 < 8; ++c1) r[c1] = cmul(u[t][c1], wl[c1]);
   }
   wave_sync();
-  // B2: lane (k1, c1) = (8 w + l6 >> 3, l6 & 7); DFT_16 over la
-  const int k1 = 8 * w + (l6 >> 3), c1 = l6 & 7;
-  Cplx<float> x[P];
-  {
+  // B2: lane (k1, c1) = (w HR + l6 >> 3, l6 & 7) for l6 < 8 HR; DFT_16 over la
+  if ((l6 >> 3) < HR) {
+    const int k1 = w * HR + (l6 >> 3), c1 = l6 & 7;
+    Cplx<float> x[16];
     const Cplx<float>* r = s + k1 * kCore2Pitch + c1;
 #pragma unroll
-    for (int a = 0; a < P; ++a) x[a] = r[9 * a];
-  }
-  dft_reg<P>(x);
+    for (int a = 0; a < 16; ++a) x[a] = r[9 * a];
+    dft_reg<16>(x);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const Cplx<float> y = x[dft_pos<P>(q)];
-    const int k = k1 + 16 * c1 + 128 * q;
-    const int j = Pd::ridx(k);
-    float oa = -0.5f * y.im, ob = 0.5f * y.re;
-    epi(q, oa, ob);
-    ra[j] = k ? oa : 0.f;
-    rb[j] = k ? ob : 0.f;
+    for (int q = 0; q < 8; ++q) {
+      const Cplx<float> y = x[dft_pos<16>(q)];
+      const int k = k1 + P * c1 + 8 * P * q;
+      const int j = Pd::ridx(k);
+      float oa = -0.5f * y.im, ob = 0.5f * y.re;
+      epi(q, oa, ob);
+      ra[j] = k ? oa : 0.f;
+      rb[j] = k ? ob : 0.f;
+    }
   }
 }
 
@@ -667,7 +673,7 @@ __device__ __forceinline__ void block_dst(T* buf, int logn, int nrow, int ppitch
     if constexpr (core_lanes(sizeof(T), n) == 128) {
       // two waves per pair, every thread (the launchers give 4 rows: 2 pairs)
       const int pr = threadIdx.x >> 7;
-      pair2_dst_core(buf + static_cast<size_t>(pr) * ppitch, threadIdx.x & 127, tw, wt);
+      pair2_dst_core<n / 64>(buf + static_cast<size_t>(pr) * ppitch, threadIdx.x & 127, tw, wt);
     } else {
       // one pair per wave (the launchers keep nrow <= 2 * waves): no loop,
       // whose invariant hoisting would keep the core's per-lane addresses live
@@ -1138,7 +1144,7 @@ __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<floa
   double lxa = 0.0, lxb = 0.0;
   if (busy) {
 #pragma unroll
-    for (int q = 0; q < NK; ++q) ly[q] = ty.lam[two ? core2_out_k(l, q) : core_out_k<P>(l, q)];
+    for (int q = 0; q < NK; ++q) ly[q] = ty.lam[two ? core2_out_k<n / 64>(l, q) : core_out_k<P>(l, q)];
     lxa = lamx[p0 + 2 * pr];
     lxb = lamx[p0 + 2 * pr + 1];
   }
@@ -1184,9 +1190,9 @@ __device__ __forceinline__ void col_block_core(const Geom& g, const ColArgs<floa
       // global loads here: a wait on a load also waits on earlier stores)
       zero_job(a.zero, static_cast<size_t>(blockIdx.y) * gridDim.x + blockIdx.x,
                static_cast<size_t>(gridDim.x) * gridDim.y);
-      pair2_dst_core(g2, l, tw, wt, sc);
+      pair2_dst_core<n / 64>(g2, l, tw, wt, sc);
       __syncthreads();   // both waves' outputs are the next transform's input
-      pair2_dst_core(g2, l, tw, wt);
+      pair2_dst_core<n / 64>(g2, l, tw, wt);
     } else {
       wave_dst_core<P>(g2, tw, wt, sc);
       wave_dst_core<P>(g2, tw, wt);

@@ -197,8 +197,10 @@ class Box final : public BoxBase {
     geom_.hy = (cfg.y_hi - cfg.y_lo) / cfg.ny;
     geom_.rr = row_rows<T>(cfg.nx, cfg.ny);
     geom_.order = cfg.shape_order;
-    // both axes on the two-wave core: strip-ordered intermediate planes
-    geom_.strip = core_lanes(sizeof(T), cfg.nx) == 128 && core_lanes(sizeof(T), cfg.ny) == 128;
+    // both axes on the two-wave core at 1024 points: strip-ordered
+    // intermediate planes
+    geom_.strip = core_lanes(sizeof(T), cfg.nx) == 128 && core_lanes(sizeof(T), cfg.ny) == 128 &&
+                  cfg.nx >= 1024 && cfg.ny >= 1024;
     lat_.ppc_x = cfg.ppc_x;
     lat_.ppc_y = cfg.ppc_y;
     lat_.nX = cfg.nx * cfg.ppc_x;
