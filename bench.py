@@ -45,9 +45,12 @@ PUSH_SOURCES = ["paper_2109_10277_amd/csrc/particles.hip",
                 "paper_2109_10277_amd/csrc/push_tile.hpp",
                 "paper_2109_10277_amd/csrc/shape.hpp"]
 PUSH_TRAFFIC = {
-    "c2": {"sha256_prefix": "5d1424f6cf536825", "bytes": 64.24e6,
-           "summary": "profiles/hbm_traffic_c2_blowout_512x512x1024_fp32.md"},
-    "c3": {"sha256_prefix": "", "bytes": None, "summary": ""},
+    "c2": {"sha256_prefix": "5d1424f6cf536825", "bytes": 64.23e6,
+           "summary": "profiles/kernel_stats_c2_blowout_512x512x1024_fp32.md"},
+    "c5": {"sha256_prefix": "5d1424f6cf536825", "bytes": 737.62e6,
+           "summary": "profiles/kernel_stats_c5_forward_1024x1024_4ppc_fp32.md"},
+    "c3": {"sha256_prefix": "5d1424f6cf536825", "bytes": 240.34e6,
+           "summary": "profiles/hbm_traffic_c3_paper_step_1024x1024x1024_fp32.md"},
 }
 
 
@@ -415,6 +418,32 @@ def emittance_study(nsteps: int, solver: str = "pc") -> dict:
             "seconds": {p: out[p]["seconds"] for p in out}}
 
 
+def solve_bench(reps: int = 200) -> dict:
+    """Standalone batched Dirichlet solves (row pass, column pass, inverse
+    row pass, with the node conversions) at 512^2 and 1024^2, batches of 2
+    and 3 FP32 planes: microseconds per batched solve."""
+    import torch
+    import workloads as W
+    from paper_2109_10277_amd import qsp
+    out = {}
+    for n in (512, 1024):
+        for nb in (2, 3):
+            cfg = W.BoxConfig(nx=n, ny=n, x_lo=-8.0, x_hi=8.0, y_lo=-8.0, y_hi=8.0, nzeta=2,
+                              zeta_hi=0.0, dzeta=0.1)
+            with qsp.Box(cfg, "fp32") as box:
+                src = torch.randn(nb, n + 1, n + 1, dtype=torch.float32, device="cuda")
+                dst = torch.empty_like(src)
+                for _ in range(5):
+                    box.solve_poisson(src, dst, 1.3)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    box.solve_poisson(src, dst, 1.3)
+                torch.cuda.synchronize()
+                out[f"{n}x{n}_batch{nb}"] = (time.perf_counter() - t0) / reps * 1e6
+    return {"us_per_batched_solve": out, "reps": reps}
+
+
 def cpu_baseline(cfg, beam, n_slices: int) -> dict:
     """The FP64 oracle on the host cores: the first n_slices slices of the
     same box, from the unperturbed plasma (a macro-particle beam is
@@ -444,7 +473,7 @@ def main():
     ap.add_argument("--workload", default="c3", choices=("c3", "c2", "c1", "c5fwd"))
     ap.add_argument("--timing-every", type=int, default=4,
                     help="time the kernels of every n-th slice with HIP events")
-    ap.add_argument("--cpu-slices", type=int, default=2)
+    ap.add_argument("--cpu-slices", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the headline workload (for profiler runs)")
@@ -460,6 +489,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times "
                          "(reference kernel for the FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--solve-bench", action="store_true",
+                    help="time standalone batched solves at 512^2 and 1024^2 and exit")
     ap.add_argument("--emittance-study", type=int, default=0, metavar="STEPS",
                     help="only run the FP32-vs-FP64 witness emittance study for STEPS time steps")
     ap.add_argument("--adjoint-only", action="store_true",
@@ -483,6 +514,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 5}))
+        return
+    if args.solve_bench:
+        print(json.dumps(solve_bench()))
         return
     if args.emittance_study:
         print(json.dumps(emittance_study(args.emittance_study, args.solver)))
