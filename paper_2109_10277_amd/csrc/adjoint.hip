@@ -295,13 +295,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushA
   for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock)
     adj_push_one<T, MODE, O>(g, L, a, I0 + e % ts.tx, J0 + e / ts.tx, scat);
   __syncthreads();
-  for (int e = threadIdx.x; e < 6 * ntile; e += kBlock) {
-    const int c = e / ntile, l = e % ntile;
-    const int gi = ox + l % ts.nw, gj = oy + l / ts.nw;
-    if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
-    const double val = tile[e];
-    if (val != 0.0) gadd(a.lam_F[c] + static_cast<size_t>(gj) * nx + gi, val);
-  }
+  push_detail::flush_tile<6>(a.lam_F, tile, ts, ox, oy, nx, ny);
 }
 
 // Transpose of a later predictor-corrector trial push (iteration m >= 1),
@@ -419,13 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_trial_later(Geom g, Lattice L, A
   for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock)
     adj_trial_later_one<T, O>(g, L, a, I0 + e % ts.tx, J0 + e / ts.tx, scat);
   __syncthreads();
-  for (int e = threadIdx.x; e < 2 * ntile; e += kBlock) {
-    const int c = e / ntile, l = e % ntile;
-    const int gi = ox + l % ts.nw, gj = oy + l / ts.nw;
-    if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
-    const double val = tile[e];
-    if (val != 0.0) gadd(a.lam_F[3 + c] + static_cast<size_t>(gj) * nx + gi, val);
-  }
+  push_detail::flush_tile<2>(a.lam_F + 3, tile, ts, ox, oy, nx, ny);
 }
 
 // Transpose of the deposit at the slice-k state: gathers the adjoints of

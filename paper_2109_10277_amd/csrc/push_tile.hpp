@@ -69,6 +69,39 @@ __device__ inline void lds_add(double* p, double v) {
 
 __device__ inline void global_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
+// Adds the nch channels of a tile histogram (nw x nh nodes starting at
+// global node (ox, oy), channel c at tile + c * nw * nh) to the global FP64
+// planes ch[c]: one atomic per stored, non-zero node.  Nodes are walked in
+// row-major order, kBlock at a time, with a running (row, column) pair
+// instead of divisions, and the channel loop is unrolled so that each
+// plane's address is a compile-time argument offset: no load, and so no
+// wait on the atomics already in flight, precedes an atomic.
+template <int nch>
+__device__ __forceinline__ void flush_tile(double* const* ch, const double* tile,
+                                           const TileShape& ts, int ox, int oy, int nx, int ny) {
+  const int ntile = ts.nw * ts.nh;
+  const int step_r = kBlock / ts.nw, step_c = kBlock % ts.nw;
+  int r = threadIdx.x / ts.nw, cl = threadIdx.x % ts.nw;
+  for (int l = threadIdx.x; l < ntile; l += kBlock) {
+    const int gi = ox + cl, gj = oy + r;
+    if (gi >= 1 && gi < nx && gj >= 1 && gj < ny) {
+      const size_t o = static_cast<size_t>(gj) * nx + gi;
+      double val[nch];
+#pragma unroll
+      for (int c = 0; c < nch; ++c) val[c] = tile[c * ntile + l];
+#pragma unroll
+      for (int c = 0; c < nch; ++c)
+        if (val[c] != 0.0) global_add(ch[c] + o, val[c]);
+    }
+    r += step_r;
+    cl += step_c;
+    if (cl >= ts.nw) {
+      cl -= ts.nw;
+      ++r;
+    }
+  }
+}
+
 __device__ inline unsigned long long block_sum(unsigned int v, unsigned int* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -372,13 +405,7 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
 
   if (tiled) {
     __syncthreads();
-    for (int e = threadIdx.x; e < nch * ntile; e += kBlock) {
-      const int c = e / ntile, l = e % ntile;
-      const int gi = ox + l % ts.nw, gj = oy + l / ts.nw;
-      if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
-      const double val = tile[e];
-      if (val != 0.0) global_add(a.dep.ch[c] + static_cast<size_t>(gj) * nx + gi, val);
-    }
+    flush_tile<nch>(a.dep.ch, tile, ts, ox, oy, nx, ny);
   }
   // counters
   const unsigned long long tc = block_sum(nclamp, red);
@@ -498,13 +525,7 @@ __device__ __forceinline__ void explicit_tile(const Geom& g, const Lattice& L,
 
   if (tiled) {
     __syncthreads();
-    for (int e = threadIdx.x; e < nch * ntile; e += kBlock) {
-      const int c = e / ntile, l = e % ntile;
-      const int gi = ox + l % ts.nw, gj = oy + l / ts.nw;
-      if (gi < 1 || gi >= nx || gj < 1 || gj >= ny) continue;
-      const double val = tile[e];
-      if (val != 0.0) global_add(a.dep.ch[c] + static_cast<size_t>(gj) * nx + gi, val);
-    }
+    flush_tile<nch>(a.dep.ch, tile, ts, ox, oy, nx, ny);
   }
 }
 
