@@ -258,7 +258,7 @@ __device__ __forceinline__ void adj_push_one(const Geom& g, const Lattice& L,
 // atomics.
 template <typename T, int MODE, int O>
 __global__ void __launch_bounds__(kBlock) k_adj_push(Geom g, Lattice L, AdjPushArgs<T> a) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   double* tile = reinterpret_cast<double*>(smem_raw);
   const push_detail::TileShape ts = push_detail::tile_shape(L, a.tile_rows, a.tile_halo);
   const int ntile = ts.nw * ts.nh;
@@ -376,7 +376,7 @@ __device__ __forceinline__ void adj_trial_later_one(const Geom& g, const Lattice
 // iteration, lam_F[3] and lam_F[4]).
 template <typename T, int O>
 __global__ void __launch_bounds__(kBlock) k_adj_trial_later(Geom g, Lattice L, AdjPushArgs<T> a) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   double* tile = reinterpret_cast<double*>(smem_raw);
   const push_detail::TileShape ts = push_detail::tile_shape(L, a.tile_rows, a.tile_halo);
   const int ntile = ts.nw * ts.nh;

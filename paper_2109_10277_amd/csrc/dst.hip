@@ -15,7 +15,7 @@ using namespace dst_detail;
 template <typename T, int LOGN, int RC>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_src_fwd_pez(Geom g, SrcPEZ<T> a, AxisTables<T> tx) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   constexpr int n = 1 << LOGN;   // = nx
   const int R = RC > 0 ? RC : g.rr;
@@ -57,7 +57,7 @@ template <typename T, int LOGN, int RC>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_src_fwd_bxby(Geom g, SrcBxBy<T> a, AxisTables<T> tx, const DevCounters* ctr) {
   if (ctr->pc_done) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   src_bxby_block<T, LOGN, RC>(g, a, tx, xcd_strip(blockIdx.x, gridDim.x), blockIdx.y, smem_raw);
 }
 
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kBlock, col_blocks_per_cu(LOGN, sizeof(T)))
 k_col_solve(Geom g, ColArgs<T> a, AxisTables<T> ty, const double* __restrict__ lamx,
             const DevCounters* ctr) {
   if (a.honor_done && ctr->pc_done) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   col_block<T, LOGN>(g, a, ty, lamx, xcd_strip(blockIdx.x, gridDim.x), blockIdx.y, smem_raw);
   // the side job's stores come last (the memory counter the strip load waits
   // on also counts stores); the two-wave core's pass issues them itself,
@@ -85,7 +85,7 @@ k_col_solve(Geom g, ColArgs<T> a, AxisTables<T> ty, const double* __restrict__ l
 template <typename T, int LOGN, int RC>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_row_inv(Geom g, RowInvArgs<T> a, AxisTables<T> tx) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   constexpr int n = 1 << LOGN;   // = nx
   const int R = RC > 0 ? RC : g.rr;
@@ -130,7 +130,7 @@ template <typename T, int LOGN, int RC>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_row_inv_pc(Geom g, PCArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
   if (ctr->pc_done) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   row_inv_pc_block<T, LOGN, RC>(g, a, tx, xcd_strip(blockIdx.x, gridDim.x), blockIdx.y, smem_raw);
 }
 

@@ -62,7 +62,7 @@ __device__ inline void record_residual(DevCounters* ctr, double rr, double bn, i
 template <typename T, int LOGN>
 __global__ void __launch_bounds__(kBlock, dst_blocks_per_cu(LOGN, sizeof(T)))
 k_expl_setup(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int n = g.nx, ny = g.ny;
   const int R = g.rr;
@@ -155,7 +155,7 @@ k_expl_rowinv(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     record_residual(ctr, rr, bn, a.it, stop, res);
   }
   if (stop) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;
@@ -275,7 +275,7 @@ k_expl_update(Geom g, ExplicitArgs<T> a, AxisTables<T> tx, DevCounters* ctr) {
     a.s->alpha[it & 1][0] = t[0] > 0.0 ? a.s->rho[(it - 1) & 1][0] / t[0] : 0.0;
     a.s->alpha[it & 1][1] = t[1] > 0.0 ? a.s->rho[(it - 1) & 1][1] / t[1] : 0.0;
   }
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   T* buf = reinterpret_cast<T*>(smem_raw);
   const int ppitch = pair_pitch<T>(n);
   const Cplx<T>* tw;

@@ -36,7 +36,7 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
     if (a.pc_tol > 0.0 && !ctr->pc_done && static_cast<int>(ctr->pc_iters) >= a.pc_max_iter)
       ctr->pc_not_converged += 1ull;
   }
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   if constexpr (MODE == kExplicitDep)
     push_detail::explicit_tile<T, O>(g, L, a, blockIdx.x, blockIdx.y,
                                      reinterpret_cast<double*>(smem_raw));
