@@ -136,9 +136,36 @@ def run_gpu(cfg, beam, precision: str, steps: int, warmup: int, timing_every: in
 
 
 def graph_replayed(cfg, beam) -> bool:
-    """Boxes without a moving macro-particle beam are replayed from HIP
-    graphs, where only the real push is timed with events."""
-    return hasattr(beam, "amp") and os.environ.get("QSP_GRAPH", "1") != "0"
+    """Boxes are replayed from HIP graphs (QSP_GRAPH=0 launches eagerly);
+    in a replay only the real push is timed with events."""
+    return os.environ.get("QSP_GRAPH", "1") != "0"
+
+
+def eager_breakdown(cfg, beam, precision: str, every: int, soa=None) -> dict:
+    """Kernel classes of one box launched kernel by kernel (a graph replay
+    times only the real push): device ms per box from the events of every
+    `every`-th slice, scaled by `every`, and the eager box's own time."""
+    import torch
+    old = os.environ.get("QSP_GRAPH")
+    os.environ["QSP_GRAPH"] = "0"
+    try:
+        box = make_box(cfg, beam, precision, soa)
+    finally:
+        if old is None:
+            del os.environ["QSP_GRAPH"]
+        else:
+            os.environ["QSP_GRAPH"] = old
+    box.set_timing(every)
+    box.init_plasma()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    box.run_box()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = box.kernel_times()
+    box.close()
+    return {"kernel_ms_per_box": kernel_summary(kt, 1, every, False),
+            "ms_per_box": (t1 - t0) * 1e3}
 
 
 def kernel_summary(kt, steps: int, every: int, graphs: bool) -> dict:
@@ -174,9 +201,11 @@ def note(msg: str) -> None:
     print(f"bench: {msg}", file=sys.stderr, flush=True)
 
 
-def leg(cfg, beam, label, key, precision, steps, warmup, every, soa=None, solves=False) -> dict:
+def leg(cfg, beam, label, key, precision, steps, warmup, every, soa=None, solves=False,
+        breakdown=False) -> dict:
     """One timed workload: throughput, kernel classes and the real push's
-    event-timed roofline."""
+    event-timed roofline (breakdown: also the kernel classes of one eagerly
+    launched box, after the timed boxes)."""
     note(f"{label} {precision}: {warmup} warm-up + {steps} timed boxes")
     graphs = graph_replayed(cfg, beam)
     box, dt, stats, kt = run_gpu(cfg, beam, precision, steps, warmup, every, soa)
@@ -199,6 +228,11 @@ def leg(cfg, beam, label, key, precision, steps, warmup, every, soa=None, solves
     if solves:
         out["dst_solves_per_s_standalone_batch3"] = standalone_solves(box, cfg)
     box.close()
+    if breakdown and graphs and every:
+        if soa is not None:   # the same beam as the timed boxes started from
+            import torch
+            soa = torch.tensor(beam.soa(), device="cuda")
+        out["eager_box"] = eager_breakdown(cfg, beam, precision, every, soa)
     return out
 
 
@@ -540,9 +574,10 @@ def main():
     soa = None if hasattr(beam, "amp") else torch.tensor(beam.soa(), device="cuda")
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     head = leg(cfg, beam, wname, key, "fp32", args.steps, args.warmup, args.timing_every, soa,
-               solves=True)
+               solves=True, breakdown=True)
     kms = head["kernel_ms_per_step"]
-    timed = {c: v for c, v in kms.items() if v is not None}
+    eb = head.get("eager_box")
+    timed = {c: v for c, v in (eb["kernel_ms_per_box"] if eb else kms).items() if v is not None}
     dominant = max(timed, key=timed.get) if timed else None
     p = head["push"]
     out = {
@@ -560,13 +595,19 @@ def main():
         "dst_solves_per_s": head["dst_solves_per_s"],
         "dst_solves_per_s_standalone_batch3": head["dst_solves_per_s_standalone_batch3"],
         "pc_iterations_per_slice": head["pc_iterations_per_slice"],
+        "graph_replay": head["graph_replay"],
         "kernel_ms_per_step": kms,
+        "kernel_ms_per_step_eager_box": None if eb is None else eb["kernel_ms_per_box"],
+        "eager_box_ms": None if eb is None else eb["ms_per_box"],
         "kernel_timing": (f"device time of the launches of every {args.timing_every}-th slice "
                           f"(HIP events on the library stream), scaled by {args.timing_every}; "
-                          "null: not timed (HIP graph replay times only the real push)"),
+                          "null: not timed (HIP graph replay times only the real push); "
+                          "kernel_ms_per_step_eager_box: every class, from one more box of the "
+                          "same workload launched kernel by kernel after the timed boxes"),
         "time_dominant_kernel_class": None if dominant is None else {
             "class": dominant, "ms_per_step": timed[dominant],
-            "share_of_step": timed[dominant] / head["ms_per_step"]},
+            "share_of_step": timed[dominant] / (eb["ms_per_box"] if eb else head["ms_per_step"]),
+            "from": "eager box" if eb else "timed boxes"},
         "roofline": {"bound": "hbm", "kernel": "k_push real (gather + AB5 push + deposit)",
                      "achieved": p["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": p["frac"], "traffic": p["traffic"],

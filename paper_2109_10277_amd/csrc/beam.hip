@@ -172,42 +172,44 @@ __device__ inline void axis(double s, int n, int (&idx)[O + 1], double (&w)[O + 
 
 // rho = q w / (hx hy dzeta), Jz = rho u_z / gamma, rho - Jz written as
 // rho (1 + u_perp^2) / (gamma (gamma + u_z)) so that it does not cancel
+// The particles of slice k are off[k] .. off[k+1]-1 of the sorted beam; the
+// range is read on the device (a captured box stays valid when the beam is
+// sorted again between boxes) and covered by a grid-stride loop.
 template <int O>
-__global__ void k_beam_deposit(Geom g, const float* __restrict__ soa, int64_t n, int64_t start,
-                               int64_t count, double dzeta, double* rho_mjz, double* jz,
-                               double* rho) {
-  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (t >= count) return;
-  const int64_t p = start + t;
-  const double x = soa[p], y = soa[n + p];
-  const double ux = soa[3 * n + p], uy = soa[4 * n + p], uz = soa[5 * n + p], w = soa[6 * n + p];
-  double sx, sy;
-  if (!node_coord(x, g.x_lo, g.hx, g.nx, sx) || !node_coord(y, g.y_lo, g.hy, g.ny, sy)) return;
-  int bi, bj;
-  double wx[O + 1], wy[O + 1];
-  shape::weights<O>(shape::locate<O>(0, sx, g.nx, bi), wx);
-  shape::weights<O>(shape::locate<O>(0, sy, g.ny, bj), wy);
-  const double gam = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
-  const double r = -w / (g.hx * g.hy * dzeta);
-  const double v[3] = {r * (1.0 + ux * ux + uy * uy) / (gam * (gam + uz)), r * uz / gam, r};
-  double* ch[3] = {rho_mjz, jz, rho};
-  for (int c = 0; c < 3; ++c) {
-    if (!ch[c]) continue;
+__global__ void k_beam_deposit(Geom g, const float* __restrict__ soa, int64_t n,
+                               const int64_t* __restrict__ off, int k, double dzeta,
+                               double* rho_mjz, double* jz, double* rho) {
+  const int64_t start = off[k], count = off[k + 1] - start;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < count;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t p = start + t;
+    const double x = soa[p], y = soa[n + p];
+    const double ux = soa[3 * n + p], uy = soa[4 * n + p], uz = soa[5 * n + p], w = soa[6 * n + p];
+    double sx, sy;
+    if (!node_coord(x, g.x_lo, g.hx, g.nx, sx) || !node_coord(y, g.y_lo, g.hy, g.ny, sy)) continue;
+    int bi, bj;
+    double wx[O + 1], wy[O + 1];
+    shape::weights<O>(shape::locate<O>(0, sx, g.nx, bi), wx);
+    shape::weights<O>(shape::locate<O>(0, sy, g.ny, bj), wy);
+    const double gam = sqrt(1.0 + ux * ux + uy * uy + uz * uz);
+    const double r = -w / (g.hx * g.hy * dzeta);
+    const double v[3] = {r * (1.0 + ux * ux + uy * uy) / (gam * (gam + uz)), r * uz / gam, r};
+    double* ch[3] = {rho_mjz, jz, rho};
+    for (int c = 0; c < 3; ++c) {
+      if (!ch[c]) continue;
 #pragma unroll
-    for (int qb = 0; qb <= O; ++qb)
+      for (int qb = 0; qb <= O; ++qb)
 #pragma unroll
-      for (int qa = 0; qa <= O; ++qa)
-        add_node(ch[c], bi + qa, bj + qb, g.nx, g.ny, v[c] * (wx[qa] * wy[qb]));
+        for (int qa = 0; qa <= O; ++qa)
+          add_node(ch[c], bi + qa, bj + qb, g.nx, g.ny, v[c] * (wx[qa] * wy[qb]));
+    }
   }
 }
 
 // one time step of the particles of a slice in that slice's fields
 template <typename T, int O>
-__global__ void k_beam_push(Geom g, float* soa, int64_t n, int64_t start, int64_t count,
-                            SliceFields<T> f, double dt) {
-  const int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (t >= count) return;
-  const int64_t p = start + t;
+__device__ __forceinline__ void beam_push_one(const Geom& g, float* soa, int64_t n, int64_t p,
+                                              const SliceFields<T>& f, double dt) {
   double u[3] = {soa[3 * n + p], soa[4 * n + p], soa[5 * n + p]};
   const double g0 = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
   const double xh = soa[p] + 0.5 * dt * u[0] / g0;
@@ -251,6 +253,15 @@ __global__ void k_beam_push(Geom g, float* soa, int64_t n, int64_t start, int64_
   soa[5 * n + p] = static_cast<float>(un[2]);
 }
 
+template <typename T, int O>
+__global__ void k_beam_push(Geom g, float* soa, int64_t n, const int64_t* __restrict__ off, int k,
+                            SliceFields<T> f, double dt) {
+  const int64_t start = off[k], count = off[k + 1] - start;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < count;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    beam_push_one<T, O>(g, soa, n, start + t, f, dt);
+}
+
 // ------------------------------------------------------------------ host side
 int beam_sort_chunks(int64_t n) { return static_cast<int>((n + kSortChunk - 1) / kSortChunk); }
 
@@ -280,30 +291,31 @@ void beam_sort(const float* in, float* out, int64_t n, double zeta_hi, double dz
   QSP_HIP(hipStreamSynchronize(st));
 }
 
-void launch_beam_deposit(const Geom& g, const float* soa, int64_t n, int64_t start, int64_t count,
-                         double dzeta, double* rho_mjz, double* jz, double* rho, hipStream_t st) {
-  if (count <= 0) return;
+void launch_beam_deposit(const Geom& g, const float* soa, int64_t n, const int64_t* off, int k,
+                         int64_t grid_count, double dzeta, double* rho_mjz, double* jz,
+                         double* rho, hipStream_t st) {
+  if (k < 0 || grid_count < 1) throw std::invalid_argument("beam deposit: bad slice or grid");
   with_order(g.order, [&](auto order) {
-    hipLaunchKernelGGL((k_beam_deposit<decltype(order)::value>), grid_of(count), dim3(kBlock), 0,
-                       st, g, soa, n, start, count, dzeta, rho_mjz, jz, rho);
+    hipLaunchKernelGGL((k_beam_deposit<decltype(order)::value>), grid_of(grid_count), dim3(kBlock),
+                       0, st, g, soa, n, off, k, dzeta, rho_mjz, jz, rho);
   });
   QSP_LAUNCH_CHECK();
 }
 
 template <typename T>
-void launch_beam_push(const Geom& g, float* soa, int64_t n, int64_t start, int64_t count,
-                      const SliceFields<T>& f, double dt, hipStream_t st) {
-  if (count <= 0) return;
+void launch_beam_push(const Geom& g, float* soa, int64_t n, const int64_t* off, int k,
+                      int64_t grid_count, const SliceFields<T>& f, double dt, hipStream_t st) {
+  if (k < 0 || grid_count < 1) throw std::invalid_argument("beam push: bad slice or grid");
   with_order(g.order, [&](auto order) {
-    hipLaunchKernelGGL((k_beam_push<T, decltype(order)::value>), grid_of(count), dim3(kBlock), 0,
-                       st, g, soa, n, start, count, f, dt);
+    hipLaunchKernelGGL((k_beam_push<T, decltype(order)::value>), grid_of(grid_count), dim3(kBlock),
+                       0, st, g, soa, n, off, k, f, dt);
   });
   QSP_LAUNCH_CHECK();
 }
 
-template void launch_beam_push<float>(const Geom&, float*, int64_t, int64_t, int64_t,
+template void launch_beam_push<float>(const Geom&, float*, int64_t, const int64_t*, int, int64_t,
                                       const SliceFields<float>&, double, hipStream_t);
-template void launch_beam_push<double>(const Geom&, float*, int64_t, int64_t, int64_t,
+template void launch_beam_push<double>(const Geom&, float*, int64_t, const int64_t*, int, int64_t,
                                        const SliceFields<double>&, double, hipStream_t);
 
 }  // namespace qsp

@@ -297,11 +297,18 @@ constexpr int kMaxBeamKeys = 16384;
 void beam_sort(const float* in, float* out, int64_t n, double zeta_hi, double dzeta, int nzeta,
                BeamScratch& s, std::vector<int64_t>& offsets, hipStream_t st);
 int beam_sort_chunks(int64_t n);
-void launch_beam_deposit(const Geom&, const float* soa, int64_t n, int64_t start, int64_t count,
-                         double dzeta, double* rho_mjz, double* jz, double* rho, hipStream_t);
+// threads of a captured beam launch (per-slice counts at the paper's beam
+// sizes stay below this; larger slices are covered by the grid-stride loop)
+constexpr int64_t kBeamGraphThreads = 65536;
+// Deposit and time step of the particles of slice k: off[k] .. off[k+1]-1
+// of the sorted beam (BeamScratch::off, read on the device); the grid is
+// sized for grid_count particles and strides over the slice's range.
+void launch_beam_deposit(const Geom&, const float* soa, int64_t n, const int64_t* off, int k,
+                         int64_t grid_count, double dzeta, double* rho_mjz, double* jz,
+                         double* rho, hipStream_t);
 template <typename T>
-void launch_beam_push(const Geom&, float* soa, int64_t n, int64_t start, int64_t count,
-                      const SliceFields<T>& f, double dt, hipStream_t);
+void launch_beam_push(const Geom&, float* soa, int64_t n, const int64_t* off, int k,
+                      int64_t grid_count, const SliceFields<T>& f, double dt, hipStream_t);
 void launch_zero_int(int* p, size_t n, hipStream_t);
 
 // ---------------------------------------------------------------- adjoint

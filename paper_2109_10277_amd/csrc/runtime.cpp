@@ -620,11 +620,9 @@ class Box final : public BoxBase {
            a.ik == b.ik && a.i1 == b.i1 && a.i2 == b.i2 && a.dep_valid == b.dep_valid;
   }
 
-  // whole boxes from the head, without a macro-particle beam (whose slice
-  // offsets change from box to box)
-  bool graph_eligible() const {
-    return graphs_ && cursor_ == 0 && beam_n_ == 0 && tape_slot_ == nullptr;
-  }
+  // whole boxes from the head (macro-particle beams included: their kernels
+  // read the slice ranges of the current sort on the device)
+  bool graph_eligible() const { return graphs_ && cursor_ == 0 && tape_slot_ == nullptr; }
 
   bool graph_matches(const qsp_box_out* out) const {
     if (!graph_.valid || graph_.version != launch_version_) return false;
@@ -1409,13 +1407,17 @@ class Box final : public BoxBase {
     }
     T* bxk = b_[ik_][0];
     T* byk = b_[ik_][1];
-    const int64_t b0 = beam_n_ ? beam_off_[k] : 0;
+    // the beam kernels of slice k read its particle range on the device; a
+    // captured box launches them for every slice (the ranges change from
+    // box to box), eager launches only where the slice holds particles
     const int64_t bcount = beam_n_ ? beam_off_[k + 1] - beam_off_[k] : 0;
+    const bool beam_here = capturing_ ? beam_n_ > 0 : bcount > 0;
+    const int64_t bgrid = capturing_ ? std::min<int64_t>(beam_n_, kBeamGraphThreads) : bcount;
     // beam deposit of slice k (Sec. II step 3)
-    if (bcount > 0)
+    if (beam_here)
       timed(QSP_K_OTHER, [&] {
-        launch_beam_deposit(geom_, beam_soa_, beam_n_, b0, bcount, cfg_.dzeta, dc[0], dc[3], nullptr,
-                            st_);
+        launch_beam_deposit(geom_, beam_soa_, beam_n_, bs_.off, k, bgrid, cfg_.dzeta, dc[0], dc[3],
+                            nullptr, st_);
       });
     // explicit beam current of slice k
     if (!cur_.empty() && cur_[k])
@@ -1511,9 +1513,10 @@ class Box final : public BoxBase {
       }
     }
     // beam particles of slice k take their time step in the final fields
-    if (bcount > 0 && beam_dt_ != 0.0) {
+    if (beam_here && beam_dt_ != 0.0) {
       timed(QSP_K_OTHER, [&] {
-        launch_beam_push<T>(geom_, beam_soa_, beam_n_, b0, bcount, fields(bxk, byk), beam_dt_, st_);
+        launch_beam_push<T>(geom_, beam_soa_, beam_n_, bs_.off, k, bgrid, fields(bxk, byk), beam_dt_,
+                            st_);
       });
       beam_dirty_ = true;
     }

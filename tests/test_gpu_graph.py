@@ -98,3 +98,27 @@ def test_graph_with_timer_and_a_new_beam():
         box.set_timing(0)
     eager.close()
     box.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_graph_replays_with_a_moving_particle_beam(prec, tol):
+    # the beam is pushed in every slice and sorted by slice again before each
+    # box, so every box has other per-slice particle ranges: the replayed
+    # boxes read them on the device and match eager launches box by box
+    cfg, beam = W.small_particle_beam(n=64, nzeta=48, n_per_beam=3000)
+    soa = torch.tensor(beam.soa(), device="cuda")
+    print(f"graph replay moving beam {prec}", flush=True)
+    eager = make_box(cfg, prec, graphs=False)
+    box = make_box(cfg, prec, graphs=True)
+    eager.set_beam_particles(soa.clone(), beam.dt)
+    box.set_beam_particles(soa.clone(), beam.dt)
+    for step in range(3):
+        ref, ref_it, _ = run(eager, cfg)
+        got, it, _ = run(box, cfg)
+        same(got, ref, tol)
+        assert np.array_equal(it, ref_it)
+        b_ref = eager.get_beam_particles().double().cpu().numpy()
+        b_got = box.get_beam_particles().double().cpu().numpy()
+        assert np.abs(b_got - b_ref).max() <= tol * max(1.0, np.abs(b_ref).max()), step
+    eager.close()
+    box.close()
