@@ -88,14 +88,18 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def push_bytes(cfg, fsize: int) -> int:
+def push_bytes(cfg, fsize: int, n_beam: int = 0) -> int:
     """Algorithmic HBM bytes of one real push launch: every particle reads
     its state (x, y, ux, uy, Psi, w) and 4 history slots x 5 quantities and
     writes 5 state + 5 history values; the six field planes are read once
-    and the four FP64 deposit planes (rho - Jz, Jx, Jy, Jz) written once."""
+    and the four FP64 deposit planes (rho - Jz, Jx, Jy, Jz) written once.
+    A launch also carries the beam work of its slice: every beam particle
+    is pushed once per box (6 FP32 values read and written) and deposited
+    once (6 read), 72 B, spread over the nzeta - 1 real pushes."""
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     plane = cfg.nx * cfg.ny
-    return n_p * (26 + 10) * fsize + 6 * plane * fsize + 4 * plane * 8
+    beam = n_beam * 72 // max(cfg.nzeta - 1, 1)
+    return n_p * (26 + 10) * fsize + 6 * plane * fsize + 4 * plane * 8 + beam
 
 
 def make_box(cfg, beam, precision, soa=None):
@@ -212,7 +216,7 @@ def leg(cfg, beam, label, key, precision, steps, warmup, every, soa=None, solves
     fsize = 4 if precision == "fp32" else 8
     push_ms, push_n = kt["push"]
     avg = push_ms / push_n if push_n else float("nan")
-    nbytes = push_bytes(cfg, fsize)
+    nbytes = push_bytes(cfg, fsize, 0 if soa is None else int(soa.shape[1]))
     achieved = nbytes / (avg * 1e-3) / 1e9
     out = {"workload": label, "precision": precision, "steps": steps,
            "value": n_p * cfg.nzeta * steps / dt, "ms_per_step": dt / steps * 1e3,
@@ -607,7 +611,8 @@ def main():
             "class": dominant, "ms_per_step": timed[dominant],
             "share_of_step": timed[dominant] / (eb["ms_per_box"] if eb else head["ms_per_step"]),
             "from": "eager box" if eb else "timed boxes"},
-        "roofline": {"bound": "hbm", "kernel": "k_push real (gather + AB5 push + deposit)",
+        "roofline": {"bound": "hbm",
+                     "kernel": "k_push real (gather + AB5 push + deposit, with the slice's beam work)",
                      "achieved": p["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": p["frac"], "traffic": p["traffic"],
                      "bytes_per_launch": p["bytes_per_launch"],

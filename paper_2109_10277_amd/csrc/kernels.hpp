@@ -148,6 +148,19 @@ struct DepOut {
 enum PushMode { kPushReal = 0, kPushTrial = 1, kDepositOnly = 2, kExplicitDep = 3, kTrialLater = 4,
                 kPushTrialTape = 5 };
 
+// Beam work carried by a real push launch, as workgroups after the plasma
+// tiles: the time step of the beam particles of slice k (the slice being
+// left) in the push's fields (push_wgs workgroups, 0: none) and the deposit
+// of slice k+1's beam particles into dep.ch[0] (rho - Jz) and dep.ch[3] (Jz)
+// (dep_wgs workgroups).  Particle ranges come from off (BeamScratch::off).
+struct BeamRide {
+  float* soa;
+  int64_t n;
+  const int64_t* off;
+  double dt;
+  int push_wgs, dep_wgs;
+};
+
 template <typename T>
 struct PushArgs {
   Particles<T> p;
@@ -176,6 +189,7 @@ struct PushArgs {
   // kPushTrialTape: copy of the slice-k particle state the push reads, 26
   // planes of np in the order xi_x, xi_y, ux, uy, psi, w, hist[4][5]
   T* tape;
+  BeamRide beam;            // kPushReal only
 };
 
 template <typename T>

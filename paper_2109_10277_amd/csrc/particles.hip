@@ -7,6 +7,7 @@
 #include "kernels.hpp"
 #include "partials.hpp"
 #include "push_tile.hpp"
+#include "beam_body.hpp"
 
 namespace qsp {
 
@@ -35,6 +36,25 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
     if (r > ctr->max_resid || r != r) ctr->max_resid = r;
     if (a.pc_tol > 0.0 && !ctr->pc_done && static_cast<int>(ctr->pc_iters) >= a.pc_max_iter)
       ctr->pc_not_converged += 1ull;
+  }
+  if constexpr (MODE == kPushReal) {
+    // beam work riding on the launch: grid rows beyond the lattice tiles
+    const int nty = L.nY / tile_shape(L, a.tile_rows, a.tile_halo).ty;
+    if (static_cast<int>(blockIdx.y) >= nty) {
+      const BeamRide& br = a.beam;
+      const int b = (static_cast<int>(blockIdx.y) - nty) * static_cast<int>(gridDim.x) +
+                    static_cast<int>(blockIdx.x);
+      if (b < br.push_wgs)
+        beam_detail::beam_push_range<T, O>(g, br.soa, br.n, br.off, a.k, a.f, br.dt,
+                                           static_cast<int64_t>(b) * kBlock + threadIdx.x,
+                                           static_cast<int64_t>(br.push_wgs) * kBlock);
+      else if (b < br.push_wgs + br.dep_wgs)
+        beam_detail::beam_deposit_range<O>(
+            g, br.soa, br.n, br.off, a.k + 1, a.dzeta, a.dep.ch[0], a.dep.ch[3], nullptr,
+            static_cast<int64_t>(b - br.push_wgs) * kBlock + threadIdx.x,
+            static_cast<int64_t>(br.dep_wgs) * kBlock);
+      return;
+    }
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
   if constexpr (MODE == kExplicitDep)
@@ -141,7 +161,13 @@ void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode
   const int nch = trial ? 2 : (mode == kExplicitDep ? 3 : 4);
   const size_t lds = a.tiled ? static_cast<size_t>(nch) * ts.nw * ts.nh * sizeof(double) : 0;
   if (lds > 160 * 1024) throw std::invalid_argument("push tile histogram exceeds the LDS");
-  const dim3 grid(L.nX / ts.tx, L.nY / ts.ty);
+  // a real push carries beam workgroups in extra grid rows
+  const int extra = mode == kPushReal ? a.beam.push_wgs + a.beam.dep_wgs : 0;
+  if (a.beam.push_wgs < 0 || a.beam.dep_wgs < 0 ||
+      (extra > 0 && (!a.beam.soa || !a.beam.off || a.beam.n <= 0)))
+    throw std::invalid_argument("beam work of a real push: bad arguments");
+  const int ntx = L.nX / ts.tx;
+  const dim3 grid(ntx, L.nY / ts.ty + (extra + ntx - 1) / ntx);
   if (mode == kTrialLater && !a.rec)
     throw std::invalid_argument("a later trial push needs the first one's record");
   if (mode == kPushTrialTape && !a.tape)

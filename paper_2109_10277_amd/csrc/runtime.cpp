@@ -584,7 +584,7 @@ class Box final : public BoxBase {
   // box launches bumps launch_version_ and forces a new capture.
   struct HostState {
     int cursor, ip, ic, in, ik, i1, i2;
-    bool dep_valid, beam_dirty;
+    bool dep_valid, beam_dirty, beam_ahead;
     int64_t slices, pushes, dst;
   };
   struct GraphItem {
@@ -602,7 +602,7 @@ class Box final : public BoxBase {
   };
 
   HostState save_host() const {
-    return {cursor_, ip_, ic_, in_, ik_, i1_, i2_, dep_valid_, beam_dirty_,
+    return {cursor_, ip_, ic_, in_, ik_, i1_, i2_, dep_valid_, beam_dirty_, beam_ahead_,
             slices_done_, pushes_, dst_solves_};
   }
   void restore_host(const HostState& h) {
@@ -611,13 +611,15 @@ class Box final : public BoxBase {
     ik_ = h.ik, i1_ = h.i1, i2_ = h.i2;
     dep_valid_ = h.dep_valid;
     beam_dirty_ = h.beam_dirty;
+    beam_ahead_ = h.beam_ahead;
     slices_done_ = h.slices;
     pushes_ = h.pushes;
     dst_solves_ = h.dst;
   }
   static bool same_host(const HostState& a, const HostState& b) {
     return a.cursor == b.cursor && a.ip == b.ip && a.ic == b.ic && a.in == b.in &&
-           a.ik == b.ik && a.i1 == b.i1 && a.i2 == b.i2 && a.dep_valid == b.dep_valid;
+           a.ik == b.ik && a.i1 == b.i1 && a.i2 == b.i2 && a.dep_valid == b.dep_valid &&
+           a.beam_ahead == b.beam_ahead;
   }
 
   // whole boxes from the head (macro-particle beams included: their kernels
@@ -1397,6 +1399,10 @@ class Box final : public BoxBase {
     double* const* dc = dep_[ic_];
     double* const* dn = dep_[in_];
     const size_t pl = plane();
+    // the previous slice's real push deposited this slice's beam particles
+    // unless the deposits are rebuilt here
+    const bool beam_done = beam_ahead_ && dep_valid_;
+    beam_ahead_ = false;
     if (!dep_valid_) {
       timed(QSP_K_OTHER, [&] {
         for (int c = 0; c < 5; ++c) launch_zero(dc[c], pl, st_);
@@ -1414,7 +1420,7 @@ class Box final : public BoxBase {
     const bool beam_here = capturing_ ? beam_n_ > 0 : bcount > 0;
     const int64_t bgrid = capturing_ ? std::min<int64_t>(beam_n_, kBeamGraphThreads) : bcount;
     // beam deposit of slice k (Sec. II step 3)
-    if (beam_here)
+    if (beam_here && !beam_done)
       timed(QSP_K_OTHER, [&] {
         launch_beam_deposit(geom_, beam_soa_, beam_n_, bs_.off, k, bgrid, cfg_.dzeta, dc[0], dc[3],
                             nullptr, st_);
@@ -1513,7 +1519,9 @@ class Box final : public BoxBase {
       }
     }
     // beam particles of slice k take their time step in the final fields
-    if (beam_here && beam_dt_ != 0.0) {
+    // (with the real push below when there is one)
+    const bool beam_push_here = beam_here && beam_dt_ != 0.0;
+    if (beam_push_here && k + 1 >= cfg_.nzeta) {
       timed(QSP_K_OTHER, [&] {
         launch_beam_push<T>(geom_, beam_soa_, beam_n_, bs_.off, k, bgrid, fields(bxk, byk), beam_dt_,
                             st_);
@@ -1538,6 +1546,19 @@ class Box final : public BoxBase {
       }
       a.iters_out = iters_out;
       a.resid_out = resid_out;
+      if (beam_n_ > 0) {
+        // the launch also pushes slice k's beam particles and deposits
+        // slice k+1's (into the planes it deposits the plasma into)
+        const int64_t ncount = beam_off_[k + 2] - beam_off_[k + 1];
+        const int64_t ngrid = capturing_ ? std::min<int64_t>(beam_n_, kBeamGraphThreads) : ncount;
+        const auto wgs = [](int64_t c) {
+          return static_cast<int>(std::min<int64_t>((c + kBlock - 1) / kBlock, 1024));
+        };
+        a.beam = {beam_soa_, beam_n_, bs_.off, beam_dt_, beam_push_here ? wgs(bgrid) : 0,
+                  (capturing_ || ncount > 0) ? wgs(ngrid) : 0};
+        if (beam_push_here) beam_dirty_ = true;
+        beam_ahead_ = true;
+      }
       const auto job = [this, a] { launch_push<T>(geom_, lat_, a, kPushReal, ctr_, st_); };
       if (capturing_ && timer_.active(cursor_)) {
         // the sampled launch runs between graph segments, under its events
@@ -1673,6 +1694,7 @@ class Box final : public BoxBase {
   int64_t beam_n_ = 0;
   double beam_dt_ = 0.0;
   bool beam_dirty_ = false;
+  bool beam_ahead_ = false;   // slice cursor_'s beam deposit is already done
   BeamScratch bs_{};
   std::vector<int64_t> beam_off_;
   std::vector<double*> cur_;          // explicit beam current per slice (or null)
