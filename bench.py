@@ -223,6 +223,7 @@ def leg(cfg, beam, label, key, precision, steps, warmup, every, soa=None, solves
            "dst_solves_per_s": sum(s["dst_solves"] for s in stats) / dt,
            "pc_iterations_per_slice": sum(s["pc_iterations"] for s in stats) / (cfg.nzeta * steps),
            "n_clamped_per_step": sum(s["n_clamped"] for s in stats) / steps,
+           "box_reruns": sum(s["box_reruns"] for s in stats),
            "graph_replay": graphs,
            "kernel_ms_per_step": kernel_summary(kt, steps, every, graphs),
            "push": {"achieved": achieved, "frac": achieved / HBM_PEAK_GBS,

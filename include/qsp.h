@@ -166,6 +166,12 @@ typedef struct {
   double max_pc_residual;     /* largest final residual of a slice             */
   double elapsed_ms;          /* device time of the last qsp_run_box           */
   int64_t device_bytes;       /* device memory held by the context             */
+  int64_t box_reruns;         /* boxes run a second time: a box replayed with  */
+                              /* the speculative predictor-corrector launch    */
+                              /* budgets left a slice unconverged below        */
+                              /* pc_max_iter, and was rerun with every         */
+                              /* iteration launched (results are those of the  */
+                              /* second run)                                   */
 } qsp_stats;
 
 /* Full state at the start of slice k (host arrays, double precision, in

@@ -112,6 +112,10 @@ struct DevCounters {
   unsigned long long n_dep_global;
   unsigned long long pc_iterations;
   unsigned long long pc_not_converged;
+  // slices whose launched iterations (a launch budget below the maximum)
+  // ended before the predictor-corrector converged
+  unsigned int budget_short;
+  unsigned int reserved0;
 };
 
 }  // namespace qsp

@@ -51,16 +51,20 @@ __global__ void k_add_current(size_t n, const double* src, double* jz, double* r
   }
 }
 
-__global__ void k_slice_end(DevCounters* ctr, int32_t* iters_out, double* resid_out,
-                            double tol, int max_iter, const double* pc_partial, int pc_nblk) {
+__global__ void k_slice_end(DevCounters* ctr, int32_t* iters_out, int32_t* iters_own,
+                            double* resid_out, double tol, int max_iter, int budgeted,
+                            const double* pc_partial, int pc_nblk) {
   if (pc_partial && !ctr->pc_done) partials::pc_consume(pc_partial, pc_nblk, tol, ctr, true);
   if (threadIdx.x != 0) return;
   const double r = ctr->pc_resid;
   if (iters_out) *iters_out = static_cast<int32_t>(ctr->pc_iters);
+  if (iters_own) *iters_own = static_cast<int32_t>(ctr->pc_iters);
   if (resid_out) *resid_out = r;
   if (r > ctr->max_resid || r != r) ctr->max_resid = r;
-  if (tol > 0.0 && !ctr->pc_done && static_cast<int>(ctr->pc_iters) >= max_iter)
-    ctr->pc_not_converged += 1ull;
+  if (tol > 0.0 && !ctr->pc_done) {
+    if (static_cast<int>(ctr->pc_iters) >= max_iter) ctr->pc_not_converged += 1ull;
+    else if (budgeted) ctr->budget_short += 1u;
+  }
 }
 
 __global__ void k_out_copy(Geom g, OutCopy c) {
@@ -173,10 +177,11 @@ void launch_add_current(size_t n, const double* src, double* jz, double* rho, hi
   QSP_LAUNCH_CHECK();
 }
 
-void launch_slice_end(DevCounters* ctr, int32_t* iters_out, double* resid_out, double tol,
-                      int max_iter, const double* pc_partial, int pc_nblk, hipStream_t st) {
-  hipLaunchKernelGGL(k_slice_end, dim3(1), dim3(kBlock), 0, st, ctr, iters_out, resid_out, tol,
-                     max_iter, pc_partial, pc_nblk);
+void launch_slice_end(DevCounters* ctr, int32_t* iters_out, int32_t* iters_own, double* resid_out,
+                      double tol, int max_iter, int budgeted, const double* pc_partial, int pc_nblk,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_slice_end, dim3(1), dim3(kBlock), 0, st, ctr, iters_out, iters_own,
+                     resid_out, tol, max_iter, budgeted, pc_partial, pc_nblk);
   QSP_LAUNCH_CHECK();
 }
 

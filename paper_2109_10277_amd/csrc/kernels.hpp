@@ -171,9 +171,15 @@ struct PushArgs {
   int tiled;                // 1: LDS tile histograms, 0: direct global atomics
   int tile_rows;            // lattice rows per workgroup tile
   int tile_halo;            // cells of LDS histogram around the tile's own cells
-  // end-of-slice bookkeeping of the predictor-corrector (real push only)
+  // end-of-slice bookkeeping of the predictor-corrector (real push only):
+  // the slice's iteration count to iters_out (caller) and iters_own
+  // (library), the residual to resid_out; pc_budgeted: fewer iterations
+  // than pc_max_iter were launched for the slice (a slice left unconverged
+  // by them is counted in DevCounters::budget_short)
   int32_t* iters_out;
+  int32_t* iters_own;
   double* resid_out;
+  int pc_budgeted;
   double pc_tol;
   int pc_max_iter;
   // partial records of the last corrector solve (null: nothing to test);
@@ -264,8 +270,9 @@ void launch_zero_t(T* p, size_t n, hipStream_t);
 template <typename T>
 void launch_guess(const Geom&, T* bx, T* by, const T* bx1, const T* by1, const T* bx2,
                   const T* by2, DevCounters*, hipStream_t);
-void launch_slice_end(DevCounters*, int32_t* iters_out, double* resid_out, double tol,
-                      int max_iter, const double* pc_partial, int pc_nblk, hipStream_t);
+void launch_slice_end(DevCounters*, int32_t* iters_out, int32_t* iters_own, double* resid_out,
+                      double tol, int max_iter, int budgeted, const double* pc_partial, int pc_nblk,
+                      hipStream_t);
 
 // copy a stored [ny][nx] grid into an [ny+1][nx+1] node array
 struct OutCopy {

@@ -32,10 +32,13 @@ k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
     // close the slice's predictor-corrector bookkeeping
     const double r = ctr->pc_resid;
     if (a.iters_out) *a.iters_out = static_cast<int32_t>(ctr->pc_iters);
+    if (a.iters_own) *a.iters_own = static_cast<int32_t>(ctr->pc_iters);
     if (a.resid_out) *a.resid_out = r;
     if (r > ctr->max_resid || r != r) ctr->max_resid = r;
-    if (a.pc_tol > 0.0 && !ctr->pc_done && static_cast<int>(ctr->pc_iters) >= a.pc_max_iter)
-      ctr->pc_not_converged += 1ull;
+    if (a.pc_tol > 0.0 && !ctr->pc_done) {
+      if (static_cast<int>(ctr->pc_iters) >= a.pc_max_iter) ctr->pc_not_converged += 1ull;
+      else if (a.pc_budgeted) ctr->budget_short += 1u;
+    }
   }
   if constexpr (MODE == kPushReal) {
     // beam work riding on the launch: grid rows beyond the lattice tiles

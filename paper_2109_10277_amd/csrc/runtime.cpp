@@ -214,6 +214,11 @@ class Box final : public BoxBase {
     tile_rows_ = default_tile_rows();
     tile_halo_ = default_tile_halo();
     if (const char* e = std::getenv("QSP_GRAPH")) graphs_ = std::atoi(e) != 0;   // 0: launch eagerly
+    // QSP_PC_BUDGET: 0 switches the speculative P-C budgets off; -1 launches
+    // one iteration fewer than the learned budgets (where that leaves at
+    // least one), also with a moving beam, so that boxes are run twice: a
+    // test of the rerun path
+    if (const char* e = std::getenv("QSP_PC_BUDGET")) spec_mode_ = std::atoi(e);
     QSP_HIP(hipSetDevice(device_));
     try {
       allocate();
@@ -227,7 +232,8 @@ class Box final : public BoxBase {
   }
 
   ~Box() override {
-    free_graph();
+    free_graph(graph_);
+    free_graph(graph_b_);
     if (cap_st_) (void)hipStreamDestroy(cap_st_);
     free_beam();
     free_adjoint();
@@ -251,6 +257,13 @@ class Box final : public BoxBase {
     QSP_HIP(hipSetDevice(device_));
     rec_valid_ = false;
     resort_beam();
+    reset_box();
+    box_reruns_ = 0;
+    fresh_box_ = true;
+  }
+
+  // plasma at rest ahead of the box, every field, deposit and counter zero
+  void reset_box() {
     launch_init_plasma<T>(lat_, p_, cfg_.n0 / (cfg_.ppc_x * cfg_.ppc_y), st_);
     for (int b = 0; b < 3; ++b)
       for (int c = 0; c < 2; ++c) launch_zero_t<T>(b_[b][c], plane(), st_);
@@ -403,6 +416,7 @@ class Box final : public BoxBase {
     s->max_pc_residual = c.max_resid;
     s->elapsed_ms = last_ms_;
     s->device_bytes = bytes_;
+    s->box_reruns = box_reruns_;
     nonfinite_ = c.nonfinite != 0;
   }
 
@@ -457,6 +471,7 @@ class Box final : public BoxBase {
   }
 
   void set_state(const qsp_slice_state* s) override {
+    fresh_box_ = false;
     resort_beam();
     const size_t np = static_cast<size_t>(lat_.np);
     const size_t nn = nodes();
@@ -539,6 +554,7 @@ class Box final : public BoxBase {
   void advance_slice(const qsp_slice_out* out) override {
     QSP_HIP(hipSetDevice(device_));
     rec_valid_ = false;
+    fresh_box_ = false;
     OutCopy oc{};
     if (out) {
       for (int q = 0; q < QSP_NQ; ++q)
@@ -550,9 +566,10 @@ class Box final : public BoxBase {
   void run_box(const qsp_box_out* out) override {
     QSP_HIP(hipSetDevice(device_));
     rec_valid_ = false;
+    const bool fresh = fresh_box_;
+    fresh_box_ = false;
     if (graph_eligible()) {
-      if (!graph_matches(out)) build_graph(out);
-      replay_graph();
+      run_box_graphs(out, fresh);
       return;
     }
     QSP_HIP(hipEventRecord(ev0_, st_));
@@ -573,6 +590,103 @@ class Box final : public BoxBase {
       step(oc, out && out->pc_iters ? out->pc_iters + rel : nullptr,
            out && out->pc_resid ? out->pc_resid + rel : nullptr);
     }
+  }
+
+  // Whole boxes from HIP graphs.  With the predictor-corrector to a
+  // tolerance, a box started from a fresh plasma launches per slice only as
+  // many iterations as the budget of the slice holds instead of
+  // pc_max_iter (the launches after convergence would read the device's
+  // converged flag and return).  A budget is the most iterations the slice
+  // needed in the boxes run so far, plus one where the slice's count has
+  // risen before.  A slice that ends its budget unconverged below
+  // pc_max_iter is counted on the device; the box is then run again from
+  // its start (plasma reset, a macro-particle beam restored) with every
+  // iteration launched, so that results and iteration counts are always
+  // those of the full launch sequence.  Boxes whose beam moves between them
+  // differ from box to box (the per-slice counts of the paper-scale step
+  // change by one here and there every time step), so they launch every
+  // iteration: a rerun costs a whole box and would outweigh what the
+  // budgets save there.
+  void run_box_graphs(const qsp_box_out* out, bool fresh) {
+    const bool moving = beam_n_ > 0 && beam_dt_ != 0.0;
+    const bool pc = !explicit_ && cfg_.pc_tol > 0.0 && spec_mode_ != 0 && (!moving || spec_mode_ < 0);
+    const bool spec = pc && fresh && budget_ready_ && budget_version_ == launch_version_;
+    bool fell_short = false;
+    if (spec) {
+      const HostState h0 = save_host();
+      if (moving)
+        QSP_HIP(hipMemcpyAsync(beam_tmp_, beam_soa_, 7 * beam_n_ * sizeof(float),
+                               hipMemcpyDeviceToDevice, st_));
+      set_budget_launch();
+      budget_on_ = true;
+      try {
+        if (!graph_matches(graph_b_, out)) build_graph(graph_b_, out);
+        replay_graph(graph_b_);
+      } catch (...) {
+        budget_on_ = false;
+        throw;
+      }
+      budget_on_ = false;
+      unsigned int shortfall = 0;
+      QSP_HIP(hipMemcpy(&shortfall, &ctr_->budget_short, sizeof(shortfall), hipMemcpyDeviceToHost));
+      if (shortfall == 0) return;
+      fell_short = true;
+      ++box_reruns_;
+      restore_host(h0);
+      if (moving)
+        QSP_HIP(hipMemcpyAsync(beam_soa_, beam_tmp_, 7 * beam_n_ * sizeof(float),
+                               hipMemcpyDeviceToDevice, st_));
+      reset_box();
+    }
+    if (!graph_matches(graph_, out)) build_graph(graph_, out);
+    replay_graph(graph_);
+    if (pc && fresh) {
+      learn_budgets(fell_short);
+      // capture the speculative box now, from this box's start, so that the
+      // next box only replays it
+      const HostState end = save_host();
+      restore_host(graph_.start);
+      set_budget_launch();
+      budget_on_ = true;
+      try {
+        if (!graph_matches(graph_b_, out)) build_graph(graph_b_, out);
+      } catch (...) {
+        budget_on_ = false;
+        restore_host(end);
+        throw;
+      }
+      budget_on_ = false;
+      restore_host(end);
+    }
+  }
+
+  // the iterations a speculative box launches per slice
+  void set_budget_launch() {
+    budget_launch_.resize(cfg_.nzeta);
+    for (int k = 0; k < cfg_.nzeta; ++k) {
+      int b = budget_[k] + margin_[k];
+      if (spec_mode_ < 0) b = budget_[k] - 1;   // test of the rerun path
+      budget_launch_[k] = std::max(1, std::min(b, cfg_.pc_max_iter));
+    }
+  }
+
+  // budgets from the iteration counts of the box just run (a whole box from
+  // a fresh plasma with every iteration launched); after a shortfall the
+  // slices that needed more than they were given get a margin from now on
+  void learn_budgets(bool after_shortfall) {
+    std::vector<int32_t> it(cfg_.nzeta);
+    QSP_HIP(hipMemcpy(it.data(), iters_own_, it.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    if (!budget_ready_ || budget_version_ != launch_version_) {
+      budget_.assign(cfg_.nzeta, 1);
+      margin_.assign(cfg_.nzeta, 0);
+    }
+    budget_version_ = launch_version_;
+    for (int k = 0; k < cfg_.nzeta; ++k) {
+      const int v = std::max(1, std::min(static_cast<int>(it[k]), cfg_.pc_max_iter));
+      if (after_shortfall && spec_mode_ > 0 && v > budget_launch_[k]) margin_[k] = 1;
+      budget_[k] = std::max(budget_[k], v);
+    }
+    budget_ready_ = true;
   }
 
   // ------------------------------------------------------- graph replay
@@ -599,6 +713,8 @@ class Box final : public BoxBase {
     qsp_box_out out{};
     HostState start{}, end{};
     std::vector<GraphItem> items;
+    bool budgeted = false;          // captured with the speculative P-C budgets
+    std::vector<int> budget;
   };
 
   HostState save_host() const {
@@ -626,13 +742,14 @@ class Box final : public BoxBase {
   // read the slice ranges of the current sort on the device)
   bool graph_eligible() const { return graphs_ && cursor_ == 0 && tape_slot_ == nullptr; }
 
-  bool graph_matches(const qsp_box_out* out) const {
-    if (!graph_.valid || graph_.version != launch_version_) return false;
-    if (graph_.has_out != (out != nullptr)) return false;
-    if (out && std::memcmp(&graph_.out, out, sizeof(qsp_box_out)) != 0) return false;
+  bool graph_matches(const BoxGraph& G, const qsp_box_out* out) const {
+    if (!G.valid || G.version != launch_version_) return false;
+    if (G.has_out != (out != nullptr)) return false;
+    if (out && std::memcmp(&G.out, out, sizeof(qsp_box_out)) != 0) return false;
+    if (G.budgeted != budget_on_ || (budget_on_ && G.budget != budget_launch_)) return false;
     const HostState h = save_host();
-    return same_host(graph_.start, h) && graph_.start.slices == h.slices &&
-           graph_.start.pushes == h.pushes && graph_.start.dst == h.dst;
+    return same_host(G.start, h) && G.start.slices == h.slices && G.start.pushes == h.pushes &&
+           G.start.dst == h.dst;
   }
 
   void begin_segment() {
@@ -648,7 +765,7 @@ class Box final : public BoxBase {
       const hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       QSP_HIP(e);
-      graph_.items.push_back({ge, {}, 0});
+      cap_graph_->items.push_back({ge, {}, 0});
     } else {
       (void)hipGraphDestroy(g);
     }
@@ -657,8 +774,9 @@ class Box final : public BoxBase {
   // The capture runs on a stream of the library's own (the caller's stream
   // may be the legacy default stream, which cannot be captured); the graphs
   // are then launched on the caller's stream.
-  void build_graph(const qsp_box_out* out) {
-    free_graph();
+  void build_graph(BoxGraph& G, const qsp_box_out* out) {
+    free_graph(G);
+    cap_graph_ = &G;
     if (!cap_st_) QSP_HIP(hipStreamCreateWithFlags(&cap_st_, hipStreamNonBlocking));
     QSP_HIP(hipStreamSynchronize(st_));
     const HostState s0 = save_host();
@@ -679,23 +797,25 @@ class Box final : public BoxBase {
       st_ = user;
       capturing_ = false;
       restore_host(s0);
-      free_graph();
+      free_graph(G);
       throw;
     }
     st_ = user;
     capturing_ = false;
-    graph_.end = save_host();
+    G.end = save_host();
     restore_host(s0);
-    graph_.start = s0;
-    graph_.version = launch_version_;
-    graph_.has_out = out != nullptr;
-    graph_.out = out ? *out : qsp_box_out{};
-    graph_.valid = true;
+    G.start = s0;
+    G.version = launch_version_;
+    G.has_out = out != nullptr;
+    G.out = out ? *out : qsp_box_out{};
+    G.budgeted = budget_on_;
+    G.budget = budget_on_ ? budget_launch_ : std::vector<int>{};
+    G.valid = true;
   }
 
-  void replay_graph() {
+  void replay_graph(BoxGraph& G) {
     QSP_HIP(hipEventRecord(ev0_, st_));
-    for (auto& it : graph_.items) {
+    for (auto& it : G.items) {
       if (it.exec) {
         QSP_HIP(hipGraphLaunch(it.exec, st_));
       } else {
@@ -709,14 +829,14 @@ class Box final : public BoxBase {
     float ms = 0.f;
     QSP_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
     last_ms_ = ms;
-    restore_host(graph_.end);
+    restore_host(G.end);
   }
 
-  void free_graph() {
-    for (auto& it : graph_.items)
+  void free_graph(BoxGraph& G) {
+    for (auto& it : G.items)
       if (it.exec) (void)hipGraphExecDestroy(it.exec);
-    graph_.items.clear();
-    graph_.valid = false;
+    G.items.clear();
+    G.valid = false;
   }
 
  public:
@@ -735,6 +855,7 @@ class Box final : public BoxBase {
   }
 
   void record(int n_slices, int K, const qsp_box_out* out) override {
+    fresh_box_ = false;
     QSP_HIP(hipSetDevice(device_));
     rec_valid_ = false;
     ensure_adjoint(n_slices, K);
@@ -1293,6 +1414,7 @@ class Box final : public BoxBase {
       ionx_ = alloc<double>(cfg_.nx + 1);
       iony_ = alloc<double>(cfg_.ny + 1);
     }
+    iters_own_ = alloc<int32_t>(cfg_.nzeta);
     ctr_ = alloc<DevCounters>(1);
     partial_ = alloc<double>(2 * static_cast<size_t>(pc_partial_count(geom_)) + 2);
     if (cfg_.mem_cap_bytes > 0 && bytes_ > cfg_.mem_cap_bytes) throw std::bad_alloc();
@@ -1464,6 +1586,9 @@ class Box final : public BoxBase {
       timed(QSP_K_ROW_INV, [&] { launch_row_inv<T>(geom_, r, 4, tx(), st_); });
       dst_solves_ += 3;
     }
+    // predictor-corrector iterations launched for this slice
+    const int pc_launch = budget_on_ ? budget_launch_[k] : cfg_.pc_max_iter;
+    const int budgeted = pc_launch < cfg_.pc_max_iter ? 1 : 0;
     // Bx/By (Sec. II step 7, Sec. III.B): explicit solver or predictor-corrector
     if (explicit_) {
       explicit_bxby(k, dc, amp, bxk, byk);
@@ -1503,7 +1628,7 @@ class Box final : public BoxBase {
         c.zero.p[1] = trial_[1];
         c.zero.count = 2;
         c.zero.n = pl;
-        for (int m = 0; m < cfg_.pc_max_iter; ++m) {
+        for (int m = 0; m < pc_launch; ++m) {
           a.pc_iter = m;
           // the first trial push of the slice leaves the record the later
           // ones start from (and on a taped slice the slice-k particle state)
@@ -1545,7 +1670,9 @@ class Box final : public BoxBase {
         a.pc_nblk = pc_partial_count(geom_);
       }
       a.iters_out = iters_out;
+      a.iters_own = iters_own_ + k;
       a.resid_out = resid_out;
+      a.pc_budgeted = budgeted;
       if (beam_n_ > 0) {
         // the launch also pushes slice k's beam particles and deposits
         // slice k+1's (into the planes it deposits the plasma into)
@@ -1563,7 +1690,7 @@ class Box final : public BoxBase {
       if (capturing_ && timer_.active(cursor_)) {
         // the sampled launch runs between graph segments, under its events
         end_segment();
-        graph_.items.push_back({nullptr, std::function<void()>(job), QSP_K_PUSH});
+        cap_graph_->items.push_back({nullptr, std::function<void()>(job), QSP_K_PUSH});
         begin_segment();
       } else {
         timed(QSP_K_PUSH, job);
@@ -1571,7 +1698,8 @@ class Box final : public BoxBase {
       pushes_ += lat_.np;
     } else {
       timed(QSP_K_OTHER, [&] {
-        launch_slice_end(ctr_, iters_out, resid_out, cfg_.pc_tol, cfg_.pc_max_iter,
+        launch_slice_end(ctr_, iters_out, iters_own_ + k, resid_out, cfg_.pc_tol, cfg_.pc_max_iter,
+                         budgeted,
                          explicit_ ? nullptr : partial_, pc_partial_count(geom_), st_);
       });
     }
@@ -1741,7 +1869,20 @@ class Box final : public BoxBase {
   bool capturing_ = false;
   hipStream_t cap_st_ = nullptr;  // capture stream
   uint64_t launch_version_ = 0;
-  BoxGraph graph_;
+  // speculative P-C launch budgets (run_box_graphs)
+  int32_t* iters_own_ = nullptr;   // per-slice iteration counts of the last box
+  std::vector<int> budget_;          // learned: iterations the slices needed so far
+  std::vector<int> budget_launch_;   // launched in the speculative box
+  std::vector<int> margin_;          // 1: the slice's count has risen before
+  bool budget_ready_ = false;
+  uint64_t budget_version_ = 0;    // launch_version_ the budgets were learned under
+  bool budget_on_ = false;         // step() launches budget_[k] iterations
+  int spec_mode_ = 1;
+  bool fresh_box_ = false;         // plasma as init_plasma left it, cursor 0
+  int64_t box_reruns_ = 0;
+  BoxGraph graph_;     // every slice launches pc_max_iter P-C iterations
+  BoxGraph graph_b_;   // launches as many as the budgets hold
+  BoxGraph* cap_graph_ = nullptr;   // the graph being captured
   // explicit Bx/By solver: deposits chi, DJx, DJy and the Krylov vectors
   double* ex_dep_[3] = {nullptr, nullptr, nullptr};
   double *ex_x_ = nullptr, *ex_r_ = nullptr, *ex_q_ = nullptr;

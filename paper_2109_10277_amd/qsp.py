@@ -79,7 +79,7 @@ class Stats(C.Structure):
                 ("n_clamped", C.c_int64), ("n_absorbed", C.c_int64),
                 ("n_deposit_global", C.c_int64), ("dst_solves", C.c_int64),
                 ("max_pc_residual", C.c_double), ("elapsed_ms", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("box_reruns", C.c_int64)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
