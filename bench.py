@@ -90,16 +90,17 @@ def workload(name: str):
 
 def push_bytes(cfg, fsize: int, n_beam: int = 0) -> int:
     """Algorithmic HBM bytes of one real push launch: every particle reads
-    its state (x, y, ux, uy, Psi, w) and 4 history slots x 5 quantities and
-    writes 5 state + 5 history values; the six field planes are read once
-    and the four FP64 deposit planes (rho - Jz, Jx, Jy, Jz) written once.
+    its state (x, y, ux, uy, Psi, w), the Adams-Bashforth history part P
+    (5) and 3 history slots x 5 quantities, and writes 5 state + 5 history
+    values and the next P (5); the six field planes are read once and the
+    four FP64 deposit planes (rho - Jz, Jx, Jy, Jz) written once.
     A launch also carries the beam work of its slice: every beam particle
     is pushed once per box (6 FP32 values read and written) and deposited
     once (6 read), 72 B, spread over the nzeta - 1 real pushes."""
     n_p = cfg.nx * cfg.ppc_x * cfg.ny * cfg.ppc_y
     plane = cfg.nx * cfg.ny
     beam = n_beam * 72 // max(cfg.nzeta - 1, 1)
-    return n_p * (26 + 10) * fsize + 6 * plane * fsize + 4 * plane * 8 + beam
+    return n_p * (26 + 15) * fsize + 6 * plane * fsize + 4 * plane * 8 + beam
 
 
 def make_box(cfg, beam, precision, soa=None):

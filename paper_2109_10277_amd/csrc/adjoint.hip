@@ -639,18 +639,28 @@ __global__ void __launch_bounds__(kBlock) k_loss(Geom g, LossArgs<T> a) {
 }
 
 template <typename T>
-__global__ void k_copy_particles(Lattice L, Particles<T> src, Particles<T> dst) {
+__global__ void k_copy_particles(Lattice L, Particles<T> src, Particles<T> dst, int k, T dz) {
   const size_t np = static_cast<size_t>(L.np);
   const size_t stride = static_cast<size_t>(gridDim.x) * blockDim.x;
+  // history slots of f_{k-1}, ..., f_{k-4}
+  const int s1 = (k + 3) & 3, s2 = (k + 2) & 3, s3 = (k + 1) & 3, s4 = k & 3;
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < np; i += stride) {
-    dst.xi_x[i] = src.xi_x[i];
-    dst.xi_y[i] = src.xi_y[i];
-    dst.ux[i] = src.ux[i];
-    dst.uy[i] = src.uy[i];
-    dst.psi[i] = src.psi[i];
+    T y[5] = {src.xi_x[i], src.xi_y[i], src.ux[i], src.uy[i], src.psi[i]};
+    dst.xi_x[i] = y[0];
+    dst.xi_y[i] = y[1];
+    dst.ux[i] = y[2];
+    dst.uy[i] = y[3];
+    dst.psi[i] = y[4];
     dst.w[i] = src.w[i];
 #pragma unroll
     for (int c = 0; c < 20; ++c) dst.hist[c * np + i] = src.hist[c * np + i];
+    if (dst.pab) {
+      const T* h = src.hist;
+#pragma unroll
+      for (int c = 0; c < 5; ++c)
+        dst.pab[c * np + i] = ab5_history(y[c], h[(s1 * 5 + c) * np + i], h[(s2 * 5 + c) * np + i],
+                                          h[(s3 * 5 + c) * np + i], h[(s4 * 5 + c) * np + i], dz);
+    }
   }
 }
 
@@ -779,9 +789,9 @@ void launch_loss(const Geom& g, const LossArgs<T>& a, hipStream_t st) {
 
 template <typename T>
 void launch_copy_particles(const Lattice& L, const Particles<T>& src, const Particles<T>& dst,
-                           hipStream_t st) {
+                           int k, double dzeta, hipStream_t st) {
   hipLaunchKernelGGL(k_copy_particles<T>, g1(static_cast<size_t>(L.np)), dim3(kBlock), 0, st, L, src,
-                     dst);
+                     dst, k, static_cast<T>(dzeta));
   QSP_LAUNCH_CHECK();
 }
 
@@ -805,7 +815,7 @@ void launch_copy_planes(size_t n, int count, const CopyPlanes<T, U>& c, hipStrea
   template void launch_adj_source<T>(const Geom&, const AdjSrcArgs<T>&, hipStream_t);           \
   template void launch_loss<T>(const Geom&, const LossArgs<T>&, hipStream_t);                   \
   template void launch_copy_particles<T>(const Lattice&, const Particles<T>&,                   \
-                                         const Particles<T>&, hipStream_t);                     \
+                                         const Particles<T>&, int, double, hipStream_t);        \
   template void launch_copy_planes<T, T>(size_t, int, const CopyPlanes<T, T>&, hipStream_t);
 QSP_INST(float)
 QSP_INST(double)

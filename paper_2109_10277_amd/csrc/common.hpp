@@ -22,6 +22,15 @@ constexpr int kMaxOut = 36;
 constexpr double kAB5[5] = {1901.0 / 720.0, -2774.0 / 720.0, 2616.0 / 720.0,
                             -1274.0 / 720.0, 251.0 / 720.0};
 
+// History part of an Adams-Bashforth step from slice k: y_k - dz (b1 f_{k-1}
+// + b2 f_{k-2} + b3 f_{k-3} + b4 f_{k-4}), so that y_{k+1} = P_k - dz b0 f_k.
+// One function for every place that forms it (the real push, state import,
+// checkpoint restore), so that they round alike.
+template <typename T>
+__host__ __device__ __forceinline__ T ab5_history(T y, T f1, T f2, T f3, T f4, T dz) {
+  return y - dz * (T(kAB5[1]) * f1 + T(kAB5[2]) * f2 + T(kAB5[3]) * f3 + T(kAB5[4]) * f4);
+}
+
 struct DeviceError : std::runtime_error {
   using std::runtime_error::runtime_error;
 };

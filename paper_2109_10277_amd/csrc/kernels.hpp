@@ -122,6 +122,11 @@ struct Particles {          // SoA, lattice order
   T* psi;
   T* w;                     // density weight n0/(ppc_x ppc_y); 0 = absorbed
   T* hist;                  // [4][5][np], slot s holds f of a slice = s mod 4
+  // [5][np] Adams-Bashforth history part ab5_history of the slice the state
+  // belongs to (the real push leaves it for the next slice; the first trial
+  // push reads it instead of the history).  Null in saved copies of the
+  // state (checkpoints, tapes), which restore it from the history.
+  T* pab;
 };
 
 template <typename T>
@@ -207,7 +212,7 @@ template <typename T>
 void launch_import_state(const Geom&, const Lattice&, const Particles<T>&, const double* x,
                          const double* y, const double* ux, const double* uy,
                          const double* psi, const double* w, const double* hist, int k,
-                         hipStream_t);
+                         double dzeta, hipStream_t);
 template <typename T>
 void launch_export_state(const Geom&, const Lattice&, const Particles<T>&, double* x,
                          double* y, double* ux, double* uy, double* psi, double* w,
@@ -447,8 +452,10 @@ void launch_adj_source(const Geom&, const AdjSrcArgs<T>&, hipStream_t);
 template <typename T>
 void launch_loss(const Geom&, const LossArgs<T>&, hipStream_t);
 template <typename T>
+// copies state and history; where dst keeps the history part P (pab), it
+// is formed from the copied state of slice k (step dzeta)
 void launch_copy_particles(const Lattice&, const Particles<T>& src, const Particles<T>& dst,
-                           hipStream_t);
+                           int k, double dzeta, hipStream_t);
 template <typename T, typename U>
 void launch_copy_planes(size_t n, int count, const CopyPlanes<T, U>&, hipStream_t);
 

@@ -15,8 +15,16 @@ using push_detail::push_tile;
 using push_detail::tile_shape;
 using push_detail::TileShape;
 
+// Waves per SIMD the compiler keeps room for: the FP32 linear-shape real
+// push is held to five (its histogram tiles already allow five workgroups
+// per CU); the other instances take what their registers allow.
 template <typename T, int MODE, int O>
-__global__ void __launch_bounds__(kBlock)
+constexpr int push_waves() {
+  return sizeof(T) == 4 && MODE == kPushReal && O == 1 ? 5 : 1;
+}
+
+template <typename T, int MODE, int O>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(push_waves<T, MODE, O>())))
 k_push(Geom g, Lattice L, PushArgs<T> a, DevCounters* ctr) {
   const bool first = blockIdx.x == 0 && blockIdx.y == 0;
   if (MODE == kPushTrial || MODE == kPushTrialTape || MODE == kTrialLater) {
@@ -84,13 +92,16 @@ __global__ void k_init_plasma(Lattice L, Particles<T> p, T w0) {
     p.w[i] = w0;
 #pragma unroll
     for (int c = 0; c < 20; ++c) p.hist[c * np + i] = T(0);
+#pragma unroll
+    for (int c = 0; c < 5; ++c) p.pab[c * np + i] = T(0);
   }
 }
 
 template <typename T>
 __global__ void k_import_state(Geom g, Lattice L, Particles<T> p, const double* x,
                                const double* y, const double* ux, const double* uy,
-                               const double* psi, const double* w, const double* hist, int k) {
+                               const double* psi, const double* w, const double* hist, int k,
+                               double dzeta) {
   const size_t np = static_cast<size_t>(L.np);
   for (size_t i = blockIdx.x * static_cast<size_t>(blockDim.x) + threadIdx.x; i < np;
        i += static_cast<size_t>(gridDim.x) * blockDim.x) {
@@ -102,15 +113,21 @@ __global__ void k_import_state(Geom g, Lattice L, Particles<T> p, const double* 
     p.uy[i] = static_cast<T>(uy[i]);
     p.psi[i] = static_cast<T>(psi[i]);
     p.w[i] = static_cast<T>(w[i]);
+    T hv[4][5];
     for (int m = 0; m < 4; ++m) {
       const int slot = (k - 1 - m + 8) & 3;
       for (int c = 0; c < 5; ++c) {
         double v = hist[(m * 5 + c) * np + i];
         if (c == 0) v /= g.hx;
         if (c == 1) v /= g.hy;
-        p.hist[(slot * 5 + c) * np + i] = static_cast<T>(v);
+        hv[m][c] = static_cast<T>(v);
+        p.hist[(slot * 5 + c) * np + i] = hv[m][c];
       }
     }
+    const T y[5] = {p.xi_x[i], p.xi_y[i], p.ux[i], p.uy[i], p.psi[i]};
+    const T dz = static_cast<T>(dzeta);
+    for (int c = 0; c < 5; ++c)
+      p.pab[c * np + i] = ab5_history(y[c], hv[0][c], hv[1][c], hv[2][c], hv[3][c], dz);
   }
 }
 
@@ -221,9 +238,9 @@ template <typename T>
 void launch_import_state(const Geom& g, const Lattice& L, const Particles<T>& p,
                          const double* x, const double* y, const double* ux, const double* uy,
                          const double* psi, const double* w, const double* hist, int k,
-                         hipStream_t st) {
+                         double dzeta, hipStream_t st) {
   hipLaunchKernelGGL(k_import_state<T>, grid_1d(L.np), dim3(kBlock), 0, st, g, L, p, x, y, ux,
-                     uy, psi, w, hist, k);
+                     uy, psi, w, hist, k, dzeta);
   QSP_LAUNCH_CHECK();
 }
 
@@ -244,7 +261,7 @@ void launch_export_state(const Geom& g, const Lattice& L, const Particles<T>& p,
   template void launch_import_state<T>(const Geom&, const Lattice&, const Particles<T>&,    \
                                        const double*, const double*, const double*,         \
                                        const double*, const double*, const double*,         \
-                                       const double*, int, hipStream_t);                    \
+                                       const double*, int, double, hipStream_t);            \
   template void launch_export_state<T>(const Geom&, const Lattice&, const Particles<T>&,    \
                                        double*, double*, double*, double*, double*,         \
                                        double*, double*, int, hipStream_t);

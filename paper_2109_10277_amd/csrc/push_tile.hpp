@@ -186,7 +186,7 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
   const T inv_hx = static_cast<T>(1.0 / a.hx), inv_hy = static_cast<T>(1.0 / a.hy);
   const T floor_d = static_cast<T>(a.psi_floor);
   const T dz = static_cast<T>(a.dzeta);
-  const T b0 = T(kAB5[0]), b1 = T(kAB5[1]), b2 = T(kAB5[2]), b3 = T(kAB5[3]), b4 = T(kAB5[4]);
+  const T b0 = T(kAB5[0]);
   const size_t np = static_cast<size_t>(L.np);
   T* hist = a.p.hist;
   const int s_new = a.k & 3;
@@ -256,13 +256,20 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
     bool alive = w != T(0);
 
     if (MODE != kDepositOnly) {
+      // the history part P_k of the step (written by the previous real push)
+      // and, for the real push, f_{k-1}, f_{k-2}, f_{k-3} (which form P_{k+1}
+      // with f_k); a taped push reads every slot for the tape
+      T pk[5];
       T h[4][5];
 #pragma unroll
       for (int c = 0; c < 5; ++c) {
-        h[0][c] = hist[(s1 * 5 + c) * np + p];
-        h[1][c] = hist[(s2 * 5 + c) * np + p];
-        h[2][c] = hist[(s3 * 5 + c) * np + p];
-        h[3][c] = hist[(s4 * 5 + c) * np + p];
+        pk[c] = a.p.pab[c * np + p];
+        if constexpr (MODE == kPushReal || TAPE) {
+          h[0][c] = hist[(s1 * 5 + c) * np + p];
+          h[1][c] = hist[(s2 * 5 + c) * np + p];
+          h[2][c] = hist[(s3 * 5 + c) * np + p];
+        }
+        if constexpr (TAPE) h[3][c] = hist[(s4 * 5 + c) * np + p];
       }
       if constexpr (MODE == kPushTrial && TAPE) {
         // the state the reverse pass of this slice starts from
@@ -335,10 +342,9 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
         f[3] = gam * id * e2 - bx - bz * ux * id;
       }
       f[4] = (ux * e1 + uy * e2) * id - ez;
-      T y[5] = {xi, eta, ux, uy, psi};
+      T y[5];
 #pragma unroll
-      for (int c = 0; c < 5; ++c)
-        y[c] = y[c] - dz * (b0 * f[c] + b1 * h[0][c] + b2 * h[1][c] + b3 * h[2][c] + b4 * h[3][c]);
+      for (int c = 0; c < 5; ++c) y[c] = pk[c] - dz * (b0 * f[c]);
       if constexpr (MODE == kPushTrial) {
         const T cx = y[2], cy = y[3];
         const T kick = dz * b0;
@@ -368,14 +374,17 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
       ux = y[2];
       uy = y[3];
       psi = y[4];
-      if (MODE == kPushReal) {
+      if constexpr (MODE == kPushReal) {
         a.p.xi_x[p] = xi;
         a.p.xi_y[p] = eta;
         a.p.ux[p] = ux;
         a.p.uy[p] = uy;
         a.p.psi[p] = psi;
 #pragma unroll
-        for (int c = 0; c < 5; ++c) hist[(s_new * 5 + c) * np + p] = f[c];
+        for (int c = 0; c < 5; ++c) {
+          hist[(s_new * 5 + c) * np + p] = f[c];
+          a.p.pab[c * np + p] = ab5_history(y[c], f[c], h[0][c], h[1][c], h[2][c], dz);
+        }
       }
     } else if (!alive) {
       continue;

@@ -498,7 +498,7 @@ class Box final : public BoxBase {
       h2d(g + 4 * nn, s->bx_prev2, nn);
       h2d(g + 5 * nn, s->by_prev2, nn);
       launch_import_state<T>(geom_, lat_, p_, q, q + np, q + 2 * np, q + 3 * np, q + 4 * np,
-                             q + 5 * np, q + 6 * np, s->k, st_);
+                             q + 5 * np, q + 6 * np, s->k, cfg_.dzeta, st_);
       for (int d = 0; d < 3; ++d)
         for (int c = 0; c < 5; ++c) launch_zero(dep_[d][c], plane(), st_);
       launch_zero(trial_[0], plane(), st_);
@@ -1041,7 +1041,7 @@ class Box final : public BoxBase {
 
   void save_checkpoint(int c) {
     Checkpoint<T>& ck = ckpt_[c];
-    launch_copy_particles<T>(lat_, p_, ck.p, st_);
+    launch_copy_particles<T>(lat_, p_, ck.p, cursor_, cfg_.dzeta, st_);
     CopyPlanes<double, double> j{};
     j.src[0] = dep_[ip_][1];
     j.src[1] = dep_[ip_][2];
@@ -1059,7 +1059,7 @@ class Box final : public BoxBase {
 
   void restore_checkpoint(int c) {
     const Checkpoint<T>& ck = ckpt_[c];
-    launch_copy_particles<T>(lat_, ck.p, p_, st_);
+    launch_copy_particles<T>(lat_, ck.p, p_, c * rec_K_, cfg_.dzeta, st_);
     CopyPlanes<double, double> j{};
     j.src[0] = ck.j[0];
     j.src[1] = ck.j[1];
@@ -1390,6 +1390,7 @@ class Box final : public BoxBase {
     p_.psi = alloc<T>(np);
     p_.w = alloc<T>(np);
     p_.hist = alloc<T>(20 * np);
+    p_.pab = alloc<T>(5 * np);
     twx_ = alloc<Cplx<T>>(2 * cfg_.nx);
     prex_ = alloc<T>(cfg_.nx);
     lamx_ = alloc<double>(cfg_.nx);
