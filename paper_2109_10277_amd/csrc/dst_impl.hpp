@@ -1070,7 +1070,7 @@ __device__ __forceinline__ void src_bxby_block(const Geom& g, const SrcBxBy<T>& 
       // -d_y Jz + (Jy_{k-1} - Jy_{k+1}) / (2 dzeta) - shift * Bx_old
       const int js = j > 0 ? j - 1 : 0;
       const double zs = a.jz[js * n + i], zn = a.jz[(j + 1 < g.ny ? j + 1 : j) * n + i];
-      const double yp = a.jy_prev[o], yt = a.jy_next[o];
+      const double yp = a.jy_prev[o], yt = a.jy_next[o] + a.sy_next[o];
       const double bo = static_cast<double>(a.bx[o]);
       const double gx = a.bgx[i], gs = a.bgy[js], gn = a.bgy[j + 1];
       const double jz_s = zs - amp * gx * gs;
@@ -1080,7 +1080,7 @@ __device__ __forceinline__ void src_bxby_block(const Geom& g, const SrcBxBy<T>& 
       // d_x Jz - (Jx_{k-1} - Jx_{k+1}) / (2 dzeta) - shift * By_old
       const int iw = i > 0 ? i - 1 : 0;
       const double zw = a.jz[j * n + iw], ze = a.jz[j * n + (i + 1 < n ? i + 1 : i)];
-      const double xp = a.jx_prev[o], xt = a.jx_next[o];
+      const double xp = a.jx_prev[o], xt = a.jx_next[o] + a.sx_next[o];
       const double bo = static_cast<double>(a.by[o]);
       const double gy = a.bgy[j], gw = a.bgx[iw], ge = a.bgx[i + 1];
       const double jz_w = zw - amp * gw * gy;

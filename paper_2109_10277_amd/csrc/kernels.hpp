@@ -25,8 +25,10 @@ struct SrcBxBy {            // Bx, By corrector sources
   const double* jz;         // Jz of slice k (plasma + particle beam)
   const double* jx_prev;    // J_perp of slice k-1
   const double* jy_prev;
-  const double* jx_next;    // trial J_perp of slice k+1
+  const double* jx_next;    // trial J_perp of slice k+1 (owner planes)
   const double* jy_next;
+  const double* sx_next;    // and their shared planes (DepOut::sh)
+  const double* sy_next;
   const T* bx;              // current iterate
   const T* by;
   double shift, dzeta;
@@ -139,8 +141,16 @@ struct SliceFields {        // the six fields a particle sees
   const T* bz;
 };
 
+// Deposit planes.  With tile histograms and shared planes (sh non-null: the
+// trial pushes), a workgroup stores the nodes of its own tile's cells into
+// ch with plain stores (every node of the lattice belongs to exactly one
+// tile, so ch needs no clearing) and adds its halo nodes and its
+// far-travelled particles to sh with atomics; readers take ch + sh.
+// Without tiles or shared planes every deposit is an atomic add to ch
+// (cleared beforehand).
 struct DepOut {
   double* ch[4];            // rho-Jz, Jx, Jy, Jz (rho is formed as (rho - Jz) + Jz)
+  double* sh[4];            // shared planes of the same channels (nullable)
 };
 
 // kExplicitDep: no push; deposit the explicit Bx/By solver's chi, DJx, DJy

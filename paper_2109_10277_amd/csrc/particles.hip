@@ -188,6 +188,11 @@ void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode
     throw std::invalid_argument("beam work of a real push: bad arguments");
   const int ntx = L.nX / ts.tx;
   const dim3 grid(ntx, L.nY / ts.ty + (extra + ntx - 1) / ntx);
+  // an owner flush writes every node once only if the tiles cover the lattice
+  if (L.nX % ts.tx || L.nY % ts.ty)
+    throw std::invalid_argument("push tiles must divide the particle lattice");
+  if (a.dep.sh[0] && !trial)
+    throw std::invalid_argument("shared deposit planes are for the trial pushes");
   if (mode == kTrialLater && !a.rec)
     throw std::invalid_argument("a later trial push needs the first one's record");
   if (mode == kPushTrialTape && !a.tape)

@@ -7,8 +7,9 @@
 // that small displacements keep full precision.  A workgroup owns a tile of
 // lattice sites; its particles deposit into FP64 histograms in LDS covering
 // the tile's cells plus a halo, which are then added to the global FP64
-// deposit arrays with one atomic per non-zero node.  Particles that have
-// left the tile+halo fall back to global FP64 atomics.
+// deposit arrays: the nodes of the tile's own cells with plain stores, the
+// halo nodes with one atomic per non-zero node into shared planes (DepOut).
+// Particles that have left the tile+halo fall back to global FP64 atomics.
 #pragma once
 
 #include "common.hpp"
@@ -102,6 +103,44 @@ __device__ __forceinline__ void flush_tile(double* const* ch, const double* tile
   }
 }
 
+// Owner form of flush_tile: the nodes of the tile's own cells (local
+// columns halo .. halo + tx/ppc_x - 1, rows likewise) are stored into ch[c],
+// zeros included; the other non-zero nodes are added to sh[c] with atomics.
+template <int nch>
+__device__ __forceinline__ void flush_tile_owned(double* const* ch, double* const* sh,
+                                                 const double* tile, const TileShape& ts, int ox,
+                                                 int oy, int nx, int ny) {
+  const int ntile = ts.nw * ts.nh;
+  const unsigned int ocx = static_cast<unsigned int>(ts.tx >> ts.lpx);
+  const unsigned int ocy = static_cast<unsigned int>(ts.ty >> ts.lpy);
+  const int step_r = kBlock / ts.nw, step_c = kBlock % ts.nw;
+  int r = threadIdx.x / ts.nw, cl = threadIdx.x % ts.nw;
+  for (int l = threadIdx.x; l < ntile; l += kBlock) {
+    const int gi = ox + cl, gj = oy + r;
+    if (gi >= 1 && gi < nx && gj >= 1 && gj < ny) {
+      const size_t o = static_cast<size_t>(gj) * nx + gi;
+      const bool own = static_cast<unsigned int>(cl - ts.halo) < ocx &&
+                       static_cast<unsigned int>(r - ts.halo) < ocy;
+      double val[nch];
+#pragma unroll
+      for (int c = 0; c < nch; ++c) val[c] = tile[c * ntile + l];
+#pragma unroll
+      for (int c = 0; c < nch; ++c) {
+        if (own)
+          ch[c][o] = val[c];
+        else if (val[c] != 0.0)
+          global_add(sh[c] + o, val[c]);
+      }
+    }
+    r += step_r;
+    cl += step_c;
+    if (cl >= ts.nw) {
+      cl -= ts.nw;
+      ++r;
+    }
+  }
+}
+
 __device__ inline unsigned long long block_sum(unsigned int v, unsigned int* red) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -116,11 +155,12 @@ __device__ inline unsigned long long block_sum(unsigned int v, unsigned int* red
 
 // Deposit of one particle: nch values v at offset (xi, eta) from its
 // lattice cell origin (ci0 + fx0, cj0 + fy0) into the tile histogram, or
-// straight to the global planes when the stencil leaves the tile (counted
-// in nglob).
+// straight to the global planes (the shared ones for an owner flush) when
+// the stencil leaves the tile (counted in nglob).
 template <typename T, int O, int nch>
 __device__ __forceinline__ void deposit_particle(const DepOut& dep, double* tile, const TileShape& ts,
-                                                 int ox, int oy, int nx, int ny, bool tiled, int ci0,
+                                                 int ox, int oy, int nx, int ny, bool tiled,
+                                                 bool owner, int ci0,
                                                  int cj0, T fx0, T fy0, T xi, T eta,
                                                  const double (&v)[4], unsigned int& nglob) {
   const int ntile = ts.nw * ts.nh;
@@ -153,7 +193,7 @@ __device__ __forceinline__ void deposit_particle(const DepOut& dep, double* tile
         const size_t o = static_cast<size_t>(gj) * nx + gi;
         const double s = sx[qa] * sy[qb];
 #pragma unroll
-        for (int c = 0; c < nch; ++c) global_add(dep.ch[c] + o, v[c] * s);
+        for (int c = 0; c < nch; ++c) global_add((owner ? dep.sh[c] : dep.ch[c]) + o, v[c] * s);
       }
     }
   }
@@ -175,6 +215,7 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
   const TileShape ts = tile_shape(L, a.tile_rows, a.tile_halo);
   const int ntile = ts.nw * ts.nh;
   const bool tiled = a.tiled != 0;
+  const bool owner = tiled && a.dep.sh[0] != nullptr;
   if (tiled) {
     __syncthreads();   // a previous tile's flush has read the histogram
     for (int e = threadIdx.x; e < nch * ntile; e += kBlock) tile[e] = 0.0;
@@ -242,8 +283,8 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
       const T kick = dz * b0;
       const double v[4] = {static_cast<double>(fac * (cx - kick * by)),
                            static_cast<double>(fac * (cy + kick * bx)), 0.0, 0.0};
-      deposit_particle<T, O, nch>(a.dep, tile, ts, ox, oy, nx, ny, tiled, ci0, cj0, fx0, fy0, xn,
-                                  en, v, nglob);
+      deposit_particle<T, O, nch>(a.dep, tile, ts, ox, oy, nx, ny, tiled, owner, ci0, cj0, fx0,
+                                  fy0, xn, en, v, nglob);
       continue;
     }
     // every load of the particle is issued before any decision on it
@@ -408,13 +449,16 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
       v[2] = static_cast<double>(-w * uy * id);
       v[3] = static_cast<double>(-w * uz * id);
     }
-    deposit_particle<T, O, nch>(a.dep, tile, ts, ox, oy, nx, ny, tiled, ci0, cj0, fx0, fy0, xi, eta,
-                                v, nglob);
+    deposit_particle<T, O, nch>(a.dep, tile, ts, ox, oy, nx, ny, tiled, owner, ci0, cj0, fx0, fy0,
+                                xi, eta, v, nglob);
   }
 
   if (tiled) {
     __syncthreads();
-    flush_tile<nch>(a.dep.ch, tile, ts, ox, oy, nx, ny);
+    if (owner)
+      flush_tile_owned<nch>(a.dep.ch, a.dep.sh, tile, ts, ox, oy, nx, ny);
+    else
+      flush_tile<nch>(a.dep.ch, tile, ts, ox, oy, nx, ny);
   }
   // counters
   const unsigned long long tc = block_sum(nclamp, red);

@@ -271,6 +271,7 @@ class Box final : public BoxBase {
       for (int c = 0; c < 5; ++c) launch_zero(dep_[d][c], plane(), st_);
     launch_zero(trial_[0], plane(), st_);
     launch_zero(trial_[1], plane(), st_);
+    zero_shared();
     launch_zero_t<T>(t1_, 4 * plane(), st_);
     launch_zero_t<T>(t2_, 4 * plane(), st_);
     static_assert(sizeof(DevCounters) % sizeof(double) == 0, "counter block size");
@@ -503,6 +504,7 @@ class Box final : public BoxBase {
         for (int c = 0; c < 5; ++c) launch_zero(dep_[d][c], plane(), st_);
       launch_zero(trial_[0], plane(), st_);
       launch_zero(trial_[1], plane(), st_);
+      zero_shared();
       launch_from_nodes<double, double>(geom_, g, dep_[ip_][1], st_);
       launch_from_nodes<double, double>(geom_, g + nn, dep_[ip_][2], st_);
       launch_from_nodes<double, T>(geom_, g + 2 * nn, b_[i1_][0], st_);
@@ -1381,6 +1383,8 @@ class Box final : public BoxBase {
       for (int c = 0; c < 5; ++c) dep_[d][c] = alloc<double>(pl);
     trial_[0] = alloc<double>(pl);
     trial_[1] = alloc<double>(pl);
+    trial_sh_[0] = alloc<double>(pl);
+    trial_sh_[1] = alloc<double>(pl);
     if (!explicit_) trial_rec_ = alloc<T>(6 * static_cast<size_t>(lat_.np));
     const size_t np = static_cast<size_t>(lat_.np);
     p_.xi_x = alloc<T>(np);
@@ -1480,6 +1484,11 @@ class Box final : public BoxBase {
   AxisTables<T> tx() const { return {twx_, prex_, lamx_}; }
   AxisTables<T> ty() const { return {twy_, prey_, lamy_}; }
 
+  void zero_shared() {
+    launch_zero(trial_sh_[0], plane(), st_);
+    launch_zero(trial_sh_[1], plane(), st_);
+  }
+
   void to_nodes_d(const double* src, double* dst) { launch_to_nodes<double>(geom_, src, dst, st_); }
 
   void add_out(OutCopy& oc, int q, void* dst, int kind) {
@@ -1529,6 +1538,7 @@ class Box final : public BoxBase {
     if (!dep_valid_) {
       timed(QSP_K_OTHER, [&] {
         for (int c = 0; c < 5; ++c) launch_zero(dc[c], pl, st_);
+        zero_shared();
       });
       PushArgs<T> a = push_args(fields(b_[ik_][0], b_[ik_][1]), dc, k);
       timed(QSP_K_OTHER, [&] { launch_push<T>(geom_, lat_, a, kDepositOnly, ctr_, st_); });
@@ -1595,7 +1605,7 @@ class Box final : public BoxBase {
       explicit_bxby(k, dc, amp, bxk, byk);
     } else {
       {
-        PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2);
+        PushArgs<T> a = push_args(fields(bxk, byk), trial_, k, 2, trial_sh_);
         // taped slices keep their record for the reverse pass
         a.rec = tape_slot_ ? tape_slot_->rec : trial_rec_;
         // a slot's particle arrays are one block of 26 planes (alloc_particles)
@@ -1609,6 +1619,8 @@ class Box final : public BoxBase {
         s.jy_prev = dp[2];
         s.jx_next = trial_[0];
         s.jy_next = trial_[1];
+        s.sx_next = trial_sh_[0];
+        s.sy_next = trial_sh_[1];
         s.bx = bxk;
         s.by = byk;
         s.shift = shift_;
@@ -1624,9 +1636,10 @@ class Box final : public BoxBase {
         c.shift[0] = c.shift[1] = shift_;
         c.honor_done = 1;
         c.w = col_width<T>(geom_, 2);
-        // the trial currents have been read: clear them for the next trial
-        c.zero.p[0] = trial_[0];
-        c.zero.p[1] = trial_[1];
+        // the trial currents have been read: clear what the next trial adds
+        // into (the shared planes; with no tiles the owner planes)
+        c.zero.p[0] = tiled_ ? trial_sh_[0] : trial_[0];
+        c.zero.p[1] = tiled_ ? trial_sh_[1] : trial_[1];
         c.zero.count = 2;
         c.zero.n = pl;
         for (int m = 0; m < pc_launch; ++m) {
@@ -1780,11 +1793,15 @@ class Box final : public BoxBase {
     dst_solves_ += 2 * (cfg_.pc_max_iter);
   }
 
-  PushArgs<T> push_args(const SliceFields<T>& f, double* const* ch, int k, int nch = 4) {
+  PushArgs<T> push_args(const SliceFields<T>& f, double* const* ch, int k, int nch = 4,
+                        double* const* sh = nullptr) {
     PushArgs<T> a{};
     a.p = p_;
     a.f = f;
-    for (int c = 0; c < nch; ++c) a.dep.ch[c] = ch[c];
+    for (int c = 0; c < nch; ++c) {
+      a.dep.ch[c] = ch[c];
+      a.dep.sh[c] = sh ? sh[c] : nullptr;
+    }
     a.k = k;
     a.dzeta = cfg_.dzeta;
     a.hx = geom_.hx;
@@ -1834,6 +1851,9 @@ class Box final : public BoxBase {
   T *t1_ = nullptr, *t2_ = nullptr;
   double* dep_[3][5] = {};
   double* trial_[2] = {};
+  // shared deposit planes of the trial pushes (DepOut::sh), cleared by each
+  // predictor-corrector iteration's column pass
+  double* trial_sh_[2] = {};
   T* trial_rec_ = nullptr;   // record of the slice's first trial push
   Particles<T> p_{};
   Cplx<T>* twx_ = nullptr;
