@@ -17,10 +17,13 @@ using push_detail::TileShape;
 
 // Waves per SIMD the compiler keeps room for: the FP32 linear-shape real
 // push is held to five (its histogram tiles already allow five workgroups
-// per CU); the other instances take what their registers allow.
+// per CU), the FP32 linear-shape later trial push to eight (all 2048 tiles
+// of a 1024^2 lattice resident at once); the other instances take what
+// their registers allow.
 template <typename T, int MODE, int O>
 constexpr int push_waves() {
-  return sizeof(T) == 4 && MODE == kPushReal && O == 1 ? 5 : 1;
+  if (sizeof(T) != 4 || O != 1) return 1;
+  return MODE == kPushReal ? 5 : MODE == kTrialLater ? 8 : 1;
 }
 
 template <typename T, int MODE, int O>
@@ -188,6 +191,11 @@ void launch_push(const Geom& g, const Lattice& L, const PushArgs<T>& a, PushMode
     throw std::invalid_argument("beam work of a real push: bad arguments");
   const int ntx = L.nX / ts.tx;
   const dim3 grid(ntx, L.nY / ts.ty + (extra + ntx - 1) / ntx);
+  // the later trial push and the gathers address a particle or field plane
+  // with 32-bit byte offsets
+  if (static_cast<uint64_t>(L.np) * sizeof(T) >= (1ull << 32) ||
+      static_cast<uint64_t>(g.nx) * g.ny * sizeof(T) >= (1ull << 32))
+    throw std::invalid_argument("a particle or field plane of 4 GiB or more");
   // an owner flush writes every node once only if the tiles cover the lattice
   if (L.nX % ts.tx || L.nY % ts.ty)
     throw std::invalid_argument("push tiles must divide the particle lattice");

@@ -44,6 +44,15 @@ __host__ __device__ inline TileShape tile_shape(const Lattice& L, int rows, int 
   return t;
 }
 
+// base[i] with the byte offset formed in 32 bits (the caller guarantees
+// i * sizeof(T) < 2^32), so that a uniform base loads through one VGPR of
+// offset instead of a 64-bit address per lane
+template <typename T>
+__device__ __forceinline__ T load_at(const T* base, unsigned int i) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     i * static_cast<unsigned int>(sizeof(T)));
+}
+
 template <typename T>
 __device__ inline bool inside(int c0, T t, int n) {
   const T fl = floor(t);
@@ -156,13 +165,15 @@ __device__ inline unsigned long long block_sum(unsigned int v, unsigned int* red
 // Deposit of one particle: nch values v at offset (xi, eta) from its
 // lattice cell origin (ci0 + fx0, cj0 + fy0) into the tile histogram, or
 // straight to the global planes (the shared ones for an owner flush) when
-// the stencil leaves the tile (counted in nglob).
+// the stencil leaves the tile (counted in nglob).  A particle that is not
+// live deposits zeros into the histogram and nothing outside it.
 template <typename T, int O, int nch>
 __device__ __forceinline__ void deposit_particle(const DepOut& dep, double* tile, const TileShape& ts,
                                                  int ox, int oy, int nx, int ny, bool tiled,
                                                  bool owner, int ci0,
                                                  int cj0, T fx0, T fy0, T xi, T eta,
-                                                 const double (&v)[4], unsigned int& nglob) {
+                                                 const double (&v)[4], unsigned int& nglob,
+                                                 bool live = true) {
   const int ntile = ts.nw * ts.nh;
   int bi, bj;
   const T dx = shape::locate<O>(ci0, fx0 + xi, nx, bi);
@@ -181,7 +192,7 @@ __device__ __forceinline__ void deposit_particle(const DepOut& dep, double* tile
 #pragma unroll
         for (int qa = 0; qa <= O; ++qa) lds_add(t + qb * ts.nw + qa, v[c] * (sx[qa] * sy[qb]));
     }
-  } else {
+  } else if (live) {
     if (tiled) ++nglob;
 #pragma unroll
     for (int qb = 0; qb <= O; ++qb) {
@@ -195,6 +206,153 @@ __device__ __forceinline__ void deposit_particle(const DepOut& dep, double* tile
 #pragma unroll
         for (int c = 0; c < nch; ++c) global_add((owner ? dep.sh[c] : dep.ch[c]) + o, v[c] * s);
       }
+    }
+  }
+}
+
+// Bx, By at displacement (xk, ek) from the lattice cell origin
+// (ci0 + fx0, cj0 + fy0), shape order O (indices clamped: always in bounds).
+template <typename T, int O>
+__device__ __forceinline__ void gather_bxby(const SliceFields<T>& f, int ci0, int cj0, T fx0, T fy0,
+                                            T xk, T ek, int nx, int ny, T& bx, T& by) {
+  if constexpr (O == 1) {
+    int ci, cj;
+    const T fx = shape::locate<1>(ci0, fx0 + xk, nx, ci);
+    const T fy = shape::locate<1>(cj0, fy0 + ek, ny, cj);
+    const T w00 = (T(1) - fx) * (T(1) - fy), w10 = fx * (T(1) - fy);
+    const T w01 = (T(1) - fx) * fy, w11 = fx * fy;
+    bx = gather(f.bx, ci, cj, w00, w10, w01, w11, nx, ny);
+    by = gather(f.by, ci, cj, w00, w10, w01, w11, nx, ny);
+  } else {
+    int bi, bj;
+    const T dx = shape::locate<O>(ci0, fx0 + xk, nx, bi);
+    const T dy = shape::locate<O>(cj0, fy0 + ek, ny, bj);
+    T wx[O + 1], wy[O + 1];
+    int ix[O + 1], iy[O + 1];
+    bool okx[O + 1], oky[O + 1];
+    shape::weights<O>(dx, wx);
+    shape::weights<O>(dy, wy);
+    shape::axis_nodes<O>(bi, nx, ix, okx);
+    shape::axis_nodes<O>(bj, ny, iy, oky);
+#pragma unroll
+    for (int q = 0; q <= O; ++q) {
+      wx[q] = okx[q] ? wx[q] : T(0);
+      wy[q] = oky[q] ? wy[q] : T(0);
+    }
+    bx = shape::interp<O>(f.bx, ix, iy, wx, wy, nx);
+    by = shape::interp<O>(f.by, ix, iy, wx, wy, nx);
+  }
+}
+
+// Trial push of a later predictor-corrector iteration for the particles of
+// the tile at lattice site (I0, J0).  Between iterations only Bx, By
+// change, and they enter the push as a kick -dz b0 (By, -Bx) on the
+// momentum: the new position, Psi and the rest of the momentum come from the
+// slice's first trial push (the record), and Bx, By are gathered at the
+// slice-k position as there.  A thread takes kLaterBatch particles at a
+// time (FP32 linear shape; one otherwise, whose registers two would crowd)
+// and issues all their loads, then all their gathers, before its first
+// deposit; a particle without deposit (record factor 0) adds zeros, so that
+// nothing waits on the factor.
+constexpr int kLaterBatch = 2;
+
+template <typename T, int O, int nch>
+__device__ __forceinline__ void trial_later_particles(const Lattice& L, const PushArgs<T>& a,
+                                                      double* tile, const TileShape& ts, int I0,
+                                                      int J0, int ox, int oy, int nx, int ny,
+                                                      bool tiled, bool owner, unsigned int& nglob) {
+  constexpr int U = sizeof(T) == 4 && O == 1 ? kLaterBatch : 1;
+  const size_t np = static_cast<size_t>(L.np);
+  const T* r = a.rec;
+  const T kick = static_cast<T>(a.dzeta) * T(kAB5[0]);
+  const int ntot = ts.tx * ts.ty;
+  for (int e0 = 0; e0 < ntot; e0 += U * kBlock) {
+    T fac[U], xk[U], ek[U], xn[U], en[U], cx[U], cy[U], bx[U], by[U];
+    int ci0[U], cj0[U];
+    T fx0[U], fy0[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kBlock + static_cast<int>(threadIdx.x);
+      const int ec = e < ntot ? e : 0;   // a missing particle reads the tile's first
+      const int I = I0 + ec % ts.tx, J = J0 + ec / ts.tx;
+      // 32-bit offsets from uniform plane bases (the launch checks that a
+      // particle plane is below 4 GiB)
+      const unsigned int p = static_cast<unsigned int>(J) * static_cast<unsigned int>(L.nX) +
+                             static_cast<unsigned int>(I);
+      fac[u] = load_at(r + 4 * np, p);
+      xk[u] = load_at(a.p.xi_x, p);
+      ek[u] = load_at(a.p.xi_y, p);
+      xn[u] = load_at(r, p);
+      en[u] = load_at(r + np, p);
+      cx[u] = load_at(r + 2 * np, p);
+      cy[u] = load_at(r + 3 * np, p);
+      ci0[u] = I >> ts.lpx;
+      cj0[u] = J >> ts.lpy;
+      fx0[u] = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
+      fy0[u] = (T(2 * (J & (L.ppc_y - 1)) + 1)) / T(2 * L.ppc_y);
+    }
+    // keep the scheduler from moving a later particle's loads behind an
+    // earlier one's gather (the wait for a load also waits for every load
+    // issued before it)
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (O == 1) {
+      // the gather of every particle of the batch: addresses and weights,
+      // then all loads, then the sums (the same sums as gather())
+      unsigned int off[U][4];
+      T wt[U][4];
+      bool ie[U], jn[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        int ci, cj;
+        const T fx = shape::locate<1>(ci0[u], fx0[u] + xk[u], nx, ci);
+        const T fy = shape::locate<1>(cj0[u], fy0[u] + ek[u], ny, cj);
+        wt[u][0] = (T(1) - fx) * (T(1) - fy);
+        wt[u][1] = fx * (T(1) - fy);
+        wt[u][2] = (T(1) - fx) * fy;
+        wt[u][3] = fx * fy;
+        ie[u] = ci + 1 < nx;
+        jn[u] = cj + 1 < ny;
+        const unsigned int r0 = static_cast<unsigned int>(cj * nx);
+        const unsigned int r1 = static_cast<unsigned int>((jn[u] ? cj + 1 : cj) * nx);
+        const unsigned int c0 = static_cast<unsigned int>(ci);
+        const unsigned int c1 = static_cast<unsigned int>(ie[u] ? ci + 1 : ci);
+        off[u][0] = r0 + c0;
+        off[u][1] = r0 + c1;
+        off[u][2] = r1 + c0;
+        off[u][3] = r1 + c1;
+      }
+      T gx[U][4], gy[U][4];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          gx[u][q] = load_at(a.f.bx, off[u][q]);
+          gy[u][q] = load_at(a.f.by, off[u][q]);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const bool e1 = ie[u], n1 = jn[u], en1 = ie[u] && jn[u];
+        bx[u] = wt[u][0] * gx[u][0] + wt[u][1] * (e1 ? gx[u][1] : T(0)) +
+                wt[u][2] * (n1 ? gx[u][2] : T(0)) + wt[u][3] * (en1 ? gx[u][3] : T(0));
+        by[u] = wt[u][0] * gy[u][0] + wt[u][1] * (e1 ? gy[u][1] : T(0)) +
+                wt[u][2] * (n1 ? gy[u][2] : T(0)) + wt[u][3] * (en1 ? gy[u][3] : T(0));
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        gather_bxby<T, O>(a.f, ci0[u], cj0[u], fx0[u], fy0[u], xk[u], ek[u], nx, ny, bx[u],
+                          by[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + u * kBlock + static_cast<int>(threadIdx.x) >= ntot) continue;
+      const bool live = fac[u] != T(0);   // selects, not branches
+      const double v[4] = {live ? static_cast<double>(fac[u] * (cx[u] - kick * by[u])) : 0.0,
+                           live ? static_cast<double>(fac[u] * (cy[u] + kick * bx[u])) : 0.0, 0.0,
+                           0.0};
+      deposit_particle<T, O, nch>(a.dep, tile, ts, ox, oy, nx, ny, tiled, owner, ci0[u], cj0[u],
+                                  fx0[u], fy0[u], xn[u], en[u], v, nglob, live);
     }
   }
 }
@@ -234,59 +392,11 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
   const int s1 = (a.k + 3) & 3, s2 = (a.k + 2) & 3, s3 = (a.k + 1) & 3, s4 = s_new;
   unsigned int nclamp = 0, nabs = 0, nglob = 0;
 
-  for (int e = threadIdx.x; e < ts.tx * ts.ty; e += kBlock) {
+  if constexpr (MODE == kTrialLater)
+    trial_later_particles<T, O, nch>(L, a, tile, ts, I0, J0, ox, oy, nx, ny, tiled, owner, nglob);
+  for (int e = threadIdx.x; MODE != kTrialLater && e < ts.tx * ts.ty; e += kBlock) {
     const int I = I0 + e % ts.tx, J = J0 + e / ts.tx;
     const size_t p = static_cast<size_t>(J) * L.nX + I;
-    if constexpr (MODE == kTrialLater) {
-      // Between predictor-corrector iterations only Bx, By change, and
-      // they enter the push as a kick -dz b0 (By, -Bx) on the momentum:
-      // the new position, Psi and the rest of the momentum come from the
-      // slice's first trial push; Bx, By are gathered at the slice-k
-      // position as there.
-      const T* r = a.rec;
-      const T fac = r[4 * np + p];
-      const T xk = a.p.xi_x[p], ek = a.p.xi_y[p];
-      const T xn = r[p], en = r[np + p];
-      const T cx = r[2 * np + p], cy = r[3 * np + p];
-      const int ci0 = I >> ts.lpx, cj0 = J >> ts.lpy;
-      const T fx0 = (T(2 * (I & (L.ppc_x - 1)) + 1)) / T(2 * L.ppc_x);
-      const T fy0 = (T(2 * (J & (L.ppc_y - 1)) + 1)) / T(2 * L.ppc_y);
-      if (fac == T(0)) continue;
-      T bx, by;
-      if constexpr (O == 1) {
-        int ci, cj;
-        const T fx = shape::locate<1>(ci0, fx0 + xk, nx, ci);
-        const T fy = shape::locate<1>(cj0, fy0 + ek, ny, cj);
-        const T w00 = (T(1) - fx) * (T(1) - fy), w10 = fx * (T(1) - fy);
-        const T w01 = (T(1) - fx) * fy, w11 = fx * fy;
-        bx = gather(a.f.bx, ci, cj, w00, w10, w01, w11, nx, ny);
-        by = gather(a.f.by, ci, cj, w00, w10, w01, w11, nx, ny);
-      } else {
-        int bi, bj;
-        const T dx = shape::locate<O>(ci0, fx0 + xk, nx, bi);
-        const T dy = shape::locate<O>(cj0, fy0 + ek, ny, bj);
-        T wx[O + 1], wy[O + 1];
-        int ix[O + 1], iy[O + 1];
-        bool okx[O + 1], oky[O + 1];
-        shape::weights<O>(dx, wx);
-        shape::weights<O>(dy, wy);
-        shape::axis_nodes<O>(bi, nx, ix, okx);
-        shape::axis_nodes<O>(bj, ny, iy, oky);
-#pragma unroll
-        for (int q = 0; q <= O; ++q) {
-          wx[q] = okx[q] ? wx[q] : T(0);
-          wy[q] = oky[q] ? wy[q] : T(0);
-        }
-        bx = shape::interp<O>(a.f.bx, ix, iy, wx, wy, nx);
-        by = shape::interp<O>(a.f.by, ix, iy, wx, wy, nx);
-      }
-      const T kick = dz * b0;
-      const double v[4] = {static_cast<double>(fac * (cx - kick * by)),
-                           static_cast<double>(fac * (cy + kick * bx)), 0.0, 0.0};
-      deposit_particle<T, O, nch>(a.dep, tile, ts, ox, oy, nx, ny, tiled, owner, ci0, cj0, fx0,
-                                  fy0, xn, en, v, nglob);
-      continue;
-    }
     // every load of the particle is issued before any decision on it
     const T w = a.p.w[p];
     T xi = a.p.xi_x[p], eta = a.p.xi_y[p];
@@ -460,7 +570,8 @@ __device__ __forceinline__ void push_tile(const Geom& g, const Lattice& L, const
     else
       flush_tile<nch>(a.dep.ch, tile, ts, ox, oy, nx, ny);
   }
-  // counters
+  // counters (none of them is kept for a trial push)
+  if constexpr (trial) return;
   const unsigned long long tc = block_sum(nclamp, red);
   const unsigned long long ta = block_sum(nabs, red);
   const unsigned long long tg = block_sum(nglob, red);
