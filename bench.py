@@ -45,11 +45,11 @@ PUSH_SOURCES = ["paper_2109_10277_amd/csrc/particles.hip",
                 "paper_2109_10277_amd/csrc/push_tile.hpp",
                 "paper_2109_10277_amd/csrc/shape.hpp"]
 PUSH_TRAFFIC = {
-    "c2": {"sha256_prefix": "815a7b97d2fb368d", "bytes": 69.51e6,
+    "c2": {"sha256_prefix": "bf4263e2f9e29491", "bytes": 69.53e6,
            "summary": "profiles/kernel_stats_c2_blowout_512x512x1024_fp32.md"},
-    "c5": {"sha256_prefix": "815a7b97d2fb368d", "bytes": 824.50e6,
+    "c5": {"sha256_prefix": "bf4263e2f9e29491", "bytes": 824.08e6,
            "summary": "profiles/kernel_stats_c5_forward_1024x1024_4ppc_fp32.md"},
-    "c3": {"sha256_prefix": "815a7b97d2fb368d", "bytes": 263.88e6,
+    "c3": {"sha256_prefix": "bf4263e2f9e29491", "bytes": 263.93e6,
            "summary": "profiles/hbm_traffic_c3_paper_step_1024x1024x1024_fp32.md"},
 }
 
