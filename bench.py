@@ -40,16 +40,18 @@ KCLASSES = ("push", "trial", "row_fwd", "col", "row_inv", "other")
 
 # HBM bytes per real-push launch from the FETCH_SIZE / WRITE_SIZE counter
 # runs (each scaled by what the counter reads for a plain 256 MiB copy),
-# valid while the push kernel's sources hash to the recorded value
+# valid while the push kernel's sources (and the runtime, which picks its
+# tiles) hash to the recorded value
 PUSH_SOURCES = ["paper_2109_10277_amd/csrc/particles.hip",
                 "paper_2109_10277_amd/csrc/push_tile.hpp",
-                "paper_2109_10277_amd/csrc/shape.hpp"]
+                "paper_2109_10277_amd/csrc/shape.hpp",
+                "paper_2109_10277_amd/csrc/runtime.cpp"]
 PUSH_TRAFFIC = {
-    "c2": {"sha256_prefix": "bf4263e2f9e29491", "bytes": 69.53e6,
+    "c2": {"sha256_prefix": "abe3ec251dc976f3", "bytes": 69.54e6,
            "summary": "profiles/kernel_stats_c2_blowout_512x512x1024_fp32.md"},
-    "c5": {"sha256_prefix": "bf4263e2f9e29491", "bytes": 824.08e6,
+    "c5": {"sha256_prefix": "abe3ec251dc976f3", "bytes": 824.48e6,
            "summary": "profiles/kernel_stats_c5_forward_1024x1024_4ppc_fp32.md"},
-    "c3": {"sha256_prefix": "bf4263e2f9e29491", "bytes": 263.93e6,
+    "c3": {"sha256_prefix": "abe3ec251dc976f3", "bytes": 260.88e6,
            "summary": "profiles/hbm_traffic_c3_paper_step_1024x1024x1024_fp32.md"},
 }
 

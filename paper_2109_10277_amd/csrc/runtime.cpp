@@ -212,6 +212,7 @@ class Box final : public BoxBase {
     shift_ = cfg.pc_shift >= 0 ? cfg.pc_shift : (explicit_ ? cfg.n0 : default_pc_shift(cfg.n0));
     tiled_ = cfg.deposit_mode == 0;
     tile_rows_ = default_tile_rows();
+    real_tile_rows_ = default_tile_rows(4096);
     tile_halo_ = default_tile_halo();
     if (const char* e = std::getenv("QSP_GRAPH")) graphs_ = std::atoi(e) != 0;   // 0: launch eagerly
     // QSP_PC_BUDGET: 0 switches the speculative P-C budgets off; -1 launches
@@ -1306,12 +1307,14 @@ class Box final : public BoxBase {
   }
 
   // Lattice rows per push workgroup (64 sites wide): as many rows as keep
-  // >= 2048 workgroups per launch, between 4 and 16 (at 1024^2 sites, 8 rows
-  // take the real push from 86 to 74 us against 16; at 512^2, 4).
-  int default_tile_rows() const {
+  // >= min_wgs workgroups per launch, between 4 and 16.  The trial pushes and
+  // the adjoint take 2048 (at 1024^2 sites 8 rows, 16 at 2048^2, 4 at 512^2),
+  // the real push 4096 (at 1024^2 sites 4 rows: 72 against 75 us with 8 and
+  // 86 with 16, while the trial pushes are faster with 8).
+  int default_tile_rows(int64_t min_wgs = 2048) const {
     const int tx = lat_.nX < 64 ? lat_.nX : 64;
     int r = 16;
-    while (r > 4 && r * tx > kBlock && lat_.np / (static_cast<int64_t>(tx) * r) < 2048) r >>= 1;
+    while (r > 4 && r * tx > kBlock && lat_.np / (static_cast<int64_t>(tx) * r) < min_wgs) r >>= 1;
     if (const char* e = std::getenv("QSP_TILE_ROWS")) {   // tuning override
       const int v = std::atoi(e);
       if (v >= 1 && v <= 16 && (v & (v - 1)) == 0 && v * tx >= kBlock) r = v;
@@ -1541,6 +1544,7 @@ class Box final : public BoxBase {
         zero_shared();
       });
       PushArgs<T> a = push_args(fields(b_[ik_][0], b_[ik_][1]), dc, k);
+      a.tile_rows = real_tile_rows_;
       timed(QSP_K_OTHER, [&] { launch_push<T>(geom_, lat_, a, kDepositOnly, ctr_, st_); });
       dep_valid_ = true;
     }
@@ -1679,6 +1683,7 @@ class Box final : public BoxBase {
     // slice); it also closes the predictor-corrector bookkeeping of slice k
     if (k + 1 < cfg_.nzeta) {
       PushArgs<T> a = push_args(fields(bxk, byk), dn, k);
+      a.tile_rows = real_tile_rows_;
       if (!explicit_) {   // the last corrector solve's convergence test
         a.pc_partial = partial_;
         a.pc_nblk = pc_partial_count(geom_);
@@ -1915,6 +1920,7 @@ class Box final : public BoxBase {
   bool dep_valid_ = false;
   bool tiled_ = true;
   int tile_rows_ = 16;
+  int real_tile_rows_ = 16;   // of the real push and the deposit-only pass
   int tile_halo_ = 2;
   bool nonfinite_ = false;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
