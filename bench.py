@@ -47,11 +47,11 @@ PUSH_SOURCES = ["paper_2109_10277_amd/csrc/particles.hip",
                 "paper_2109_10277_amd/csrc/shape.hpp",
                 "paper_2109_10277_amd/csrc/runtime.cpp"]
 PUSH_TRAFFIC = {
-    "c2": {"sha256_prefix": "abe3ec251dc976f3", "bytes": 69.54e6,
+    "c2": {"sha256_prefix": "6f740fbb09b747c8", "bytes": 69.54e6,
            "summary": "profiles/kernel_stats_c2_blowout_512x512x1024_fp32.md"},
-    "c5": {"sha256_prefix": "abe3ec251dc976f3", "bytes": 824.48e6,
+    "c5": {"sha256_prefix": "6f740fbb09b747c8", "bytes": 824.48e6,
            "summary": "profiles/kernel_stats_c5_forward_1024x1024_4ppc_fp32.md"},
-    "c3": {"sha256_prefix": "abe3ec251dc976f3", "bytes": 260.88e6,
+    "c3": {"sha256_prefix": "6f740fbb09b747c8", "bytes": 260.88e6,
            "summary": "profiles/hbm_traffic_c3_paper_step_1024x1024x1024_fp32.md"},
 }
 

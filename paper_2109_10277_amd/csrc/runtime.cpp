@@ -243,6 +243,15 @@ class Box final : public BoxBase {
   }
 
   void set_deposit_tiled(bool on) override {
+    if (on != tiled_ && trial_[0]) {
+      // with tiles the trial pushes store every node of the trial current
+      // planes and add into the shared ones, without tiles they add into
+      // the trial current planes: either way from zero
+      QSP_HIP(hipSetDevice(device_));
+      launch_zero(trial_[0], plane(), st_);
+      launch_zero(trial_[1], plane(), st_);
+      zero_shared();
+    }
     tiled_ = on;
     ++launch_version_;
   }
